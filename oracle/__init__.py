@@ -1,0 +1,267 @@
+"""ctypes front end of the FP64 CPU oracle (karl_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU-baseline
+leg of the benchmark, never by the product path.  It shares no code with the HIP
+library; it reads a workload description by attribute (duck typing) and packs it
+into the oracle's own C structs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_karl.so")
+SRC = os.path.join(HERE, "karl_oracle.c")
+
+MAX_PROC = 16
+NCOUNTERS = 48
+NLEDGER = 24
+NHIST = 4
+NREASON = 8
+
+# counter / ledger offsets (mirror of karl_oracle.h)
+C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 2, 4, 6, 8
+C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES = 10, 11, 12
+C_PROC, C_DEATH = 16, 32
+L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 17, 18, 19, 20
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with every operation rounded once (no contraction)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall",
+               "-shared", "-fPIC", "-o", LIB_PATH, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Species(C.Structure):
+    _fields_ = [("mass", C.c_double), ("charge", C.c_double), ("e_cut", C.c_double),
+                ("lifetime", C.c_double), ("cap", C.c_int64), ("tracked", C.c_int32),
+                ("pad", C.c_int32), ("xs_emin", C.c_double), ("xs_emax", C.c_double),
+                ("edges", C.POINTER(C.c_double))]
+
+
+class _Process(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
+                ("pad", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double))]
+
+
+class _Desc(C.Structure):
+    _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
+                ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
+                ("n_ion", C.POINTER(C.c_double)), ("t_gas", C.c_double), ("m_gas", C.c_double),
+                ("bz", C.c_double), ("sp", _Species * 2), ("n_proc", C.c_int32),
+                ("n_e", C.c_int32), ("proc", _Process * MAX_PROC), ("source", C.c_int32),
+                ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
+                ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
+                ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
+                ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
+                ("pad2", C.c_int32), ("planes", C.POINTER(C.c_int32)),
+                ("n_primaries", C.c_int64)]
+
+
+class _Tallies(C.Structure):
+    _fields_ = [("counters", C.POINTER(C.c_int64)), ("ledger", C.POINTER(C.c_double)),
+                ("density_time", C.POINTER(C.c_double)), ("recomb", C.POINTER(C.c_int64)),
+                ("jz", C.POINTER(C.c_int64)), ("jr", C.POINTER(C.c_int64)),
+                ("spectra", C.POINTER(C.c_int64)), ("digests", C.POINTER(C.c_uint64)),
+                ("hist", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.ko_run.argtypes = [C.POINTER(_Desc), C.c_int64, C.c_int64, C.POINTER(_Tallies)]
+        L.ko_run.restype = C.c_int
+        L.ko_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
+        L.ko_philox.restype = None
+        L.ko_u53.argtypes = [C.c_uint32, C.c_uint32]
+        L.ko_u53.restype = C.c_double
+        L.ko_constants.argtypes = [C.POINTER(C.c_double)]
+        L.ko_constants.restype = None
+        L.ko_mix64.argtypes = [C.c_uint64]
+        L.ko_mix64.restype = C.c_uint64
+        L.ko_beta_shape.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.ko_beta_shape.restype = C.c_double
+        L.ko_birth.argtypes = [C.POINTER(_Desc), C.c_int64, C.POINTER(C.c_double)]
+        L.ko_birth.restype = C.c_int
+        L.ko_debug_collide.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int64, C.c_uint64,
+                                       C.c_uint32, C.c_double, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]
+        L.ko_debug_collide.restype = C.c_int
+        L.ko_debug_helix.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_double, C.c_double,
+                                     C.POINTER(C.c_double)]
+        L.ko_debug_helix.restype = None
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Desc:
+    """Packs a workload into the oracle's descriptor; keeps the numpy buffers alive."""
+
+    def __init__(self, w):
+        self.w = w
+        self.keep = []
+        d = _Desc()
+        d.radius = w.radius
+        d.length = w.length
+        d.n_r = w.n_r
+        d.n_z = w.n_z
+        n_gas = np.ascontiguousarray(w.n_gas, dtype=np.float64)
+        self.keep.append(n_gas)
+        d.n_gas = _dptr(n_gas)
+        if w.n_ion is not None:
+            n_ion = np.ascontiguousarray(w.n_ion, dtype=np.float64)
+            self.keep.append(n_ion)
+            d.n_ion = _dptr(n_ion)
+        d.t_gas = w.t_gas
+        d.m_gas = w.m_gas
+        d.bz = w.bz
+        nb = len(w.species[0].edges) - 1
+        for s in range(2):
+            sp = w.species[s]
+            edges = np.ascontiguousarray(sp.edges, dtype=np.float64)
+            assert len(edges) == nb + 1, "both species need the same number of bins"
+            self.keep.append(edges)
+            d.sp[s].mass = sp.mass
+            d.sp[s].charge = sp.charge
+            d.sp[s].e_cut = sp.e_cut
+            d.sp[s].lifetime = sp.lifetime
+            d.sp[s].cap = int(sp.cap)
+            d.sp[s].tracked = 1 if sp.tracked else 0
+            d.sp[s].xs_emin = sp.xs_emin
+            d.sp[s].xs_emax = sp.xs_emax
+            d.sp[s].edges = _dptr(edges)
+        d.n_proc = len(w.processes)
+        d.n_e = w.n_e
+        for i, p in enumerate(w.processes):
+            xs = np.ascontiguousarray(p.xs, dtype=np.float64)
+            assert len(xs) == w.n_e
+            self.keep.append(xs)
+            d.proc[i].kind = p.kind
+            d.proc[i].species = p.species
+            d.proc[i].target = p.target
+            d.proc[i].e_th = p.e_th
+            d.proc[i].xs = _dptr(xs)
+        d.source = w.source
+        d.beam_species = w.beam_species
+        d.beta_e0 = w.beta_e0
+        d.beta_z = w.beta_z
+        d.beta_fmax = w.beta_fmax
+        d.beam_energy = w.beam_energy
+        for k in range(3):
+            d.beam_pos[k] = w.beam_pos[k]
+            d.beam_dir[k] = w.beam_dir[k]
+        d.seed = w.seed
+        d.n_bins = nb
+        planes = np.ascontiguousarray(w.planes, dtype=np.int32)
+        self.keep.append(planes)
+        d.n_planes = len(planes)
+        d.planes = planes.ctypes.data_as(C.POINTER(C.c_int32))
+        d.n_primaries = w.n_primaries
+        self.d = d
+
+
+def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.ndarray]:
+    nb = len(w.species[0].edges) - 1
+    t = {
+        "counters": np.zeros(NCOUNTERS, np.int64),
+        "ledger": np.zeros(NLEDGER, np.float64),
+        "density_time": np.zeros((2, w.n_r, w.n_z), np.float64),
+        "recomb": np.zeros((w.n_r, w.n_z), np.int64),
+        "jz": np.zeros((2, w.n_r, w.n_z + 1, 2), np.int64),
+        "jr": np.zeros((2, w.n_r + 1, w.n_z, 2), np.int64),
+        "spectra": np.zeros((2, len(w.planes), 2, nb + 2), np.int64),
+    }
+    if digests:
+        t["digests"] = np.zeros(w.n_primaries, np.uint64)
+    if hist:
+        t["hist"] = np.zeros((w.n_primaries, NHIST), np.float64)
+    return t
+
+
+def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, digests: bool = False,
+        hist: bool = False, tallies: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
+    """Transport primaries [pid_begin, pid_end) of workload `w`; returns (or adds into) tallies."""
+    if pid_end is None:
+        pid_end = w.n_primaries
+    t = tallies if tallies is not None else empty_tallies(w, digests, hist)
+    D = Desc(w)
+    T = _Tallies()
+    T.counters = t["counters"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.ledger = _dptr(t["ledger"])
+    T.density_time = _dptr(t["density_time"])
+    T.recomb = t["recomb"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.jz = t["jz"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.jr = t["jr"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.spectra = t["spectra"].ctypes.data_as(C.POINTER(C.c_int64))
+    if "digests" in t:
+        T.digests = t["digests"].ctypes.data_as(C.POINTER(C.c_uint64))
+    if "hist" in t:
+        T.hist = _dptr(t["hist"])
+    rc = lib().ko_run(C.byref(D.d), pid_begin, pid_end, C.byref(T))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the job (rc={rc})")
+    return t
+
+
+def philox(k0, k1, c0, c1, c2, c3):
+    out = (C.c_uint32 * 4)()
+    lib().ko_philox(k0, k1, c0, c1, c2, c3, out)
+    return list(out)
+
+
+def birth(w, pid: int) -> np.ndarray:
+    D = Desc(w)
+    out = np.zeros(8)
+    rc = lib().ko_birth(C.byref(D.d), pid, _dptr(out))
+    assert rc == 0
+    return out
+
+
+def collide(w, proc: int, pid: int, lineage: int, s: int, e: float, direction) -> np.ndarray:
+    D = Desc(w)
+    dr = np.ascontiguousarray(direction, dtype=np.float64)
+    out = np.zeros(16)
+    rc = lib().ko_debug_collide(C.byref(D.d), proc, pid, lineage, s, e, _dptr(dr), _dptr(out))
+    assert rc == 0
+    return out
+
+
+def helix(charge, mass, bz, pos, direction, speed, path) -> np.ndarray:
+    p = np.ascontiguousarray(pos, dtype=np.float64)
+    dr = np.ascontiguousarray(direction, dtype=np.float64)
+    out = np.zeros(6)
+    lib().ko_debug_helix(charge, mass, bz, _dptr(p), _dptr(dr), speed, path, _dptr(out))
+    return out
+
+
+def constants() -> np.ndarray:
+    out = np.zeros(6)
+    lib().ko_constants(_dptr(out))
+    return out
+
+
+def u53(a: int, b: int) -> float:
+    return lib().ko_u53(a, b)
+
+
+def beta_shape(e, e0=18600.0, z=2.0):
+    return lib().ko_beta_shape(e, e0, z)

@@ -1,0 +1,136 @@
+/*
+ * karl_oracle.h -- plain, slow, sequential FP64 CPU oracle of the particle-history
+ * transport of the KARL Monte Carlo method (arXiv 2503.10263).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or call
+ * this code: only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark use it.  It shares no code, header, table or constant with the HIP
+ * library; it is written from the paper and from the reading of it listed in the
+ * design notes (draw schedule, geometry, kinematics).
+ *
+ * All arrays are host memory owned by the caller.  Functions return 0 on success
+ * and a negative value on invalid input; they never abort.
+ */
+#ifndef KARL_ORACLE_H
+#define KARL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KO_MAX_PROC 16
+
+enum { KO_ELASTIC = 0, KO_EXCITATION = 1, KO_IONIZATION = 2, KO_RECOMBINATION = 3 };
+enum { KO_TARGET_GAS = 0, KO_TARGET_ION = 1 };
+enum { KO_SOURCE_BETA = 0, KO_SOURCE_BEAM = 1 };
+enum { KO_EXIT_LOW = 0, KO_EXIT_HIGH, KO_WALL, KO_CUTOFF, KO_RECOMBINED, KO_CAP,
+       KO_LIFETIME, KO_UNTRACKED, KO_NREASON };
+
+/* counters (int64) */
+#define KO_C_BIRTH         0   /* [2] particles born per species                  */
+#define KO_C_STEP          2   /* [2] flight segments per species                 */
+#define KO_C_COLL          4   /* [2] collisions per species                      */
+#define KO_C_ZCROSS        6   /* [2] z-face crossings per species                */
+#define KO_C_RCROSS        8   /* [2] r-face crossings per species (incl. wall)   */
+#define KO_C_TARGET_REDRAW 10  /* ionization target-velocity redraws              */
+#define KO_C_BEB_TRIES     11  /* secondary-energy proposals                      */
+#define KO_C_BETA_TRIES    12  /* beta-energy proposals                           */
+#define KO_C_PROC          16  /* [16] collisions per process                     */
+#define KO_C_DEATH         32  /* [2][8] deletions per species and reason         */
+#define KO_NCOUNTERS       48
+
+/* energy / time ledger (double) */
+#define KO_L_E_PRIMARY     0   /* birth energy of primaries (eV)                  */
+#define KO_L_E_DEATH       1   /* [2][8] energy at deletion per species/reason    */
+#define KO_L_E_EXC         17  /* excitation losses                               */
+#define KO_L_E_BIND        18  /* ionization binding energies                     */
+#define KO_L_E_GAS         19  /* energy given to the gas (elastic + ionization)  */
+#define KO_L_T_ALIVE       20  /* [2] summed particle lifetimes (s)               */
+#define KO_NLEDGER         24
+
+#define KO_NHIST           4   /* per history: E_in, E_accounted, n_born, n_dead  */
+
+typedef struct {
+    double mass;          /* kg */
+    double charge;        /* C, signed */
+    double e_cut;         /* eV: E < e_cut terminates */
+    double lifetime;      /* s */
+    int64_t cap;          /* maximum interactions */
+    int32_t tracked;      /* 0: counted at birth, never transported */
+    int32_t pad;
+    double xs_emin;       /* eV: first table node */
+    double xs_emax;       /* eV: last table node */
+    const double* edges;  /* [n_bins+1] spectrum bin edges (eV), increasing */
+} ko_species;
+
+typedef struct {
+    int32_t kind;         /* KO_ELASTIC ... */
+    int32_t species;      /* projectile slot: 0 electron, 1 ion */
+    int32_t target;       /* KO_TARGET_GAS or KO_TARGET_ION */
+    int32_t pad;
+    double e_th;          /* excitation energy or binding energy (eV); 0 otherwise */
+    const double* xs;     /* [n_e] cross section (m^2) at the species' nodes */
+} ko_process;
+
+typedef struct {
+    double radius, length;       /* m */
+    int32_t n_r, n_z;            /* grid (>= 1 each) */
+    const double* n_gas;         /* [n_z] gas density per z-cell (m^-3) */
+    const double* n_ion;         /* [n_r*n_z] ion target field (m^-3) or NULL */
+    double t_gas;                /* K */
+    double m_gas;                /* kg */
+    double bz;                   /* T; 0: straight lines */
+    ko_species sp[2];
+    int32_t n_proc, n_e;
+    ko_process proc[KO_MAX_PROC];
+    int32_t source, beam_species;
+    double beta_e0, beta_z, beta_fmax;
+    double beam_energy, beam_pos[3], beam_dir[3];
+    uint32_t seed;
+    int32_t n_bins;
+    int32_t n_planes, pad2;
+    const int32_t* planes;       /* [n_planes] z-face indices */
+    int64_t n_primaries;
+} ko_desc;
+
+typedef struct {
+    int64_t* counters;     /* [KO_NCOUNTERS] */
+    double* ledger;        /* [KO_NLEDGER] */
+    double* density_time;  /* [2][n_r][n_z] seconds */
+    int64_t* recomb;       /* [n_r][n_z] */
+    int64_t* jz;           /* [2][n_r][n_z+1][2] */
+    int64_t* jr;           /* [2][n_r+1][n_z][2] */
+    int64_t* spectra;      /* [2][n_planes][2][n_bins+2] */
+    uint64_t* digests;     /* [n_primaries] or NULL */
+    double* hist;          /* [n_primaries][KO_NHIST] or NULL */
+} ko_tallies;
+
+/* Transport primaries pid_begin..pid_end-1 and add their contributions to t. */
+int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t);
+
+/* ---- single-step entry points used by the oracle's own pin tests ---- */
+void ko_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+               uint32_t out[4]);
+double ko_u53(uint32_t a, uint32_t b);
+/* QE (J/eV), k_B, m_e c^2 (eV), alpha, pi, 2 pi as used by the oracle */
+void ko_constants(double out[6]);
+uint64_t ko_mix64(uint64_t z);
+double ko_beta_shape(double e, double e0, double z);
+/* birth state of primary pid: x,y,z,u,v,w,E,tries */
+int ko_birth(const ko_desc* d, int64_t pid, double out[8]);
+/* kinematics of process `proc` for one particle at the origin:
+   out[0]=E', out[1..3]=dir', out[4]=alive, out[5]=n_products,
+   out[6]=E_slow, out[7..9]=dir_slow, out[10]=E_ion, out[11..13]=dir_ion,
+   out[14]=energy to gas, out[15]=w (ionization) */
+int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, uint32_t s,
+                     double e, const double dir[3], double out[16]);
+/* helix: position and direction after path length `path` (guiding-centre formulas) */
+void ko_debug_helix(double charge, double mass, double bz, const double pos[3],
+                    const double dir[3], double speed, double path, double out[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,341 @@
+"""Seeded synthetic problem descriptions for the transport hot path.
+
+This module builds the *inputs* of a transport job -- geometry, gas density per
+z-cell, target fields, species constants, cross-section tables, spectrum bin
+edges and source parameters -- in SI units with energies in eV.  It holds none
+of the transport arithmetic (no free-path sampling, kinematics or tallying):
+both the HIP library and the oracle consume what it produces.
+
+The paper's own inputs (literature cross sections, the KATRIN gas profile, its
+parameter files) are not available, so every table is an analytic placeholder
+with the right structure (thresholds, 256 log-spaced nodes, magnitudes of the
+electron-H2 and H2+-H2 data shown in the paper's cross-section figures).
+Problem statement: geometry and gas profile (Sec. "Density fields",
+"Scalar field"), species and processes (Sec. "Interactions", "Species"),
+injector (Sec. "Injection"), tallies (Sec. "Density fields",
+"Current collection", "Calculation of fields").
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# physical constants (CODATA 2018; e and k_B exact by SI definition)
+# ----------------------------------------------------------------------------
+QE = 1.602176634e-19            # C, also J per eV
+KB = 1.380649e-23               # J/K
+M_E = 9.1093837015e-31          # kg
+AMU = 1.66053906660e-27         # kg
+EPS0 = 8.8541878128e-12         # F/m
+A0 = 5.29177210903e-11          # Bohr radius, m
+RYD_EV = 13.605693122994        # Rydberg energy, eV
+M_H2 = 2.01565006414 * AMU      # two 1H atoms (electron masses included)
+M_H2P = M_H2 - M_E              # H2+ ion
+
+# process kinds
+ELASTIC = 0
+EXCITATION = 1
+IONIZATION = 2
+RECOMBINATION = 3
+KIND_NAMES = {ELASTIC: "elastic", EXCITATION: "excitation",
+              IONIZATION: "ionization", RECOMBINATION: "recombination"}
+
+# target of a process: the background gas or the frozen ion-density field
+TARGET_GAS = 0
+TARGET_ION_FIELD = 1
+
+# primary source
+SOURCE_BETA = 0
+SOURCE_BEAM = 1
+
+# species slots
+ELECTRON = 0
+ION = 1
+
+# deletion reasons (deletion logger, Sec. "Termination")
+REASONS = ["exit_low", "exit_high", "wall", "cutoff", "recombined", "cap",
+           "lifetime", "untracked"]
+
+MAX_PROC = 16
+
+# Upper bound of the unnormalised allowed beta shape used by the rejection
+# sampler for E0 = 18600 eV, Z = 2.  The shape's maximum is 1.034917e19 (at
+# E = 2499.25 eV, printed by oracle/beta_fmax.py); 1 % headroom.
+BETA_E0 = 18600.0
+BETA_Z = 2.0
+BETA_FMAX = 1.0453e19
+
+
+@dataclass
+class Species:
+    """Per-species constants (Sec. "Species": ParticleType -> mass, charge)."""
+    name: str
+    mass: float                 # kg
+    charge: float               # C (signed)
+    tracked: bool = True        # False: counted at birth, never transported
+    e_cut: float = 0.0          # eV; E < e_cut terminates (strict)
+    cap: int = 1_000_000        # maximum number of interactions
+    lifetime: float = math.inf  # s
+    xs_emin: float = 1.0        # eV, first table node (energy for sigma)
+    xs_emax: float = 2.0e4      # eV, last table node
+    edges: np.ndarray = field(default_factory=lambda: np.arange(0.0, 2.0e4 + 1.0))
+
+
+@dataclass
+class Process:
+    """One interaction channel (Sec. "Interactions")."""
+    kind: int
+    species: int                # projectile species slot
+    target: int                 # TARGET_GAS or TARGET_ION_FIELD
+    e_th: float                 # eV: excitation energy / binding energy; 0 otherwise
+    xs: np.ndarray              # [n_e] cross section in m^2 at the species' nodes
+    name: str = ""
+
+
+@dataclass
+class Workload:
+    """Complete description of one transport job."""
+    name: str
+    radius: float               # m
+    length: float               # m
+    n_r: int
+    n_z: int
+    n_gas: np.ndarray           # [n_z] m^-3, cell-averaged
+    n_ion: Optional[np.ndarray] # [n_r*n_z] m^-3 or None
+    t_gas: float                # K
+    m_gas: float                # kg
+    bz: float                   # T; 0 selects straight-line transport
+    species: List[Species]
+    processes: List[Process]
+    n_e: int = 256              # table nodes
+    source: int = SOURCE_BETA
+    beta_e0: float = BETA_E0
+    beta_z: float = BETA_Z
+    beta_fmax: float = BETA_FMAX
+    beam_species: int = ELECTRON
+    beam_energy: float = 0.0
+    beam_pos: tuple = (0.0, 0.0, 0.0)
+    beam_dir: tuple = (0.0, 0.0, 1.0)
+    seed: int = 1
+    planes: List[int] = field(default_factory=list)   # z-face indices
+    n_primaries: int = 0
+
+    @property
+    def n_bins(self) -> int:
+        return len(self.species[0].edges) - 1
+
+    def describe(self) -> str:
+        return (f"{self.name}: R={self.radius} m L={self.length} m grid {self.n_r}x{self.n_z} "
+                f"B={self.bz} T procs={len(self.processes)} N={self.n_primaries} seed={self.seed}")
+
+
+# ----------------------------------------------------------------------------
+# table helpers
+# ----------------------------------------------------------------------------
+def log_nodes(emin: float, emax: float, n: int) -> np.ndarray:
+    """Energies of the n log-spaced table nodes (node k at emin*(emax/emin)^(k/(n-1)))."""
+    k = np.arange(n, dtype=np.float64)
+    return emin * np.exp(k * (math.log(emax / emin) / (n - 1)))
+
+
+def xs_elastic_e(e: np.ndarray) -> np.ndarray:
+    """Placeholder e-H2 elastic cross section (m^2): flat 1.5e-19 at low E, ~E^-1.3 above 20 eV."""
+    return 1.5e-19 / (1.0 + (e / 20.0) ** 1.3)
+
+
+def xs_beb(e: np.ndarray, b: float = 15.43, u: float = 15.98, n: float = 2.0) -> np.ndarray:
+    """Kim-Rudd binary-encounter-Bethe total ionization cross section (m^2), zero below B."""
+    e = np.asarray(e, dtype=np.float64)
+    t = e / b
+    uu = u / b
+    s = 4.0 * math.pi * A0 * A0 * n * (RYD_EV / b) ** 2
+    out = np.zeros_like(e)
+    ok = t >= 1.0
+    tt = t[ok]
+    lt = np.log(tt)
+    out[ok] = s / (tt + uu + 1.0) * (0.5 * lt * (1.0 - 1.0 / tt ** 2) + 1.0 - 1.0 / tt - lt / (tt + 1.0))
+    return out
+
+
+def xs_excitation(e: np.ndarray, ex: float, amp: float) -> np.ndarray:
+    """Placeholder excitation shape amp*(1-x)*ln(1/x+1)*x with x = ex/E, zero below ex."""
+    e = np.asarray(e, dtype=np.float64)
+    out = np.zeros_like(e)
+    ok = e > ex
+    x = ex / e[ok]
+    out[ok] = amp * (1.0 - x) * np.log(1.0 / x + 1.0) * x
+    return out
+
+
+def xs_recombination(e: np.ndarray) -> np.ndarray:
+    """Placeholder radiative recombination cross section 1e-21 m^2 * (1 eV / E)."""
+    return 1.0e-21 / np.asarray(e, dtype=np.float64)
+
+
+def xs_langevin(e_cm: np.ndarray, alpha_vol: float = 0.787e-30) -> np.ndarray:
+    """Langevin capture cross section pi*sqrt(2 a' e^2/(4 pi eps0 E_cm)) (m^2), E_cm in eV."""
+    e2 = QE * QE / (4.0 * math.pi * EPS0)
+    return math.pi * np.sqrt(2.0 * alpha_vol * e2 / (np.asarray(e_cm) * QE))
+
+
+def cell_average(knots_z, knots_v, length: float, n_z: int) -> np.ndarray:
+    """Exact cell averages of a piecewise-linear profile over n_z equal cells."""
+    kz = np.asarray(knots_z, dtype=np.float64)
+    kv = np.asarray(knots_v, dtype=np.float64)
+    out = np.empty(n_z)
+    dz = length / n_z
+    for k in range(n_z):
+        a, b = k * dz, (k + 1) * dz
+        pts = np.concatenate(([a], kz[(kz > a) & (kz < b)], [b]))
+        vals = np.interp(pts, kz, kv)
+        out[k] = np.sum(0.5 * (vals[1:] + vals[:-1]) * np.diff(pts)) / (b - a)
+    return out
+
+
+def electron(e_cut=1.0, cap=1_000_000, edges=None, emin=1.0, emax=2.0e4) -> Species:
+    return Species("e-", M_E, -QE, True, e_cut, cap, math.inf, emin, emax,
+                   np.arange(0.0, 2.0e4 + 1.0) if edges is None else np.asarray(edges, np.float64))
+
+
+def h2_ion(tracked: bool, cap=1_000_000, edges=None, emin=1.0e-4, emax=1.0e2, n_bins=20000) -> Species:
+    if edges is None:
+        edges = np.linspace(0.0, 100.0, n_bins + 1)
+    return Species("H2+", M_H2P, QE, tracked, 0.0, cap, math.inf, emin, emax, np.asarray(edges, np.float64))
+
+
+def _cfg1_processes(n_e: int) -> List[Process]:
+    en = log_nodes(1.0, 2.0e4, n_e)
+    return [
+        Process(ELASTIC, ELECTRON, TARGET_GAS, 0.0, xs_elastic_e(en), "e elastic"),
+        Process(IONIZATION, ELECTRON, TARGET_GAS, 15.43, xs_beb(en), "e ionization (BEB)"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 12.6, xs_excitation(en, 12.6, 1.5e-20), "e exc 12.6"),
+    ]
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+# ----------------------------------------------------------------------------
+def cfg_tiny(n_primaries: int = 10_000, seed: int = 1, bz: float = 0.0,
+             column_cm2: float = 1.0e16, n_r: int = 1, n_z: int = 1) -> Workload:
+    """Tiny plain FP64 case: 1 m tube of radius 45 mm, uniform H2 with the given column
+    density, straight-line transport, elastic + BEB ionization + one 12.6 eV excitation,
+    1 eV exit spectra at both ends; ions counted, not tracked."""
+    n_e = 256
+    length = 1.0
+    n = column_cm2 * 1.0e4 / length
+    return Workload(
+        name="tiny", radius=0.045, length=length, n_r=n_r, n_z=n_z,
+        n_gas=np.full(n_z, n), n_ion=None, t_gas=80.0, m_gas=M_H2, bz=bz,
+        species=[electron(), h2_ion(tracked=False)], processes=_cfg1_processes(n_e),
+        n_e=n_e, source=SOURCE_BETA, seed=seed, planes=[0, n_z], n_primaries=n_primaries)
+
+
+def cfg_full(n_primaries: int = 1_000_000, seed: int = 1) -> Workload:
+    """Full plain FP64 case: 10 m cylinder of radius 45 mm, axial profile flat over the
+    central 8 m with linear falloff to 5 % at the ends (column 5e17 cm^-2), uniform 2.5 T
+    axial field (guiding-centre transport), 8 electron processes including recombination on
+    a frozen ion-density field, tracked H2+ with Langevin elastic scattering, 64x512 (r,z)
+    grids and 2048-bin spectra per species at z = 0, 5, 10 m."""
+    n_e = 256
+    length, n_z, n_r = 10.0, 512, 64
+    column = 5.0e17 * 1.0e4
+    shape = cell_average([0.0, 1.0, 9.0, 10.0], [0.05, 1.0, 1.0, 0.05], length, n_z)
+    n0 = column / (9.05)            # integral of the shape over 10 m is 9.05 m
+    n_gas = n0 * shape
+    n_ion = np.repeat((1.0e15 * shape)[None, :], n_r, axis=0).reshape(-1)
+    en = log_nodes(1.0, 2.0e4, n_e)
+    ei = log_nodes(1.0e-4, 1.0e2, n_e)
+    procs = [
+        Process(ELASTIC, ELECTRON, TARGET_GAS, 0.0, xs_elastic_e(en), "e elastic"),
+        Process(IONIZATION, ELECTRON, TARGET_GAS, 15.43, xs_beb(en), "e ionization (BEB)"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 8.9, xs_excitation(en, 8.9, 1.5e-20), "e exc 8.9"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 11.37, xs_excitation(en, 11.37, 1.5e-20), "e exc 11.37"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 12.6, xs_excitation(en, 12.6, 1.5e-20), "e exc 12.6"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 0.516, xs_excitation(en, 0.516, 3.0e-21), "e vib 0.516"),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 0.044, xs_excitation(en, 0.044, 5.0e-21), "e rot 0.044"),
+        Process(RECOMBINATION, ELECTRON, TARGET_ION_FIELD, 0.0, xs_recombination(en), "e recombination"),
+        Process(ELASTIC, ION, TARGET_GAS, 0.0, xs_langevin(ei), "H2+ Langevin elastic"),
+    ]
+    e_edges = 1.0 * (2.0e4 / 1.0) ** (np.arange(2049) / 2048.0)
+    i_edges = 1.0e-4 * (1.0e2 / 1.0e-4) ** (np.arange(2049) / 2048.0)
+    return Workload(
+        name="full", radius=0.045, length=length, n_r=n_r, n_z=n_z, n_gas=n_gas, n_ion=n_ion,
+        t_gas=80.0, m_gas=M_H2, bz=2.5,
+        species=[electron(edges=e_edges), h2_ion(tracked=True, edges=i_edges)],
+        processes=procs, n_e=n_e, source=SOURCE_BETA, seed=seed,
+        planes=[0, 256, 512], n_primaries=n_primaries)
+
+
+def cfg_batched(n_jobs: int = 256, rng_seed: int = 20250313, scale: float = 1.0) -> List[Workload]:
+    """Batched case: n_jobs jobs with tiny-case physics in guiding-centre mode; primaries
+    log-uniform in 1e3-1e6 (times `scale`), column log-uniform in 1e16-1e18 cm^-2 over 1 m,
+    B uniform in 1-3.6 T, Philox seed 1000+j."""
+    rng = np.random.default_rng(rng_seed)
+    jobs = []
+    for j in range(n_jobs):
+        n_prim = int(round(10.0 ** rng.uniform(3.0, 6.0) * scale))
+        column = 10.0 ** rng.uniform(16.0, 18.0)
+        b = float(rng.uniform(1.0, 3.6))
+        w = cfg_tiny(n_primaries=max(n_prim, 1), seed=1000 + j, bz=b, column_cm2=column)
+        w.name = f"batched[{j}]"
+        jobs.append(w)
+    return jobs
+
+
+def cfg_mixed(n_primaries: int = 100_000_000, seed: int = 1) -> Workload:
+    """Mixed-precision case: tiny-case geometry and physics at 1e8 primaries."""
+    w = cfg_tiny(n_primaries=n_primaries, seed=seed)
+    w.name = "mixed"
+    return w
+
+
+def serving_requests(n: int = 600, rate: float = 20.0, rng_seed: int = 20250313,
+                     scale: float = 1.0):
+    """Serving case: Poisson arrivals at `rate` jobs/s; each job a tiny-case variant in
+    guiding-centre mode with column 1e16-1e18 cm^-2, B 1-3.6 T, primaries log-uniform
+    1e4-1e7 (times `scale`), grid 32x256, 48x384 or 64x512.  Returns (arrival_s, Workload)."""
+    rng = np.random.default_rng(rng_seed)
+    t = 0.0
+    out = []
+    grids = [(32, 256), (48, 384), (64, 512)]
+    for j in range(n):
+        t += rng.exponential(1.0 / rate)
+        column = 10.0 ** rng.uniform(16.0, 18.0)
+        b = float(rng.uniform(1.0, 3.6))
+        n_prim = int(round(10.0 ** rng.uniform(4.0, 7.0) * scale))
+        n_r, n_z = grids[int(rng.integers(0, 3))]
+        w = cfg_tiny(n_primaries=max(n_prim, 1), seed=5000 + j, bz=b, column_cm2=column,
+                     n_r=n_r, n_z=n_z)
+        w.name = f"serve[{j}]"
+        out.append((t, w))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# small test problems (beams, single processes)
+# ----------------------------------------------------------------------------
+def beam_problem(energy: float, processes: List[Process], n_gas: np.ndarray, length: float,
+                 radius: float = 1.0, n_r: int = 1, bz: float = 0.0, t_gas: float = 0.0,
+                 n_primaries: int = 10_000, seed: int = 7, species: Optional[List[Species]] = None,
+                 planes: Optional[List[int]] = None, n_ion: Optional[np.ndarray] = None,
+                 beam_pos=(0.0, 0.0, 0.0), beam_dir=(0.0, 0.0, 1.0), beam_species: int = ELECTRON,
+                 n_e: int = 256) -> Workload:
+    """A directed mono-energetic beam (Sec. "Injection": directed streams for tests)."""
+    n_z = len(n_gas)
+    if species is None:
+        species = [electron(), h2_ion(tracked=False)]
+    return Workload(
+        name="beam", radius=radius, length=length, n_r=n_r, n_z=n_z,
+        n_gas=np.asarray(n_gas, np.float64), n_ion=n_ion, t_gas=t_gas, m_gas=M_H2, bz=bz,
+        species=species, processes=processes, n_e=n_e, source=SOURCE_BEAM,
+        beam_species=beam_species, beam_energy=energy, beam_pos=tuple(beam_pos),
+        beam_dir=tuple(beam_dir), seed=seed, planes=[0, n_z] if planes is None else planes,
+        n_primaries=n_primaries)
+
+
+def with_primaries(w: Workload, n: int) -> Workload:
+    return replace(w, n_primaries=n)
