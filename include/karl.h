@@ -1,0 +1,190 @@
+/*
+ * karl.h -- C ABI of libkarl, the MI355X (gfx950) implementation of the particle-history
+ * transport of the KARL Monte Carlo method (Sendlinger, Kellerer, Spanier, arXiv 2503.10263).
+ *
+ * A job is the paper's problem statement: a cylindrical gas column (Sec. 2.2, "Scalar
+ * field"), a uniform axial magnetic field or none (Sec. 3.1), the tracked species and their
+ * interactions with cross sections given as 1-D functions (Sec. 3.3), an injector (Sec. 3.5)
+ * and the diagnostics -- density fields, current collectors, deletion logger (Sec. 2.2, 2.3,
+ * 3.2, 3.4).  karl_transport() runs the main simulation cycle of Sec. 2.1 for a range of
+ * primary events on the GPU: every history is followed through free flights with
+ * d = -lambda ln(eta) (eqs. 1-2), segment stops, interactions and secondaries until all its
+ * particles terminate.
+ *
+ * Conventions
+ *   - SI units, energies in eV.  All pointers in karl_job_desc are HOST memory owned by the
+ *     caller and deep-copied by karl_create_job (the caller may free them on return), except
+ *     `workspace`, which is DEVICE memory owned by the caller; it must stay allocated until
+ *     karl_destroy_job and must not be used by anything else meanwhile.
+ *   - Every entry point returns a karl_status; nothing throws across the ABI.  On failure
+ *     karl_last_error() returns a message for the calling thread.
+ *   - Results depend only on (descriptor, set of primary ids): random numbers are
+ *     Philox4x32-10 keyed by (seed, primary id) and counted by (step, slot, lineage), so
+ *     launch partitioning, chunking, batching and queue sizes do not change any integer
+ *     tally; floating-point tallies differ only in the order of their additions.
+ */
+#ifndef KARL_H
+#define KARL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t karl_status;
+#define KARL_OK         0
+#define KARL_EINVAL    (-1)  /* invalid descriptor, argument or buffer size          */
+#define KARL_ENOMEM    (-2)  /* workspace smaller than karl_workspace_bytes()        */
+#define KARL_EDEVICE   (-3)  /* a HIP call failed                                     */
+#define KARL_EOVERFLOW (-4)  /* a single primary's secondaries exceed the queue       */
+#define KARL_ESTATE    (-5)  /* call on a destroyed or failed job                     */
+#define KARL_ENUMERIC  (-6)  /* NaN/Inf met in the particle state                     */
+
+#define KARL_MAX_PROC 16
+
+enum { KARL_ELASTIC = 0, KARL_EXCITATION = 1, KARL_IONIZATION = 2, KARL_RECOMBINATION = 3 };
+enum { KARL_TARGET_GAS = 0, KARL_TARGET_ION_FIELD = 1 };
+enum { KARL_SOURCE_BETA = 0, KARL_SOURCE_BEAM = 1 };
+enum { KARL_FP64 = 0, KARL_FP32 = 1 };
+
+/* job flags */
+#define KARL_FLAG_DIGESTS 1u   /* per-primary 64-bit digest of the event sequence          */
+#define KARL_FLAG_HISTORY 2u   /* per-primary ledger: E_in, E_accounted, n_born, n_deleted  */
+
+/* deletion reasons (Sec. 3.2, deletion logger) */
+enum { KARL_EXIT_LOW = 0, KARL_EXIT_HIGH, KARL_WALL, KARL_CUTOFF, KARL_RECOMBINED, KARL_CAP,
+       KARL_LIFETIME, KARL_UNTRACKED, KARL_NREASON };
+
+/* layout of the counters array (int64) */
+#define KARL_C_BIRTH          0  /* [2] particles born per species                      */
+#define KARL_C_STEP           2  /* [2] flight segments per species                     */
+#define KARL_C_COLL           4  /* [2] interactions per species                        */
+#define KARL_C_ZCROSS         6  /* [2] z-face crossings per species                    */
+#define KARL_C_RCROSS         8  /* [2] r-face crossings per species (wall included)    */
+#define KARL_C_TARGET_REDRAW 10  /* ionization target-velocity redraws                  */
+#define KARL_C_BEB_TRIES     11  /* secondary-energy proposals                          */
+#define KARL_C_BETA_TRIES    12  /* beta-energy proposals                               */
+#define KARL_C_PROC          16  /* [16] interactions per process                       */
+#define KARL_C_DEATH         32  /* [2][8] deletions per species and reason             */
+#define KARL_NCOUNTERS       48
+
+/* layout of the ledger array (double) */
+#define KARL_L_E_PRIMARY      0  /* summed birth energy of primaries (eV)               */
+#define KARL_L_E_DEATH        1  /* [2][8] energy at deletion per species and reason    */
+#define KARL_L_E_EXC         17  /* excitation energy losses                            */
+#define KARL_L_E_BIND        18  /* ionization binding energies                         */
+#define KARL_L_E_GAS         19  /* energy handed to the gas (elastic, ionization frame) */
+#define KARL_L_T_ALIVE       20  /* [2] summed particle lifetimes (s)                   */
+#define KARL_NLEDGER         24
+
+#define KARL_NHIST            4  /* per-primary ledger entries                          */
+
+typedef struct {
+    double mass;            /* kg */
+    double charge;          /* C, signed; sets the gyration sense */
+    double e_cut;           /* eV; a particle with E < e_cut is deleted (strict) */
+    double lifetime;        /* s; deletion once the summed flight time reaches it (INFINITY: none) */
+    int64_t cap;            /* maximum number of interactions (Sec. 3.2) */
+    int32_t tracked;        /* 0: counted at birth and deleted, never transported */
+    int32_t reserved0;
+    double xs_emin;         /* eV; energy of the first cross-section node */
+    double xs_emax;         /* eV; energy of the last node; nodes are log-spaced */
+    const double* edges;    /* [n_bins+1] increasing spectrum bin edges (eV) */
+} karl_species_desc;
+
+typedef struct {
+    int32_t kind;           /* KARL_ELASTIC ... KARL_RECOMBINATION */
+    int32_t species;        /* projectile: 0 electron slot, 1 ion slot */
+    int32_t target;         /* KARL_TARGET_GAS or KARL_TARGET_ION_FIELD */
+    int32_t reserved0;
+    double e_th;            /* eV: excitation energy or ionization binding energy; 0 else */
+    const double* xs;       /* [n_e] cross section (m^2) at the projectile species' nodes */
+} karl_process_desc;
+
+typedef struct {
+    double radius, length;        /* cylinder r <= radius, 0 <= z <= length (m) */
+    int32_t n_r, n_z;             /* segments of the density/current grid (>= 1) */
+    const double* n_gas;          /* [n_z] gas density per z-segment (m^-3) */
+    const double* n_ion;          /* [n_r*n_z] ion-density target field (m^-3) or NULL */
+    double t_gas;                 /* gas temperature (K); 0: target at rest */
+    double m_gas;                 /* gas molecule mass (kg) */
+    double bz;                    /* axial field (T); 0 selects straight-line transport */
+    karl_species_desc species[2]; /* slot 0 electrons, slot 1 ions */
+    int32_t n_proc;               /* <= KARL_MAX_PROC */
+    int32_t n_e;                  /* cross-section nodes per table, 2..1024 */
+    karl_process_desc proc[KARL_MAX_PROC];
+    int32_t source;               /* KARL_SOURCE_BETA or KARL_SOURCE_BEAM */
+    int32_t beam_species;
+    double beta_e0, beta_z, beta_fmax;  /* endpoint (eV), daughter charge, shape bound */
+    double beam_energy, beam_pos[3], beam_dir[3];
+    uint32_t seed;
+    int32_t n_bins;               /* spectrum bins per species (edges hold n_bins+1) */
+    int32_t n_planes;             /* spectrum planes, each a z-face index 0..n_z */
+    int32_t reserved0;
+    const int32_t* planes;
+    int64_t n_primaries;          /* primary ids are 0 .. n_primaries-1 */
+    int32_t precision;            /* KARL_FP64 or KARL_FP32 transport state */
+    uint32_t flags;               /* KARL_FLAG_* */
+    int64_t queue_capacity;       /* secondary-queue entries per buffer; 0: 1<<22 */
+    int64_t chunk;                /* initial primaries per launch; 0: 65536 */
+    void* workspace;              /* device memory, >= karl_workspace_bytes() */
+    uint64_t workspace_bytes;
+} karl_job_desc;
+
+/* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements:
+   counters KARL_NCOUNTERS; ledger KARL_NLEDGER; density_time 2*n_r*n_z;
+   recomb n_r*n_z; jz 2*n_r*(n_z+1)*2; jr 2*(n_r+1)*n_z*2; spectra 2*n_planes*2*(n_bins+2);
+   digests n_primaries (needs KARL_FLAG_DIGESTS); hist n_primaries*KARL_NHIST
+   (needs KARL_FLAG_HISTORY).  Index order is row-major in the order written. */
+typedef struct {
+    int64_t* counters;
+    double* ledger;
+    double* density_time;   /* [species][r][z] seconds spent per segment (eq. 3 numerator) */
+    int64_t* recomb;        /* [r][z] recombinations N_gamma (eq. 3) */
+    int64_t* jz;            /* [species][r][z-face][dir] crossings, dir 1 = +z (Sec. 2.3) */
+    int64_t* jr;            /* [species][r-face][z][dir] crossings, dir 1 = outward */
+    int64_t* spectra;       /* [species][plane][dir][bin] with under/overflow bins 0, n_bins+1 */
+    uint64_t* digests;
+    double* hist;
+} karl_tallies;
+
+/* Device bytes a job needs (tables, tallies and their snapshot, two secondary queues). */
+karl_status karl_workspace_bytes(const karl_job_desc* desc, uint64_t* bytes);
+
+/* Validate, deep-copy and upload a job; tallies start at zero.  The device is the current
+   HIP device of the calling thread.  On success *out owns host resources until
+   karl_destroy_job. */
+karl_status karl_create_job(const karl_job_desc* desc, void** out);
+
+/* Transport primaries pid_begin .. pid_end-1 (0 <= begin <= end <= n_primaries) and add
+   their contributions to the job's tallies.  Work is enqueued on `hip_stream` (NULL: the
+   null stream); the call returns after the last launch has completed, because the number of
+   secondary generations is only known on the device.  Disjoint ranges accumulate;
+   overlapping ranges count twice. */
+karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* hip_stream);
+
+/* Copy the tallies into caller-owned host buffers (synchronizes `hip_stream`). Returns the
+   job's sticky device status (KARL_EOVERFLOW, KARL_ENUMERIC) if one was raised. */
+karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream);
+
+/* Zero the tallies. */
+karl_status karl_reset_tallies(void* job, void* hip_stream);
+
+/* Timing of the transport kernels since creation or the last reset, measured with HIP
+   events on the launch stream: *kernel_ms total, *n_launches launches, *generations
+   secondary generations processed, *max_queue the largest generation. */
+karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches,
+                           int64_t* generations, int64_t* max_queue);
+
+/* Release host resources of the job (the caller still owns the workspace). */
+karl_status karl_destroy_job(void* job);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* karl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KARL_H */

@@ -91,6 +91,10 @@ def lib():
         L.ko_u53.restype = C.c_double
         L.ko_constants.argtypes = [C.POINTER(C.c_double)]
         L.ko_constants.restype = None
+        L.ko_log.argtypes = [C.c_double]
+        L.ko_log.restype = C.c_double
+        L.ko_sincos.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ko_sincos.restype = None
         L.ko_mix64.argtypes = [C.c_uint64]
         L.ko_mix64.restype = C.c_uint64
         L.ko_beta_shape.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -257,6 +261,16 @@ def constants() -> np.ndarray:
     out = np.zeros(6)
     lib().ko_constants(_dptr(out))
     return out
+
+
+def log(x: float) -> float:
+    return lib().ko_log(x)
+
+
+def sincos(x: float):
+    s, c = C.c_double(), C.c_double()
+    lib().ko_sincos(x, C.byref(s), C.byref(c))
+    return s.value, c.value
 
 
 def u53(a: int, b: int) -> float:

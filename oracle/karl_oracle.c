@@ -87,6 +87,104 @@ uint64_t ko_mix64(uint64_t z) {
     return z;
 }
 
+
+/* ------------------------------------------------------------------ */
+/* elementary functions written out with IEEE basic operations only, so */
+/* that an independent implementation of the same steps reproduces them */
+/* bit for bit (the guiding-centre phase amplifies any 1-ulp difference) */
+/* ------------------------------------------------------------------ */
+#define SQRT_HALF 0.70710678118654757
+#define LN2_HI 0.6931471805601177        /* ln 2 rounded to 40 bits: e*LN2_HI is exact */
+#define LN2_LO (-1.7239444525614835e-13) /* ln 2 - LN2_HI */
+#define PIO4 0.78539816339744828
+#define TWO_OVER_PI 0.6366197723675814
+#define PIO2_1 1.5707963407039642        /* pi/2 in four 26-bit pieces */
+#define PIO2_2 (-1.3909067675399456e-08)
+#define PIO2_3 6.123233932053594e-17
+#define PIO2_4 6.368317178484799e-25
+
+/* ln x: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m-1)/(m+1),
+   atanh(s)/s = sum z^n/(2n+1), z = s^2 <= 0.0295, summed to n = 12 (truncation < 2^-62) */
+double ko_log(double x) {
+    if (!(x > 0.0)) return (x == 0.0) ? -INFINITY : NAN;
+    if (isinf(x)) return x;
+    int e;
+    double m = frexp(x, &e);
+    if (m < SQRT_HALF) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double f = m - 1.0;
+    double s = f / (m + 1.0);
+    double z = s * s;
+    double p = 0.04;                      /* 1/25 */
+    p = 0.043478260869565216 + z * p;     /* 1/23 */
+    p = 0.047619047619047616 + z * p;     /* 1/21 */
+    p = 0.05263157894736842 + z * p;      /* 1/19 */
+    p = 0.058823529411764705 + z * p;     /* 1/17 */
+    p = 0.06666666666666667 + z * p;      /* 1/15 */
+    p = 0.07692307692307693 + z * p;      /* 1/13 */
+    p = 0.09090909090909091 + z * p;      /* 1/11 */
+    p = 0.1111111111111111 + z * p;       /* 1/9  */
+    p = 0.14285714285714285 + z * p;      /* 1/7  */
+    p = 0.2 + z * p;                      /* 1/5  */
+    p = 0.3333333333333333 + z * p;       /* 1/3  */
+    double t = 2.0 * s;
+    double lm = t + t * (z * p);
+    double de = (double)e;
+    return de * LN2_HI + (de * LN2_LO + lm);
+}
+
+/* sin and cos: r = x - k pi/2 (Cody-Waite with four 26-bit pieces of pi/2, exact products
+   for |k| < 2^27), Taylor series on |r| <= pi/4 to r^19 and r^20, quadrant from k mod 4 */
+void ko_sincos(double x, double* sn, double* cs) {
+    if (!isfinite(x)) {
+        *sn = NAN;
+        *cs = NAN;
+        return;
+    }
+    double r = x;
+    long long q = 0;
+    if (fabs(x) > PIO4) {
+        double xx = x;
+        if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / TWO_PI) * TWO_PI;
+        double k = floor(xx * TWO_OVER_PI + 0.5);
+        r = xx - k * PIO2_1;
+        r = r - k * PIO2_2;
+        r = r - k * PIO2_3;
+        r = r - k * PIO2_4;
+        q = (long long)k;
+    }
+    double z = r * r;
+    double ps = -8.22063524662433e-18;    /* -1/19! */
+    ps = 2.8114572543455206e-15 + z * ps; /*  1/17! */
+    ps = -7.647163731819816e-13 + z * ps; /* -1/15! */
+    ps = 1.6059043836821613e-10 + z * ps; /*  1/13! */
+    ps = -2.505210838544172e-08 + z * ps; /* -1/11! */
+    ps = 2.7557319223985893e-06 + z * ps; /*  1/9!  */
+    ps = -0.0001984126984126984 + z * ps; /* -1/7!  */
+    ps = 0.008333333333333333 + z * ps;   /*  1/5!  */
+    ps = -0.16666666666666666 + z * ps;   /* -1/3!  */
+    double sv = r + r * (z * ps);
+    double pc = 4.110317623312165e-19;    /*  1/20! */
+    pc = -1.5619206968586225e-16 + z * pc; /* -1/18! */
+    pc = 4.779477332387385e-14 + z * pc;  /*  1/16! */
+    pc = -1.1470745597729725e-11 + z * pc; /* -1/14! */
+    pc = 2.08767569878681e-09 + z * pc;   /*  1/12! */
+    pc = -2.755731922398589e-07 + z * pc; /* -1/10! */
+    pc = 2.48015873015873e-05 + z * pc;   /*  1/8!  */
+    pc = -0.001388888888888889 + z * pc;  /* -1/6!  */
+    pc = 0.041666666666666664 + z * pc;   /*  1/4!  */
+    double cv = (1.0 - 0.5 * z) + (z * z) * pc;
+    switch (q & 3) {
+        case 0: *sn = sv; *cs = cv; break;
+        case 1: *sn = cv; *cs = -sv; break;
+        case 2: *sn = -sv; *cs = -cv; break;
+        default: *sn = -cv; *cs = sv; break;
+    }
+}
+
+
 typedef struct { double d0, d1; } pair_t;
 
 /* one slot of the draw schedule: key (seed, pid), counter (step, slot, lineage) */
@@ -253,7 +351,7 @@ static double xs_lookup(const ctx_t* c, int i, double exs) {
     const ko_process* pr = &d->proc[i];
     if (exs < pr->e_th) return 0.0;
     int s = pr->species;
-    double x = log(exs / d->sp[s].xs_emin) * c->inv_dlog[s];
+    double x = ko_log(exs / d->sp[s].xs_emin) * c->inv_dlog[s];
     int k;
     double f;
     if (!(x > 0.0)) {
@@ -353,7 +451,8 @@ static int gc_set(ctx_t* c, part_t* p, double xp, double yp, int at_birth) {
 /* ------------------------------------------------------------------ */
 static void rotate(double u, double v, double w, double mu, double phi, double out[3]) {
     double s = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double cp = cos(phi), sp = sin(phi);
+    double sp, cp;
+    ko_sincos(phi, &sp, &cp);
     double a, b, cc;
     if (fabs(w) < 1.0 - 1e-10) {
         double t = sqrt(1.0 - w * w);
@@ -379,13 +478,16 @@ static void thermal(const ctx_t* c, const part_t* p, uint32_t sa, uint32_t sb, d
     }
     pair_t a = draw(c->d->seed, p->pid, p->lineage, p->s, sa);
     pair_t b = draw(c->d->seed, p->pid, p->lineage, p->s, sb);
-    double r1 = sqrt(-2.0 * log(a.d0 + TWO_M53));
-    double r2 = sqrt(-2.0 * log(b.d0 + TWO_M53));
+    double r1 = sqrt(-2.0 * ko_log(a.d0 + TWO_M53));
+    double r2 = sqrt(-2.0 * ko_log(b.d0 + TWO_M53));
     double a1 = TWO_PI * a.d1;
     double a2 = TWO_PI * b.d1;
-    V[0] = c->sigma_v * (r1 * cos(a1));
-    V[1] = c->sigma_v * (r1 * sin(a1));
-    V[2] = c->sigma_v * (r2 * cos(a2));
+    double s1, c1, s2, c2;
+    ko_sincos(a1, &s1, &c1);
+    ko_sincos(a2, &s2, &c2);
+    V[0] = c->sigma_v * (r1 * c1);
+    V[1] = c->sigma_v * (r1 * s1);
+    V[2] = c->sigma_v * (r2 * c2);
 }
 
 static void set_velocity(part_t* p, double m, const double vv[3]) {
@@ -432,7 +534,7 @@ static void k_elastic(ctx_t* c, part_t* p, double* gas_out) {
 static double beb_sample(const ctx_t* c, const part_t* p, double t, int64_t* tries) {
     if (!(t > 1.0)) return 0.0;
     double tp1 = t + 1.0;
-    double lt = log(t);
+    double lt = ko_log(t);
     double a4 = 4.0 / (tp1 * tp1);
     double it2 = 1.0 / (t * t);
     double i1 = (t - 1.0) / tp1;
@@ -591,7 +693,7 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
         pair_t q0 = draw(d->seed, p->pid, p->lineage, p->s, 0);
         double eta = q0.d0 + TWO_M53;
         double xi = q0.d1;
-        double dist = (sum > 0.0) ? -log(eta) / sum : INFINITY;
+        double dist = (sum > 0.0) ? -ko_log(eta) / sum : INFINITY;
 
         /* distance to the next face of the current cell */
         double sg = INFINITY;
@@ -666,7 +768,8 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
             if (c->gc) {
                 double om = c->omega[p->sp];
                 double al = -(om * (p->s_path / p->vel));
-                double ca = cos(al), sa = sin(al);
+                double sa, ca;
+                ko_sincos(al, &sa, &ca);
                 double un = ca * p->u - sa * p->v;
                 double vn = sa * p->u + ca * p->v;
                 p->u = un;
@@ -784,11 +887,14 @@ static void birth(ctx_t* c, uint32_t pid, seed_t* b, int64_t* tries) {
     double mu = 2.0 * q1.d1 - 1.0;
     double ph = TWO_PI * q2.d0;
     double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-    b->x = r * cos(al);
-    b->y = r * sin(al);
+    double sal, cal, sph, cph;
+    ko_sincos(al, &sal, &cal);
+    ko_sincos(ph, &sph, &cph);
+    b->x = r * cal;
+    b->y = r * sal;
     b->z = z;
-    b->u = st * cos(ph);
-    b->v = st * sin(ph);
+    b->u = st * cph;
+    b->v = st * sph;
     b->w = mu;
     b->iz = k;
     b->ir = count_faces_le(c->rf, d->n_r, r);
@@ -889,7 +995,8 @@ void ko_debug_helix(double charge, double mass, double bz, const double pos[3],
     double gx = pos[0] + speed * v / om;
     double gy = pos[1] - speed * u / om;
     double al = -(om * (path / speed));
-    double ca = cos(al), sa = sin(al);
+    double sa, ca;
+    ko_sincos(al, &sa, &ca);
     double un = ca * u - sa * v;
     double vn = sa * u + ca * v;
     out[0] = gx - speed * vn / om;

@@ -117,6 +117,9 @@ double ko_u53(uint32_t a, uint32_t b);
 /* QE (J/eV), k_B, m_e c^2 (eV), alpha, pi, 2 pi as used by the oracle */
 void ko_constants(double out[6]);
 uint64_t ko_mix64(uint64_t z);
+/* natural logarithm and sine/cosine from IEEE basic operations (see karl_oracle.c) */
+double ko_log(double x);
+void ko_sincos(double x, double* s, double* c);
 double ko_beta_shape(double e, double e0, double z);
 /* birth state of primary pid: x,y,z,u,v,w,E,tries */
 int ko_birth(const ko_desc* d, int64_t pid, double out[8]);

@@ -1,0 +1,606 @@
+// C ABI of libkarl (include/karl.h): validation, workspace layout, table upload, and the
+// generation loop that drives the transport kernel for a range of primaries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "karl.h"
+#include "karl_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+karl_status fail(karl_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_CHECK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(KARL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr double kKB = 1.380649e-23;
+constexpr size_t kAlign = 256;
+constexpr int kBlock = 256;
+constexpr int64_t kDefaultCapacity = int64_t(1) << 22;
+constexpr int64_t kDefaultChunk = 65536;
+constexpr int64_t kMaxChunk = int64_t(1) << 26;
+constexpr size_t kMaxLds = 65536;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Byte offsets of every region of the caller's workspace.
+struct Layout {
+    size_t xs, n_gas, zf, rf, zcdf, n_ion, edges, plane_of;
+    size_t tallies, tally_bytes;
+    size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
+    size_t snapshot, control, queues, queue_entries;
+    size_t total;
+};
+
+size_t real_size(const karl_job_desc* d) { return d->precision == KARL_FP32 ? 4 : 8; }
+
+Layout make_layout(const karl_job_desc* d) {
+    Layout L{};
+    const size_t rs = real_size(d);
+    const size_t nr = (size_t)d->n_r, nz = (size_t)d->n_z;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.xs = take(rs * (size_t)d->n_proc * (size_t)d->n_e);
+    L.n_gas = take(rs * nz);
+    L.zf = take(rs * (nz + 1));
+    L.rf = take(rs * (nr + 1));
+    L.zcdf = take(rs * (nz + 1));
+    L.n_ion = take(d->n_ion ? 8 * nr * nz : 0);
+    L.edges = take(8 * 2 * ((size_t)d->n_bins + 1));
+    L.plane_of = take(4 * (nz + 1));
+    // tallies: one contiguous block so that a snapshot is one copy
+    size_t t = 0;
+    auto tk = [&](size_t bytes) {
+        size_t o = t;
+        t += (bytes + 7) & ~size_t(7);
+        return o;
+    };
+    const size_t np = (size_t)d->n_primaries;
+    L.t_counters = tk(8 * KARL_NCOUNTERS);
+    L.t_ledger = tk(8 * KARL_NLEDGER);
+    L.t_dens = tk(8 * 2 * nr * nz);
+    L.t_recomb = tk(8 * nr * nz);
+    L.t_jz = tk(8 * 2 * nr * (nz + 1) * 2);
+    L.t_jr = tk(8 * 2 * (nr + 1) * nz * 2);
+    L.t_spectra = tk(8 * 2 * (size_t)d->n_planes * 2 * ((size_t)d->n_bins + 2));
+    L.t_digests = tk((d->flags & KARL_FLAG_DIGESTS) ? 8 * np : 0);
+    L.t_hist = tk((d->flags & KARL_FLAG_HISTORY) ? 8 * KARL_NHIST * np : 0);
+    L.tally_bytes = t;
+    L.tallies = take(t);
+    L.snapshot = take(t);
+    L.control = take(64);
+    L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
+    L.queues = take(2 * L.queue_entries * (7 * 8 + 8 + 4 + 4));
+    L.total = off;
+    return L;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+karl_status validate(const karl_job_desc* d, bool need_workspace) {
+    if (!d) return fail(KARL_EINVAL, "descriptor is NULL");
+    if (!finite_pos(d->radius) || !finite_pos(d->length))
+        return fail(KARL_EINVAL, "radius and length must be finite and positive");
+    if (d->n_r < 1 || d->n_r > 2047 || d->n_z < 1 || d->n_z >= (1 << 19))
+        return fail(KARL_EINVAL, "grid must have 1 <= n_r <= 2047 and 1 <= n_z < 2^19");
+    if (d->n_e < 2 || d->n_e > 1024) return fail(KARL_EINVAL, "n_e must be in 2..1024");
+    if (d->n_proc < 0 || d->n_proc > KARL_MAX_PROC)
+        return fail(KARL_EINVAL, "n_proc must be in 0..%d", KARL_MAX_PROC);
+    if (d->n_bins < 1 || d->n_bins > (1 << 20)) return fail(KARL_EINVAL, "n_bins must be in 1..2^20");
+    if (d->n_planes < 0 || (d->n_planes > 0 && !d->planes))
+        return fail(KARL_EINVAL, "planes missing");
+    for (int p = 0; p < d->n_planes; ++p)
+        if (d->planes[p] < 0 || d->planes[p] > d->n_z)
+            return fail(KARL_EINVAL, "plane %d: z-face index %d outside 0..n_z", p, d->planes[p]);
+    if (!d->n_gas) return fail(KARL_EINVAL, "n_gas is NULL");
+    for (int k = 0; k < d->n_z; ++k)
+        if (!std::isfinite(d->n_gas[k]) || d->n_gas[k] < 0.0)
+            return fail(KARL_EINVAL, "n_gas[%d] must be finite and >= 0", k);
+    if (d->n_ion)
+        for (int k = 0; k < d->n_r * d->n_z; ++k)
+            if (!std::isfinite(d->n_ion[k]) || d->n_ion[k] < 0.0)
+                return fail(KARL_EINVAL, "n_ion[%d] must be finite and >= 0", k);
+    if (!std::isfinite(d->t_gas) || d->t_gas < 0.0) return fail(KARL_EINVAL, "t_gas must be >= 0");
+    if (!finite_pos(d->m_gas)) return fail(KARL_EINVAL, "m_gas must be positive");
+    if (!std::isfinite(d->bz)) return fail(KARL_EINVAL, "bz must be finite");
+    for (int s = 0; s < 2; ++s) {
+        const karl_species_desc& sp = d->species[s];
+        if (!finite_pos(sp.mass)) return fail(KARL_EINVAL, "species %d: mass must be positive", s);
+        if (!std::isfinite(sp.charge) || (d->bz != 0.0 && sp.charge == 0.0))
+            return fail(KARL_EINVAL, "species %d: charge must be finite and nonzero in a field", s);
+        if (!(sp.e_cut >= 0.0) || !(sp.lifetime > 0.0) || sp.cap < 1)
+            return fail(KARL_EINVAL, "species %d: e_cut >= 0, lifetime > 0, cap >= 1 required", s);
+        if (!finite_pos(sp.xs_emin) || !(sp.xs_emax > sp.xs_emin) || !std::isfinite(sp.xs_emax))
+            return fail(KARL_EINVAL, "species %d: need 0 < xs_emin < xs_emax", s);
+        if (!sp.edges) return fail(KARL_EINVAL, "species %d: spectrum edges missing", s);
+        for (int b = 0; b < d->n_bins; ++b)
+            if (!(sp.edges[b] < sp.edges[b + 1]))
+                return fail(KARL_EINVAL, "species %d: edges must increase", s);
+    }
+    for (int i = 0; i < d->n_proc; ++i) {
+        const karl_process_desc& p = d->proc[i];
+        if (p.kind < KARL_ELASTIC || p.kind > KARL_RECOMBINATION)
+            return fail(KARL_EINVAL, "process %d: unknown kind %d", i, p.kind);
+        if (p.species < 0 || p.species > 1) return fail(KARL_EINVAL, "process %d: species", i);
+        if (p.target != KARL_TARGET_GAS && p.target != KARL_TARGET_ION_FIELD)
+            return fail(KARL_EINVAL, "process %d: target", i);
+        if (!p.xs) return fail(KARL_EINVAL, "process %d: table missing", i);
+        if (!std::isfinite(p.e_th) || p.e_th < 0.0) return fail(KARL_EINVAL, "process %d: e_th", i);
+        if (p.kind == KARL_IONIZATION && !(p.e_th > 0.0))
+            return fail(KARL_EINVAL, "process %d: ionization needs a binding energy > 0", i);
+        for (int k = 0; k < d->n_e; ++k)
+            if (!std::isfinite(p.xs[k]) || p.xs[k] < 0.0)
+                return fail(KARL_EINVAL, "process %d: cross section %d must be finite and >= 0", i, k);
+    }
+    if (d->source == KARL_SOURCE_BETA) {
+        if (!finite_pos(d->beta_e0) || !finite_pos(d->beta_fmax) || !std::isfinite(d->beta_z))
+            return fail(KARL_EINVAL, "beta source needs e0 > 0 and f_max > 0");
+    } else if (d->source == KARL_SOURCE_BEAM) {
+        if (d->beam_species < 0 || d->beam_species > 1 || !std::isfinite(d->beam_energy) ||
+            d->beam_energy < 0.0)
+            return fail(KARL_EINVAL, "beam needs a species slot and an energy >= 0");
+        const double n = std::sqrt(d->beam_dir[0] * d->beam_dir[0] + d->beam_dir[1] * d->beam_dir[1] +
+                                   d->beam_dir[2] * d->beam_dir[2]);
+        if (!(std::fabs(n - 1.0) < 1e-9)) return fail(KARL_EINVAL, "beam direction must be a unit vector");
+        const double r = std::sqrt(d->beam_pos[0] * d->beam_pos[0] + d->beam_pos[1] * d->beam_pos[1]);
+        if (!(r < d->radius) || !(d->beam_pos[2] >= 0.0) || !(d->beam_pos[2] <= d->length))
+            return fail(KARL_EINVAL, "beam start must lie inside the cylinder");
+    } else {
+        return fail(KARL_EINVAL, "unknown source %d", d->source);
+    }
+    if (d->n_primaries < 0 || d->n_primaries > (int64_t)0xFFFFFFFFLL)
+        return fail(KARL_EINVAL, "n_primaries must be in 0..2^32-1");
+    if (d->precision != KARL_FP64 && d->precision != KARL_FP32)
+        return fail(KARL_EINVAL, "precision must be KARL_FP64 or KARL_FP32");
+    if (d->queue_capacity < 0 || d->chunk < 0) return fail(KARL_EINVAL, "negative queue/chunk size");
+    if (need_workspace) {
+        const Layout L = make_layout(d);
+        if (!d->workspace) return fail(KARL_EINVAL, "workspace is NULL");
+        if (d->workspace_bytes < L.total)
+            return fail(KARL_ENOMEM, "workspace has %llu bytes, job needs %llu",
+                        (unsigned long long)d->workspace_bytes, (unsigned long long)L.total);
+    }
+    return KARL_OK;
+}
+
+int count_faces_le(const std::vector<double>& faces, int n, double r) {
+    int k = 0;
+    for (int j = 1; j < n; ++j)
+        if (faces[j] <= r) k = j;
+    return k;
+}
+
+struct Job {
+    int precision = 0;
+    uint32_t flags = 0;
+    int64_t n_primaries = 0;
+    int n_r = 0, n_z = 0, n_planes = 0, n_bins = 0;
+    char* ws = nullptr;
+    Layout lay{};
+    karl::DevJob dj{};
+    karl::QueueSoA q[2]{};
+    unsigned long long* fetch = nullptr;
+    unsigned long long* qcount = nullptr;
+    unsigned int* status = nullptr;
+    size_t lds = 0;
+    int max_blocks = 0;
+    int64_t capacity = 0;
+    int64_t chunk = 0;
+    unsigned long long* host_ctl = nullptr;   // pinned: [qcount, status]
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
+    int64_t launches = 0, generations = 0, max_queue = 0;
+    bool failed = false;
+    int device = 0;
+};
+
+template <typename T>
+std::vector<T> convert(const double* src, size_t n) {
+    std::vector<T> out(n);
+    for (size_t i = 0; i < n; ++i) out[i] = (T)src[i];
+    return out;
+}
+
+karl_status upload_real(const Job& j, size_t off, const std::vector<double>& v) {
+    char* dst = j.ws + off;
+    if (j.precision == KARL_FP32) {
+        std::vector<float> f = convert<float>(v.data(), v.size());
+        HIP_CHECK(hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        HIP_CHECK(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return KARL_OK;
+}
+
+karl::QueueSoA queue_at(char* base, size_t cap) {
+    karl::QueueSoA q;
+    size_t o = 0;
+    auto d = [&]() {
+        double* p = (double*)(base + o);
+        o += 8 * cap;
+        return p;
+    };
+    q.x = d(); q.y = d(); q.z = d(); q.u = d(); q.v = d(); q.w = d(); q.e = d();
+    q.lin = (unsigned long long*)(base + o);
+    o += 8 * cap;
+    q.pid = (uint32_t*)(base + o);
+    o += 4 * cap;
+    q.meta = (uint32_t*)(base + o);
+    return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* karl_last_error(void) { return g_err; }
+
+karl_status karl_workspace_bytes(const karl_job_desc* desc, uint64_t* bytes) {
+    if (!bytes) return fail(KARL_EINVAL, "bytes is NULL");
+    karl_status st = validate(desc, false);
+    if (st != KARL_OK) return st;
+    *bytes = make_layout(desc).total;
+    return KARL_OK;
+}
+
+karl_status karl_create_job(const karl_job_desc* d, void** out) {
+    g_err[0] = '\0';
+    if (!out) return fail(KARL_EINVAL, "out is NULL");
+    *out = nullptr;
+    karl_status st = validate(d, true);
+    if (st != KARL_OK) return st;
+    Job* j = new Job();
+    j->precision = d->precision;
+    j->flags = d->flags;
+    j->n_primaries = d->n_primaries;
+    j->n_r = d->n_r;
+    j->n_z = d->n_z;
+    j->n_planes = d->n_planes;
+    j->n_bins = d->n_bins;
+    j->ws = (char*)d->workspace;
+    j->lay = make_layout(d);
+    j->capacity = (int64_t)j->lay.queue_entries;
+    j->chunk = d->chunk > 0 ? d->chunk : kDefaultChunk;
+    const Layout& L = j->lay;
+    auto cleanup = [&](karl_status s) {
+        if (j->host_ctl) (void)hipHostFree(j->host_ctl);
+        if (j->ev0) (void)hipEventDestroy(j->ev0);
+        if (j->ev1) (void)hipEventDestroy(j->ev1);
+        delete j;
+        return s;
+    };
+#define TRY(expr)                                 \
+    do {                                          \
+        karl_status s_ = (expr);                  \
+        if (s_ != KARL_OK) return cleanup(s_);    \
+    } while (0)
+#define TRY_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return cleanup(fail(KARL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+
+    TRY_HIP(hipGetDevice(&j->device));
+    hipDeviceProp_t prop;
+    TRY_HIP(hipGetDeviceProperties(&prop, j->device));
+
+    // ---- host-side tables
+    const int nz = d->n_z, nr = d->n_r;
+    std::vector<double> xs((size_t)d->n_proc * d->n_e);
+    for (int i = 0; i < d->n_proc; ++i)
+        std::memcpy(&xs[(size_t)i * d->n_e], d->proc[i].xs, sizeof(double) * (size_t)d->n_e);
+    std::vector<double> ngas(d->n_gas, d->n_gas + nz);
+    std::vector<double> zf(nz + 1), rf(nr + 1), zcdf(nz + 1);
+    for (int k = 0; k <= nz; ++k) zf[k] = d->length * (double)k / (double)nz;
+    for (int k = 0; k <= nr; ++k) rf[k] = d->radius * (double)k / (double)nr;
+    zcdf[0] = 0.0;
+    for (int k = 0; k < nz; ++k) zcdf[k + 1] = zcdf[k] + d->n_gas[k];
+    std::vector<double> edges(2 * ((size_t)d->n_bins + 1));
+    for (int s = 0; s < 2; ++s)
+        std::memcpy(&edges[(size_t)s * (d->n_bins + 1)], d->species[s].edges,
+                    sizeof(double) * ((size_t)d->n_bins + 1));
+    std::vector<int32_t> plane_of(nz + 1, -1);
+    for (int p = 0; p < d->n_planes; ++p)
+        if (plane_of[d->planes[p]] < 0) plane_of[d->planes[p]] = p;
+
+    TRY(upload_real(*j, L.xs, xs));
+    TRY(upload_real(*j, L.n_gas, ngas));
+    TRY(upload_real(*j, L.zf, zf));
+    TRY(upload_real(*j, L.rf, rf));
+    TRY(upload_real(*j, L.zcdf, zcdf));
+    if (d->n_ion)
+        TRY_HIP(hipMemcpy(j->ws + L.n_ion, d->n_ion, sizeof(double) * (size_t)nr * nz, hipMemcpyHostToDevice));
+    TRY_HIP(hipMemcpy(j->ws + L.edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
+    TRY_HIP(hipMemcpy(j->ws + L.plane_of, plane_of.data(), sizeof(int32_t) * plane_of.size(), hipMemcpyHostToDevice));
+
+    // ---- device job
+    karl::DevJob& J = j->dj;
+    J.radius = d->radius;
+    J.length = d->length;
+    J.n_r = nr;
+    J.n_z = nz;
+    J.n_e = d->n_e;
+    J.n_proc = d->n_proc;
+    J.n_bins = d->n_bins;
+    J.n_planes = d->n_planes;
+    J.gc = d->bz != 0.0 ? 1 : 0;
+    J.source = d->source;
+    J.beam_species = d->beam_species;
+    J.flags = (int32_t)d->flags;
+    J.seed = d->seed;
+    J.n_ion_present = d->n_ion ? 1 : 0;
+    for (int s = 0; s < 2; ++s) {
+        const karl_species_desc& sp = d->species[s];
+        J.tracked[s] = sp.tracked ? 1 : 0;
+        J.cap[s] = sp.cap;
+        J.mass[s] = sp.mass;
+        J.charge[s] = sp.charge;
+        J.e_cut[s] = sp.e_cut;
+        J.lifetime[s] = sp.lifetime;
+        J.msum[s] = sp.mass + d->m_gas;
+        J.xs_emin[s] = sp.xs_emin;
+        J.inv_dlog[s] = (double)(d->n_e - 1) / std::log(sp.xs_emax / sp.xs_emin);
+        J.omega[s] = sp.charge * d->bz / sp.mass;
+        J.nps[s] = 0;
+    }
+    for (int i = 0; i < KARL_MAX_PROC; ++i) {
+        J.kind[i] = i < d->n_proc ? d->proc[i].kind : 0;
+        J.target[i] = i < d->n_proc ? d->proc[i].target : 0;
+        J.e_th[i] = i < d->n_proc ? d->proc[i].e_th : 0.0;
+    }
+    for (int i = 0; i < d->n_proc; ++i) {
+        const int s = d->proc[i].species;
+        J.pidx[s][J.nps[s]++] = i;
+    }
+    J.sigma_v = std::sqrt(kKB * d->t_gas / d->m_gas);
+    J.m_gas = d->m_gas;
+    J.beta_e0 = d->beta_e0;
+    J.beta_z = d->beta_z;
+    J.beta_fmax = d->beta_fmax;
+    J.beam_e = d->beam_energy;
+    for (int k = 0; k < 3; ++k) {
+        J.beam_pos[k] = d->beam_pos[k];
+        J.beam_dir[k] = d->beam_dir[k];
+    }
+    J.beam_ir = count_faces_le(rf, nr, std::sqrt(d->beam_pos[0] * d->beam_pos[0] + d->beam_pos[1] * d->beam_pos[1]));
+    J.beam_iz = count_faces_le(zf, nz, d->beam_pos[2]);
+    char* w = j->ws;
+    J.xs = w + L.xs;
+    J.n_gas = w + L.n_gas;
+    J.zf = w + L.zf;
+    J.rf = w + L.rf;
+    J.zcdf = w + L.zcdf;
+    J.n_ion = d->n_ion ? (const double*)(w + L.n_ion) : nullptr;
+    J.edges = (const double*)(w + L.edges);
+    J.plane_of = (const int32_t*)(w + L.plane_of);
+    char* t = w + L.tallies;
+    J.counters = (unsigned long long*)(t + L.t_counters);
+    J.ledger = (double*)(t + L.t_ledger);
+    J.dens = (double*)(t + L.t_dens);
+    J.recomb = (unsigned long long*)(t + L.t_recomb);
+    J.jz = (unsigned long long*)(t + L.t_jz);
+    J.jr = (unsigned long long*)(t + L.t_jr);
+    J.spectra = (unsigned long long*)(t + L.t_spectra);
+    J.digests = (d->flags & KARL_FLAG_DIGESTS) ? (unsigned long long*)(t + L.t_digests) : nullptr;
+    J.hist = (d->flags & KARL_FLAG_HISTORY) ? (double*)(t + L.t_hist) : nullptr;
+    unsigned long long* ctl = (unsigned long long*)(w + L.control);
+    j->fetch = ctl;
+    j->qcount = ctl + 1;
+    j->status = (unsigned int*)(ctl + 2);
+    J.status = j->status;
+    j->q[0] = queue_at(w + L.queues, L.queue_entries);
+    j->q[1] = queue_at(w + L.queues + L.queue_entries * (7 * 8 + 8 + 4 + 4), L.queue_entries);
+
+    j->lds = karl::lds_bytes(J, d->precision);
+    if (j->lds > kMaxLds)
+        return cleanup(fail(KARL_EINVAL, "tables need %zu bytes of LDS per workgroup (max %zu)",
+                            j->lds, kMaxLds));
+    int per_cu = 0;
+    TRY_HIP(karl::transport_occupancy(d->precision, kBlock, j->lds, &per_cu));
+    if (per_cu < 1) per_cu = 1;
+    j->max_blocks = per_cu * prop.multiProcessorCount;
+
+    TRY_HIP(hipHostMalloc((void**)&j->host_ctl, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    TRY_HIP(hipEventCreate(&j->ev0));
+    TRY_HIP(hipEventCreate(&j->ev1));
+    // zero tallies and control words
+    TRY_HIP(karl::launch_fill_u64((unsigned long long*)t, L.tally_bytes / 8, 0ull, nullptr));
+    TRY_HIP(karl::launch_fill_u64(ctl, 8, 0ull, nullptr));
+    TRY_HIP(hipDeviceSynchronize());
+#undef TRY
+#undef TRY_HIP
+    *out = j;
+    return KARL_OK;
+}
+
+static karl_status run_generations(Job* j, int64_t pid_begin, int64_t n, hipStream_t s,
+                                   bool* overflow, int64_t* max_gen) {
+    *overflow = false;
+    *max_gen = 0;
+    int mode = 0;
+    int64_t items = n;
+    int qin = 0;
+    while (items > 0) {
+        karl::GenArgs g{};
+        g.mode = mode;
+        g.pid_begin = pid_begin;
+        g.n_items = items;
+        g.fetch = j->fetch;
+        g.qin = j->q[qin];
+        g.qout = j->q[1 - qin];
+        g.qout_count = j->qcount;
+        g.capacity = j->capacity;
+        HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
+        int64_t blocks = (items + kBlock - 1) / kBlock;
+        if (blocks > j->max_blocks) blocks = j->max_blocks;
+        HIP_CHECK(hipEventRecord(j->ev0, s));
+        HIP_CHECK(karl::launch_transport(j->dj, g, j->precision, (int)blocks, kBlock, j->lds, s));
+        HIP_CHECK(hipEventRecord(j->ev1, s));
+        HIP_CHECK(hipMemcpyAsync(j->host_ctl, j->qcount, 2 * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, j->ev0, j->ev1));
+        j->kernel_ms += ms;
+        j->launches += 1;
+        if (mode == 1) j->generations += 1;
+        const unsigned long long produced = j->host_ctl[0];
+        const unsigned int status = (unsigned int)(j->host_ctl[1] & 0xFFFFFFFFull);
+        if (status & karl::STATUS_OVERFLOW) {
+            *overflow = true;
+            return KARL_OK;
+        }
+        items = (int64_t)produced;
+        if (items > *max_gen) *max_gen = items;
+        if (items > j->max_queue) j->max_queue = items;
+        mode = 1;
+        qin = 1 - qin;
+    }
+    return KARL_OK;
+}
+
+karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_ESTATE, "job is NULL");
+    if (j->failed) return fail(KARL_ESTATE, "job failed earlier; destroy and recreate it");
+    if (pid_begin < 0 || pid_end < pid_begin || pid_end > j->n_primaries)
+        return fail(KARL_EINVAL, "pid range [%lld, %lld) outside 0..%lld", (long long)pid_begin,
+                    (long long)pid_end, (long long)j->n_primaries);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(hipSetDevice(j->device));
+    int64_t b = pid_begin;
+    char* tallies = j->ws + j->lay.tallies;
+    char* snap = j->ws + j->lay.snapshot;
+    while (b < pid_end) {
+        const int64_t n = std::min<int64_t>(j->chunk, pid_end - b);
+        HIP_CHECK(hipMemcpyAsync(snap, tallies, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
+        bool overflow = false;
+        int64_t max_gen = 0;
+        karl_status st = run_generations(j, b, n, s, &overflow, &max_gen);
+        if (st != KARL_OK) {
+            j->failed = true;
+            return st;
+        }
+        if (overflow) {
+            // undo the partial chunk and retry with half as many primaries
+            HIP_CHECK(hipMemcpyAsync(tallies, snap, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
+            j->host_ctl[2] = (unsigned long long)((unsigned int)j->host_ctl[1] & ~karl::STATUS_OVERFLOW);
+            HIP_CHECK(hipMemcpyAsync(j->status, &j->host_ctl[2], sizeof(unsigned int), hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (n == 1) {
+                j->failed = true;
+                return fail(KARL_EOVERFLOW, "primary %lld alone overflows a queue of %lld entries",
+                            (long long)b, (long long)j->capacity);
+            }
+            j->chunk = std::max<int64_t>(1, n / 2);
+            continue;
+        }
+        b += n;
+        // next chunk: keep the largest generation near half the queue capacity
+        if (max_gen > 0) {
+            const double per_primary = (double)max_gen / (double)n;
+            const double target = 0.5 * (double)j->capacity / per_primary;
+            j->chunk = std::max<int64_t>(1, std::min<int64_t>(kMaxChunk, (int64_t)target));
+        } else {
+            j->chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(j->chunk, 2 * n));
+        }
+    }
+    return KARL_OK;
+}
+
+karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j || !out) return fail(KARL_EINVAL, "job or out is NULL");
+    HIP_CHECK(hipSetDevice(j->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(hipStreamSynchronize(s));
+    const karl::DevJob& J = j->dj;
+    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z;
+    auto get = [&](void* dst, const void* src, size_t bytes) -> karl_status {
+        if (dst && src && bytes) HIP_CHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        return KARL_OK;
+    };
+    karl_status st;
+    if ((st = get(out->counters, J.counters, 8 * KARL_NCOUNTERS)) != KARL_OK) return st;
+    if ((st = get(out->ledger, J.ledger, 8 * KARL_NLEDGER)) != KARL_OK) return st;
+    if ((st = get(out->density_time, J.dens, 8 * 2 * nr * nz)) != KARL_OK) return st;
+    if ((st = get(out->recomb, J.recomb, 8 * nr * nz)) != KARL_OK) return st;
+    if ((st = get(out->jz, J.jz, 8 * 2 * nr * (nz + 1) * 2)) != KARL_OK) return st;
+    if ((st = get(out->jr, J.jr, 8 * 2 * (nr + 1) * nz * 2)) != KARL_OK) return st;
+    if ((st = get(out->spectra, J.spectra, 8 * 2 * (size_t)j->n_planes * 2 * ((size_t)j->n_bins + 2))) != KARL_OK)
+        return st;
+    if (out->digests) {
+        if (!J.digests) return fail(KARL_EINVAL, "digests requested but KARL_FLAG_DIGESTS not set");
+        if ((st = get(out->digests, J.digests, 8 * (size_t)j->n_primaries)) != KARL_OK) return st;
+    }
+    if (out->hist) {
+        if (!J.hist) return fail(KARL_EINVAL, "history ledger requested but KARL_FLAG_HISTORY not set");
+        if ((st = get(out->hist, J.hist, 8 * KARL_NHIST * (size_t)j->n_primaries)) != KARL_OK) return st;
+    }
+    unsigned int status = 0;
+    HIP_CHECK(hipMemcpy(&status, j->status, sizeof(status), hipMemcpyDeviceToHost));
+    if (status & karl::STATUS_NUMERIC) return fail(KARL_ENUMERIC, "NaN met in the particle state");
+    if (j->failed) return fail(KARL_ESTATE, "job failed earlier; tallies are incomplete");
+    return KARL_OK;
+}
+
+karl_status karl_reset_tallies(void* job, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_EINVAL, "job is NULL");
+    HIP_CHECK(hipSetDevice(j->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(karl::launch_fill_u64((unsigned long long*)(j->ws + j->lay.tallies), j->lay.tally_bytes / 8, 0ull, s));
+    HIP_CHECK(karl::launch_fill_u64(j->fetch, 3, 0ull, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    j->kernel_ms = 0.0;
+    j->launches = j->generations = j->max_queue = 0;
+    j->failed = false;
+    return KARL_OK;
+}
+
+karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches, int64_t* generations,
+                           int64_t* max_queue) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_EINVAL, "job is NULL");
+    if (kernel_ms) *kernel_ms = j->kernel_ms;
+    if (n_launches) *n_launches = j->launches;
+    if (generations) *generations = j->generations;
+    if (max_queue) *max_queue = j->max_queue;
+    return KARL_OK;
+}
+
+karl_status karl_destroy_job(void* job) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_EINVAL, "job is NULL");
+    if (j->host_ctl) (void)hipHostFree(j->host_ctl);
+    if (j->ev0) (void)hipEventDestroy(j->ev0);
+    if (j->ev1) (void)hipEventDestroy(j->ev1);
+    delete j;
+    return KARL_OK;
+}
+
+}  // extern "C"

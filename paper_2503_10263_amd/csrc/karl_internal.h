@@ -1,0 +1,92 @@
+// Internal interface between the C-ABI host code (karl_api.hip) and the device code
+// (karl_kernels.hip) of libkarl.  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "karl.h"
+
+namespace karl {
+
+// Secondary queue in structure-of-arrays layout: one coalesced array per field.
+struct QueueSoA {
+    double* x;
+    double* y;
+    double* z;
+    double* u;
+    double* v;
+    double* w;
+    double* e;
+    unsigned long long* lin;   // lineage
+    uint32_t* pid;             // primary id
+    uint32_t* meta;            // species | r-cell << 2 | z-cell << 13
+};
+
+// Everything the transport kernel needs about one job, passed by value.
+struct DevJob {
+    double radius, length;
+    int32_t n_r, n_z, n_e, n_proc, n_bins, n_planes;
+    int32_t gc, source, beam_species, flags;
+    uint32_t seed;
+    int32_t beam_ir, beam_iz, n_ion_present;
+    int32_t nps[2];
+    int32_t tracked[2];
+    int64_t cap[2];
+    double mass[2], charge[2], e_cut[2], lifetime[2];
+    double msum[2];        // mass + m_gas
+    double xs_emin[2], inv_dlog[2];
+    double omega[2];       // charge * bz / mass
+    double sigma_v;        // sqrt(k T / m_gas)
+    double m_gas;
+    double beta_e0, beta_z, beta_fmax;
+    double beam_e, beam_pos[3], beam_dir[3];
+    int32_t pidx[2][KARL_MAX_PROC];   // global process index of the j-th process of a species
+    int32_t kind[KARL_MAX_PROC];
+    int32_t target[KARL_MAX_PROC];
+    double e_th[KARL_MAX_PROC];
+    // device tables (Real = double or float according to the precision)
+    const void* xs;        // [n_proc][n_e]
+    const void* n_gas;     // [n_z]
+    const void* zf;        // [n_z+1] z faces
+    const void* rf;        // [n_r+1] r faces
+    const void* zcdf;      // [n_z+1] cumulative gas weights
+    const double* n_ion;   // [n_r*n_z]
+    const double* edges;   // [2][n_bins+1]
+    const int32_t* plane_of;   // [n_z+1] plane index or -1
+    // tallies
+    unsigned long long* counters;
+    double* ledger;
+    double* dens;
+    unsigned long long* recomb;
+    unsigned long long* jz;
+    unsigned long long* jr;
+    unsigned long long* spectra;
+    unsigned long long* digests;
+    double* hist;
+    unsigned int* status;
+};
+
+// One generation: primaries (mode 0) or the secondaries of the previous generation.
+struct GenArgs {
+    int32_t mode;
+    int32_t pad;
+    int64_t pid_begin;
+    int64_t n_items;
+    unsigned long long* fetch;
+    QueueSoA qin;
+    QueueSoA qout;
+    unsigned long long* qout_count;
+    int64_t capacity;
+};
+
+enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
+
+size_t lds_bytes(const DevJob& j, int precision);
+hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, int grid,
+                            int block, size_t lds, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
+                           hipStream_t s);
+hipError_t transport_occupancy(int precision, int block, size_t lds, int* blocks_per_cu);
+
+}  // namespace karl

@@ -1,0 +1,1116 @@
+// Device code of libkarl: the particle-history transport of the KARL method (arXiv
+// 2503.10263) for gfx950.
+//
+// One lane carries one particle from birth to deletion (main cycle, Sec. 2.1): free flight
+// d = -lambda ln(eta) with lambda from eq. (1), stop without interaction at every segment face
+// and redraw (Sec. 3.1 "Movement"), guiding-centre helix in a uniform axial field (Sec. 3.1
+// "Drift mover"), interaction chosen with weight sigma_i n_i and performed (Sec. 3.3),
+// termination and deletion logging (Sec. 3.2).  A lane whose particle is deleted takes the
+// next work item of the generation: a primary id (generation 0) or a secondary produced by
+// the previous generation.  Secondaries go to the next generation's queue through one
+// wave-aggregated atomic (ballot + mbcnt prefix) per wave.
+//
+// Layout: particle state lives in registers; cross-section tables, gas density and face
+// positions are staged in LDS per workgroup; queues are structure-of-arrays in HBM; tallies
+// are FP64/int64 in HBM, updated once per segment visit (time) or crossing (counts);
+// per-event counters are kept in registers or LDS and flushed once per workgroup.
+//
+// Every floating-point expression of the FP64 instantiation is written in the same order as
+// the specification of the method so that, compiled without contraction, each operation is
+// rounded exactly as the reference evaluation is.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "karl_internal.h"
+
+namespace karl {
+namespace {
+
+constexpr double kQE = 1.602176634e-19;   // J per eV (exact)
+constexpr double kMEC2 = 510998.95;        // electron rest energy, eV (CODATA 2018)
+constexpr double kALPHA = 7.2973525693e-3; // fine-structure constant (CODATA 2018)
+constexpr double kPI = 3.14159265358979323846;
+constexpr double kTWO_PI = 6.28318530717958647692;
+constexpr double kTWO_PI_DEF = 6.28318530717958647692;
+constexpr unsigned long long kPHI64 = 0x9E3779B97F4A7C15ull;
+constexpr unsigned long long kDIGEST0 = 0x5851F42D4C957F2Dull;
+constexpr uint32_t kBIRTH_STEP = 0xFFFFFFFFu;
+
+constexpr int kBlock = 256;
+constexpr int kNCnt = KARL_NCOUNTERS;
+constexpr int kNLed = KARL_NLEDGER;
+
+// ---------------------------------------------------------------- elementary functions
+// FP64 logarithm and sine/cosine built from IEEE basic operations only.  The guiding-centre
+// phase (omega t ~ 1e5 rad) amplifies any 1-ulp difference of a transcendental roughly
+// fifty-fold per collision, so these are spelled out step by step -- frexp reduction and
+// atanh series for ln, Cody-Waite reduction by pi/2 in four 26-bit pieces and Taylor
+// series for sin/cos -- which any other evaluation of the same steps reproduces exactly.
+constexpr double kSqrtHalf = 0.70710678118654757;
+constexpr double kLn2Hi = 0.6931471805601177;         // ln 2 to 40 bits (e * hi exact)
+constexpr double kLn2Lo = -1.7239444525614835e-13;    // ln 2 - hi
+constexpr double kPiO4 = 0.78539816339744828;
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPiO2_1 = 1.5707963407039642;
+constexpr double kPiO2_2 = -1.3909067675399456e-08;
+constexpr double kPiO2_3 = 6.123233932053594e-17;
+constexpr double kPiO2_4 = 6.368317178484799e-25;
+
+__device__ __forceinline__ double klog(double x) {
+    if (!(x > 0.0)) return (x == 0.0) ? -INFINITY : NAN;
+    if (isinf(x)) return x;
+    int e;
+    double m = frexp(x, &e);                 // m in [0.5, 1)
+    if (m < kSqrtHalf) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (m + 1.0);          // ln m = 2 atanh(s)
+    const double z = s * s;
+    double p = 0.04;                         // coefficients 1/(2n+1), n = 12 .. 1
+    p = 0.043478260869565216 + z * p;
+    p = 0.047619047619047616 + z * p;
+    p = 0.05263157894736842 + z * p;
+    p = 0.058823529411764705 + z * p;
+    p = 0.06666666666666667 + z * p;
+    p = 0.07692307692307693 + z * p;
+    p = 0.09090909090909091 + z * p;
+    p = 0.1111111111111111 + z * p;
+    p = 0.14285714285714285 + z * p;
+    p = 0.2 + z * p;
+    p = 0.3333333333333333 + z * p;
+    const double t = 2.0 * s;
+    const double lm = t + t * (z * p);
+    const double de = (double)e;
+    return de * kLn2Hi + (de * kLn2Lo + lm);
+}
+__device__ __forceinline__ float klog(float x) { return logf(x); }
+
+__device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
+    if (!isfinite(x)) {
+        *sn = NAN;
+        *cs = NAN;
+        return;
+    }
+    double r = x;
+    long long q = 0;
+    if (fabs(x) > kPiO4) {
+        double xx = x;
+        if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / kTWO_PI_DEF) * kTWO_PI_DEF;
+        const double k = floor(xx * kTwoOverPi + 0.5);
+        r = xx - k * kPiO2_1;
+        r = r - k * kPiO2_2;
+        r = r - k * kPiO2_3;
+        r = r - k * kPiO2_4;
+        q = (long long)k;
+    }
+    const double z = r * r;
+    double ps = -8.22063524662433e-18;       // sine: -1/19! ... -1/3!
+    ps = 2.8114572543455206e-15 + z * ps;
+    ps = -7.647163731819816e-13 + z * ps;
+    ps = 1.6059043836821613e-10 + z * ps;
+    ps = -2.505210838544172e-08 + z * ps;
+    ps = 2.7557319223985893e-06 + z * ps;
+    ps = -0.0001984126984126984 + z * ps;
+    ps = 0.008333333333333333 + z * ps;
+    ps = -0.16666666666666666 + z * ps;
+    const double sv = r + r * (z * ps);
+    double pc = 4.110317623312165e-19;       // cosine: 1/20! ... 1/4!
+    pc = -1.5619206968586225e-16 + z * pc;
+    pc = 4.779477332387385e-14 + z * pc;
+    pc = -1.1470745597729725e-11 + z * pc;
+    pc = 2.08767569878681e-09 + z * pc;
+    pc = -2.755731922398589e-07 + z * pc;
+    pc = 2.48015873015873e-05 + z * pc;
+    pc = -0.001388888888888889 + z * pc;
+    pc = 0.041666666666666664 + z * pc;
+    const double cv = (1.0 - 0.5 * z) + (z * z) * pc;
+    switch (q & 3) {
+        case 0: *sn = sv; *cs = cv; break;
+        case 1: *sn = cv; *cs = -sv; break;
+        case 2: *sn = -sv; *cs = -cv; break;
+        default: *sn = -cv; *cs = sv; break;
+    }
+}
+__device__ __forceinline__ void ksincos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+__device__ __forceinline__ double ksqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float ksqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double kexp(double x) { return exp(x); }
+__device__ __forceinline__ float kexp(float x) { return expf(x); }
+__device__ __forceinline__ double kfabs(double x) { return fabs(x); }
+__device__ __forceinline__ float kfabs(float x) { return fabsf(x); }
+__device__ __forceinline__ double kfmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float kfmax(float a, float b) { return fmaxf(a, b); }
+
+template <typename Real> struct Prec;
+template <> struct Prec<double> {
+    static constexpr double eps = 1.1102230246251565404e-16;  // 2^-53
+    // 53-bit uniform in [0,1) from two 32-bit words
+    static __device__ __forceinline__ double uni(uint32_t a, uint32_t b, uint32_t) {
+        return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * eps;
+    }
+};
+template <> struct Prec<float> {
+    static constexpr float eps = 5.9604644775390625e-8f;       // 2^-24
+    // 24-bit uniform in [0,1) from the high bits of the first word of the pair
+    static __device__ __forceinline__ float uni(uint32_t a, uint32_t, uint32_t) {
+        return (float)(a >> 8) * eps;
+    }
+};
+
+// ---------------------------------------------------------------- random numbers
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 products
+// with the Weyl key schedule.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                     uint32_t c2, uint32_t c3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+template <typename Real> struct Pair { Real d0, d1; };
+
+// one slot of the draw schedule: key (seed, pid), counter (step, slot, lineage)
+template <typename Real>
+__device__ __forceinline__ Pair<Real> draw(uint32_t seed, uint32_t pid, unsigned long long lin,
+                                           uint32_t s, uint32_t slot) {
+    const U4 w = philox(seed, pid, s, slot, (uint32_t)lin, (uint32_t)(lin >> 32));
+    return Pair<Real>{Prec<Real>::uni(w.x, w.y, 0u), Prec<Real>::uni(w.z, w.w, 0u)};
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014)
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+__device__ __forceinline__ unsigned long long child_lineage(unsigned long long parent, uint32_t s,
+                                                            uint32_t j) {
+    return mix64(parent ^ (kPHI64 * ((((unsigned long long)s) << 3) | (unsigned long long)(j + 1))));
+}
+
+__device__ __forceinline__ unsigned long long digest_event(unsigned long long d, uint32_t s,
+                                                           uint32_t kind, uint32_t a, uint32_t b) {
+    const unsigned long long w = ((unsigned long long)s << 32) |
+                                 ((unsigned long long)(kind & 0xFu) << 28) |
+                                 ((unsigned long long)(a & 0xFFu) << 20) |
+                                 (unsigned long long)(b & 0xFFFFFu);
+    return mix64(d ^ w);
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ unsigned rank_in(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Reserve one slot per lane with `want` among the active lanes with a single atomic.
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* ctr, bool want) {
+    const unsigned long long m = __ballot(want);
+    unsigned long long base = 0;
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        if ((int)lane_id() == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+    }
+    return base + rank_in(m);
+}
+
+// Add 1 to s_cnt[key] for every active lane, one LDS atomic per distinct key in the wave.
+__device__ __forceinline__ void wave_count(unsigned long long* s_cnt, int key) {
+    bool pending = true;
+    for (;;) {
+        const unsigned long long mp = __ballot(pending);
+        if (!mp) break;
+        const int leader = __ffsll((long long)mp) - 1;
+        const int k0 = __shfl(key, leader);
+        const unsigned long long mk = __ballot(pending && key == k0);
+        if ((int)lane_id() == leader) atomicAdd(&s_cnt[k0], (unsigned long long)__popcll(mk));
+        if (key == k0) pending = false;
+    }
+}
+
+__device__ __forceinline__ void add_u64(unsigned long long* p, unsigned long long v) {
+    atomicAdd(p, v);
+}
+__device__ __forceinline__ void add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// ---------------------------------------------------------------- state
+template <typename Real>
+struct Part {
+    Real x, y, z, u, v, w, e, vel, s_path;
+    double t_alive, t_cell, e_exc, e_bind, e_gas;
+    unsigned long long lin, dg;
+    uint32_t pid, s;
+    int32_t sp, ir, iz;
+    int64_t n_int;
+    bool alive;
+};
+
+template <typename Real>
+struct Lds {
+    unsigned long long* cnt;   // [48]
+    double* led;               // [24]
+    const int32_t* pidx;       // [2][16]
+    const int32_t* kind;       // [16]
+    const int32_t* tgt;        // [16]
+    const Real* eth;           // [16]
+    const Real* xs;            // [n_proc][n_e]
+    const Real* ngas;          // [n_z]
+    const Real* zf;            // [n_z+1]
+    const Real* rf;            // [n_r+1]
+};
+
+struct LaneCnt {
+    uint32_t step0, step1, coll0, coll1, zc0, zc1, rc0, rc1;
+};
+
+template <typename T>
+__device__ __forceinline__ T sel2(int sp, T a, T b) { return sp ? b : a; }
+
+// ---------------------------------------------------------------- tally helpers
+template <typename Real>
+__device__ __forceinline__ void flush_time(const DevJob& J, Part<Real>& p) {
+    if (p.t_cell != 0.0) {
+        add_f64(&J.dens[((size_t)p.sp * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], p.t_cell);
+        p.t_cell = 0.0;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void ev(Part<Real>& p, uint32_t kind, uint32_t a, uint32_t b,
+                                   bool on) {
+    if (on) p.dg = digest_event(p.dg, p.s, kind, a, b);
+}
+
+template <typename Real>
+__device__ void kill(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int reason) {
+    flush_time(J, p);
+    atomicAdd(&L.cnt[KARL_C_DEATH + p.sp * KARL_NREASON + reason], 1ull);
+    atomicAdd(&L.led[KARL_L_E_DEATH + p.sp * KARL_NREASON + reason], (double)p.e);
+    if (p.t_alive != 0.0) atomicAdd(&L.led[KARL_L_T_ALIVE + p.sp], p.t_alive);
+    if (p.e_exc != 0.0) atomicAdd(&L.led[KARL_L_E_EXC], p.e_exc);
+    if (p.e_bind != 0.0) atomicAdd(&L.led[KARL_L_E_BIND], p.e_bind);
+    if (p.e_gas != 0.0) atomicAdd(&L.led[KARL_L_E_GAS], p.e_gas);
+    if (J.flags & KARL_FLAG_DIGESTS) {
+        p.dg = digest_event(p.dg, p.s, 6u, (uint32_t)reason, 0u);
+        add_u64(&J.digests[p.pid], p.dg);
+    }
+    if (J.flags & KARL_FLAG_HISTORY) {
+        add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 1], (((double)p.e + p.e_exc) + p.e_bind) + p.e_gas);
+        add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 3], 1.0);
+    }
+    p.alive = false;
+}
+
+template <typename Real>
+__device__ __forceinline__ void cross_r(const DevJob& J, Part<Real>& p, LaneCnt& lc, int f, int dir) {
+    if (p.sp) ++lc.rc1; else ++lc.rc0;
+    add_u64(&J.jr[(((size_t)p.sp * (J.n_r + 1) + (size_t)f) * J.n_z + (size_t)p.iz) * 2 + (size_t)dir], 1ull);
+    ev(p, 4u, (uint32_t)dir, (uint32_t)(f * J.n_z + p.iz), (J.flags & KARL_FLAG_DIGESTS) != 0);
+}
+
+// r-cell k with rf[k] <= r < rf[k+1], clamped to 0..n_r-1, found by walking from a guess
+template <typename Real>
+__device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess) {
+    int k = guess;
+    while (k + 1 < n_r && rf[k + 1] <= r) ++k;
+    while (k > 0 && !(rf[k] <= r)) --k;
+    return k;
+}
+
+// Guiding centre from position and velocity; returns true if the orbit reaches the wall.
+// At birth the r-cell is set from the guiding-centre radius; after a collision every r-face
+// between the old and new guiding-centre radius counts as crossed.
+template <typename Real>
+__device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
+                       Real yp, bool at_birth) {
+    const Real om = (Real)sel2(p.sp, J.omega[0], J.omega[1]);
+    const Real gx = xp + p.vel * p.v / om;
+    const Real gy = yp - p.vel * p.u / om;
+    const Real rho = ksqrt(gx * gx + gy * gy);
+    const Real rl = p.vel * ksqrt(p.u * p.u + p.v * p.v) / kfabs(om);
+    p.x = gx;
+    p.y = gy;
+    p.s_path = (Real)0;
+    const int nir = r_cell(L.rf, J.n_r, rho, p.ir);
+    if (at_birth) {
+        p.ir = nir;
+    } else if (nir != p.ir) {
+        flush_time(J, p);
+        if (nir > p.ir) {
+            for (int f = p.ir + 1; f <= nir; ++f) cross_r(J, p, lc, f, 1);
+        } else {
+            for (int f = p.ir; f > nir; --f) cross_r(J, p, lc, f, 0);
+        }
+        p.ir = nir;
+    }
+    return rho + rl >= (Real)J.radius;
+}
+
+// ---------------------------------------------------------------- kinematics
+template <typename Real>
+__device__ __forceinline__ void rotate(Real u, Real v, Real w, Real mu, Real phi, Real out[3]) {
+    const Real s = ksqrt(kfmax((Real)0, (Real)1 - mu * mu));
+    Real sp, cp;
+    ksincos(phi, &sp, &cp);
+    Real a, b, c;
+    if (kfabs(w) < (Real)1 - (Real)1e-10) {
+        const Real t = ksqrt((Real)1 - w * w);
+        a = mu * u + s * (u * w * cp - v * sp) / t;
+        b = mu * v + s * (v * w * cp + u * sp) / t;
+        c = mu * w - s * t * cp;
+    } else {
+        a = s * cp;
+        b = s * sp;
+        c = (w > (Real)0) ? mu : -mu;
+    }
+    const Real n = ksqrt(a * a + b * b + c * c);
+    out[0] = a / n;
+    out[1] = b / n;
+    out[2] = c / n;
+}
+
+// thermal target velocity from two Box-Muller slots
+template <typename Real>
+__device__ void thermal(const DevJob& J, const Part<Real>& p, uint32_t sa, uint32_t sb, Real V[3]) {
+    const Real sv = (Real)J.sigma_v;
+    if (!(sv > (Real)0)) {
+        V[0] = V[1] = V[2] = (Real)0;
+        return;
+    }
+    const Pair<Real> a = draw<Real>(J.seed, p.pid, p.lin, p.s, sa);
+    const Pair<Real> b = draw<Real>(J.seed, p.pid, p.lin, p.s, sb);
+    const Real r1 = ksqrt((Real)-2 * klog(a.d0 + Prec<Real>::eps));
+    const Real r2 = ksqrt((Real)-2 * klog(b.d0 + Prec<Real>::eps));
+    const Real a1 = (Real)kTWO_PI * a.d1;
+    const Real a2 = (Real)kTWO_PI * b.d1;
+    Real s1, c1, s2, c2;
+    ksincos(a1, &s1, &c1);
+    ksincos(a2, &s2, &c2);
+    V[0] = sv * (r1 * c1);
+    V[1] = sv * (r1 * s1);
+    V[2] = sv * (r2 * c2);
+}
+
+template <typename Real>
+__device__ __forceinline__ void set_velocity(Part<Real>& p, Real m, const Real vv[3]) {
+    const Real v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
+    p.e = (Real)0.5 * m * v2 / (Real)kQE;
+    p.vel = ksqrt(v2);
+    if (p.vel > (Real)0) {
+        p.u = vv[0] / p.vel;
+        p.v = vv[1] / p.vel;
+        p.w = vv[2] / p.vel;
+    }
+}
+
+template <typename Real>
+__device__ void k_elastic(const DevJob& J, Part<Real>& p) {
+    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
+    const Real M = (Real)J.m_gas;
+    const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
+    Real V[3];
+    thermal(J, p, 2u, 3u, V);
+    const Real g[3] = {v[0] - V[0], v[1] - V[1], v[2] - V[2]};
+    const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    Real gh[3] = {(Real)0, (Real)0, (Real)1};
+    if (gm > (Real)0) {
+        gh[0] = g[0] / gm;
+        gh[1] = g[1] / gm;
+        gh[2] = g[2] / gm;
+    }
+    const Real mt = m + M;
+    const Real cm[3] = {(m * v[0] + M * V[0]) / mt, (m * v[1] + M * V[1]) / mt,
+                        (m * v[2] + M * V[2]) / mt};
+    const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
+    const Real mu = (Real)2 * q.d0 - (Real)1;
+    const Real phi = (Real)kTWO_PI * q.d1;
+    Real gn[3];
+    rotate(gh[0], gh[1], gh[2], mu, phi, gn);
+    const Real a = M / mt * gm;
+    const Real vn[3] = {cm[0] + a * gn[0], cm[1] + a * gn[1], cm[2] + a * gn[2]};
+    const Real e0 = p.e;
+    set_velocity(p, m, vn);
+    p.e_gas += (double)(e0 - p.e);
+}
+
+// Kim-Rudd BEB secondary-energy distribution (Q = 1) on w = W/B in [0,(t-1)/2]: exact
+// rejection from the positive four-term envelope, each term drawn by its closed-form inverse.
+template <typename Real>
+__device__ Real beb_sample(const DevJob& J, const Part<Real>& p, Real t, uint32_t* tries) {
+    if (!(t > (Real)1)) return (Real)0;
+    const Real tp1 = t + (Real)1;
+    const Real lt = klog(t);
+    const Real a4 = (Real)4 / (tp1 * tp1);
+    const Real it2 = (Real)1 / (t * t);
+    const Real i1 = (t - (Real)1) / tp1;
+    const Real i2 = (t - (Real)1) / (t * tp1);
+    const Real i3 = (Real)0.5 * lt * ((Real)1 - a4);
+    const Real i4 = (Real)0.5 * lt * (a4 - it2);
+    const Real c1 = i1, c2 = c1 + i2, c3 = c2 + i3, tot = c3 + i4;
+    const Real wmax = (Real)0.5 * (t - (Real)1);
+    Real w = (Real)0;
+    for (uint32_t k = 0; k < 64u; ++k) {
+        const Pair<Real> a = draw<Real>(J.seed, p.pid, p.lin, p.s, 8u + 2u * k);
+        const Pair<Real> b = draw<Real>(J.seed, p.pid, p.lin, p.s, 9u + 2u * k);
+        const Real pick = a.d0 * tot;
+        const Real u = a.d1;
+        if (pick < c1) w = (Real)1 / ((Real)1 - u * ((Real)1 - (Real)2 / tp1)) - (Real)1;
+        else if (pick < c2) w = t - (Real)1 / ((Real)1 / t + u * ((Real)2 / tp1 - (Real)1 / t));
+        else if (pick < c3) w = (Real)1 / ksqrt((Real)1 - u * ((Real)1 - a4)) - (Real)1;
+        else w = t - (Real)1 / ksqrt(it2 + u * (a4 - it2));
+        if (w < (Real)0) w = (Real)0;
+        if (w > wmax) w = wmax;
+        const Real x1 = (Real)1 / (w + (Real)1), x2 = (Real)1 / (t - w);
+        const Real env = x1 * x1 + x2 * x2 + lt * (x1 * x1 * x1 + x2 * x2 * x2);
+        const Real g = env - (x1 + x2) / tp1;
+        *tries += 1u;
+        if (b.d0 * env < g) return w;
+    }
+    return w;
+}
+
+// allowed beta shape (nonrelativistic Fermi function, massless neutrino)
+template <typename Real>
+__device__ __forceinline__ Real beta_shape(Real e, Real e0, Real z) {
+    if (!(e > (Real)0) || !(e < e0)) return (Real)0;
+    const Real wt = e + (Real)kMEC2;
+    const Real pm = ksqrt(e * (e + (Real)2 * (Real)kMEC2));
+    const Real y = (Real)kTWO_PI * (Real)kALPHA * z * wt / pm;
+    const Real q = e0 - e;
+    return ((Real)kTWO_PI * (Real)kALPHA * z * wt / ((Real)1 - kexp(-y))) * wt * q * q;
+}
+
+// ---------------------------------------------------------------- queue
+template <typename Real>
+__device__ __forceinline__ void queue_write(const GenArgs& G, unsigned long long i, Real x, Real y,
+                                           Real z, const Real d[3], Real e,
+                                           unsigned long long lin, uint32_t pid, uint32_t meta) {
+    G.qout.x[i] = (double)x;
+    G.qout.y[i] = (double)y;
+    G.qout.z[i] = (double)z;
+    G.qout.u[i] = (double)d[0];
+    G.qout.v[i] = (double)d[1];
+    G.qout.w[i] = (double)d[2];
+    G.qout.e[i] = (double)e;
+    G.qout.lin[i] = lin;
+    G.qout.pid[i] = pid;
+    G.qout.meta[i] = meta;
+}
+
+__device__ __forceinline__ uint32_t pack_meta(int sp, int ir, int iz) {
+    return (uint32_t)sp | ((uint32_t)ir << 2) | ((uint32_t)iz << 13);
+}
+
+// A product that is never transported (untracked species, or born below the cutoff) is
+// counted, logged and deleted at once, exactly as its birth would do.
+template <typename Real>
+__device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real e,
+                               unsigned long long lin, uint32_t pid, int ir, int iz, int reason) {
+    atomicAdd(&L.cnt[KARL_C_BIRTH + sp], 1ull);
+    atomicAdd(&L.cnt[KARL_C_DEATH + sp * KARL_NREASON + reason], 1ull);
+    atomicAdd(&L.led[KARL_L_E_DEATH + sp * KARL_NREASON + reason], (double)e);
+    if (J.flags & KARL_FLAG_DIGESTS) {
+        unsigned long long d = mix64(lin ^ kDIGEST0);
+        d = digest_event(d, 0u, 1u, (uint32_t)sp, (uint32_t)(ir * J.n_z + iz));
+        d = digest_event(d, 0u, 6u, (uint32_t)reason, 0u);
+        add_u64(&J.digests[pid], d);
+    }
+    if (J.flags & KARL_FLAG_HISTORY) {
+        add_f64(&J.hist[(size_t)pid * KARL_NHIST + 1], (double)e);
+        add_f64(&J.hist[(size_t)pid * KARL_NHIST + 2], 1.0);
+        add_f64(&J.hist[(size_t)pid * KARL_NHIST + 3], 1.0);
+    }
+}
+
+template <typename Real>
+__device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+                             int pi, Real xc, Real yc, uint32_t* n_redraw, uint32_t* n_beb) {
+    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
+    const Real B = L.eth[pi];
+    const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
+    Real V[3], g[3];
+    thermal(J, p, 2u, 3u, V);
+    g[0] = v[0] - V[0];
+    g[1] = v[1] - V[1];
+    g[2] = v[2] - V[2];
+    Real er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+    for (uint32_t r = 1; er < B && r <= 15u; ++r) {
+        *n_redraw += 1u;
+        thermal(J, p, 136u + 2u * r, 137u + 2u * r, V);
+        g[0] = v[0] - V[0];
+        g[1] = v[1] - V[1];
+        g[2] = v[2] - V[2];
+        er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+    }
+    if (er < B) {
+        V[0] = V[1] = V[2] = (Real)0;
+        g[0] = v[0];
+        g[1] = v[1];
+        g[2] = v[2];
+        er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+    }
+    const Real t = er / B;
+    const Real w = beb_sample(J, p, t, n_beb);
+    const Real W = w * B;
+    Real ef = er - B - W;
+    if (ef < (Real)0) ef = (Real)0;
+    const Real den = er - B;
+    Real ctf = (Real)1, cts = (Real)0;
+    if (den > (Real)0) {
+        ctf = ksqrt(ef / den);
+        cts = ksqrt(W / den);
+    }
+    const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    Real gh[3] = {(Real)0, (Real)0, (Real)1};
+    if (gm > (Real)0) {
+        gh[0] = g[0] / gm;
+        gh[1] = g[1] / gm;
+        gh[2] = g[2] / gm;
+    }
+    const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
+    const Real phi = (Real)kTWO_PI * q.d1;
+    const Real phis = phi - (Real)kPI;
+    Real df[3], ds[3];
+    rotate(gh[0], gh[1], gh[2], ctf, phi, df);
+    rotate(gh[0], gh[1], gh[2], cts, phis, ds);
+    const Real sf = ksqrt((Real)2 * ef * (Real)kQE / m);
+    const Real ss = ksqrt((Real)2 * W * (Real)kQE / m);
+    const Real vf[3] = {V[0] + sf * df[0], V[1] + sf * df[1], V[2] + sf * df[2]};
+    const Real vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
+    const Real mi = (Real)J.mass[1];
+    const Real es = (Real)0.5 * m * (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) / (Real)kQE;
+    const Real eion = (Real)0.5 * mi * (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) / (Real)kQE;
+    const Real e0 = p.e;
+    set_velocity(p, m, vf);
+    p.e_bind += (double)B;
+    p.e_gas += (double)(e0 - (p.e + es + eion + B));
+
+    // products: slow electron (slot 0) and ion (slot 1), born at the collision point
+    const unsigned long long lin_e = child_lineage(p.lin, p.s, 0u);
+    const unsigned long long lin_i = child_lineage(p.lin, p.s, 1u);
+    Real de[3] = {(Real)0, (Real)0, (Real)1};
+    const Real vsm = ksqrt(vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]);
+    if (vsm > (Real)0) {
+        de[0] = vs[0] / vsm;
+        de[1] = vs[1] / vsm;
+        de[2] = vs[2] / vsm;
+    }
+    Real di[3] = {(Real)0, (Real)0, (Real)1};
+    const Real Vm = ksqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
+    if (Vm > (Real)0) {
+        di[0] = V[0] / Vm;
+        di[1] = V[1] / Vm;
+        di[2] = V[2] / Vm;
+    }
+    bool push_e = true, push_i = true;
+    if (!J.tracked[0]) {
+        product_inline(J, L, 0, es, lin_e, p.pid, p.ir, p.iz, KARL_UNTRACKED);
+        push_e = false;
+    } else if (es < (Real)J.e_cut[0]) {
+        product_inline(J, L, 0, es, lin_e, p.pid, p.ir, p.iz, KARL_CUTOFF);
+        push_e = false;
+    }
+    if (!J.tracked[1]) {
+        product_inline(J, L, 1, eion, lin_i, p.pid, p.ir, p.iz, KARL_UNTRACKED);
+        push_i = false;
+    } else if (eion < (Real)J.e_cut[1]) {
+        product_inline(J, L, 1, eion, lin_i, p.pid, p.ir, p.iz, KARL_CUTOFF);
+        push_i = false;
+    }
+    const unsigned long long se = wave_reserve(G.qout_count, push_e);
+    const unsigned long long si = wave_reserve(G.qout_count, push_i);
+    const unsigned long long cap = (unsigned long long)G.capacity;
+    if (push_e) {
+        if (se < cap) queue_write(G, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz));
+        else atomicOr(J.status, STATUS_OVERFLOW);
+    }
+    if (push_i) {
+        if (si < cap) queue_write(G, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz));
+        else atomicOr(J.status, STATUS_OVERFLOW);
+    }
+}
+
+// ---------------------------------------------------------------- birth (Sec. 3.5)
+template <typename Real>
+__device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Real>& p,
+                      uint32_t* n_beta) {
+    p.lin = 0ull;
+    p.pid = pid;
+    if (J.source == KARL_SOURCE_BEAM) {
+        p.sp = J.beam_species;
+        p.x = (Real)J.beam_pos[0];
+        p.y = (Real)J.beam_pos[1];
+        p.z = (Real)J.beam_pos[2];
+        p.u = (Real)J.beam_dir[0];
+        p.v = (Real)J.beam_dir[1];
+        p.w = (Real)J.beam_dir[2];
+        p.e = (Real)J.beam_e;
+        p.ir = J.beam_ir;
+        p.iz = J.beam_iz;
+        return;
+    }
+    p.sp = 0;
+    const Pair<Real> q0 = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 0u);
+    const Pair<Real> q1 = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 1u);
+    const Pair<Real> q2 = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 2u);
+    const Real* zcdf = (const Real*)J.zcdf;
+    const Real wsum = zcdf[J.n_z];
+    int k;
+    Real z;
+    if (wsum > (Real)0) {
+        const Real tt = q0.d0 * wsum;
+        // first k with tt < zcdf[k+1]
+        int lo = 0, hi = J.n_z;   // answer in [lo, hi]; hi = n_z means none
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (tt < zcdf[mid + 1]) hi = mid;
+            else lo = mid + 1;
+        }
+        k = lo;
+        if (k >= J.n_z) {
+            k = J.n_z - 1;
+            while (k > 0 && !(L.ngas[k] > (Real)0)) --k;
+        }
+        z = L.zf[k] + ((tt - zcdf[k]) / L.ngas[k]) * ((Real)J.length / (Real)J.n_z);
+    } else {
+        z = q0.d0 * (Real)J.length;
+        int kk = 0;
+        for (int j = 1; j < J.n_z; ++j)
+            if (L.zf[j] <= z) kk = j;
+        k = kk;
+    }
+    const Real r = (Real)J.radius * ksqrt(q0.d1);
+    const Real al = (Real)kTWO_PI * q1.d0;
+    const Real mu = (Real)2 * q1.d1 - (Real)1;
+    const Real ph = (Real)kTWO_PI * q2.d0;
+    const Real st = ksqrt(kfmax((Real)0, (Real)1 - mu * mu));
+    Real sa, ca, sph, cph;
+    ksincos(al, &sa, &ca);
+    ksincos(ph, &sph, &cph);
+    p.x = r * ca;
+    p.y = r * sa;
+    p.z = z;
+    p.u = st * cph;
+    p.v = st * sph;
+    p.w = mu;
+    p.iz = k;
+    p.ir = r_cell(L.rf, J.n_r, r, 0);
+    Real e = (Real)0;
+    const Real e0 = (Real)J.beta_e0, bz = (Real)J.beta_z, fmax_ = (Real)J.beta_fmax;
+    for (uint32_t j = 0; j < 64u; ++j) {
+        const Pair<Real> q = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 3u + j);
+        e = e0 * (q.d0 + Prec<Real>::eps);
+        *n_beta += 1u;
+        if (q.d1 * fmax_ < beta_shape(e, e0, bz)) break;
+    }
+    p.e = e;
+}
+
+// common start of every particle (primary or secondary); returns with p.alive set
+template <typename Real>
+__device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc) {
+    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
+    p.s = 0u;
+    p.n_int = 0;
+    p.t_alive = 0.0;
+    p.t_cell = 0.0;
+    p.e_exc = p.e_bind = p.e_gas = 0.0;
+    p.s_path = (Real)0;
+    p.alive = true;
+    p.vel = (p.e > (Real)0) ? ksqrt((Real)2 * p.e * (Real)kQE / m) : (Real)0;
+    p.dg = mix64(p.lin ^ kDIGEST0);
+    atomicAdd(&L.cnt[KARL_C_BIRTH + p.sp], 1ull);
+    if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 2], 1.0);
+    ev(p, 1u, (uint32_t)p.sp, (uint32_t)(p.ir * J.n_z + p.iz), dig);
+    if (!sel2(p.sp, J.tracked[0], J.tracked[1])) { kill(J, L, p, KARL_UNTRACKED); return; }
+    if (p.e < (Real)sel2(p.sp, J.e_cut[0], J.e_cut[1])) { kill(J, L, p, KARL_CUTOFF); return; }
+    if (!(p.vel > (Real)0)) { kill(J, L, p, KARL_LIFETIME); return; }
+    if (J.gc) {
+        if (gc_set(J, L, p, lc, p.x, p.y, true)) {
+            cross_r(J, p, lc, J.n_r, 1);
+            kill(J, L, p, KARL_WALL);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- one flight segment
+template <typename Real>
+__device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+                     LaneCnt& lc, uint32_t* n_redraw, uint32_t* n_beb) {
+    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    const int sp = p.sp;
+    const Real m = (Real)sel2(sp, J.mass[0], J.mass[1]);
+    // cross sections at the current energy, rates in the current cell (eq. 1)
+    const Real exs = p.e * (Real)J.m_gas / (Real)sel2(sp, J.msum[0], J.msum[1]);
+    const Real xl = klog(exs / (Real)sel2(sp, J.xs_emin[0], J.xs_emin[1])) *
+                    (Real)sel2(sp, J.inv_dlog[0], J.inv_dlog[1]);
+    int k;
+    Real f;
+    if (!(xl > (Real)0)) {
+        k = 0;
+        f = (Real)0;
+    } else if (xl >= (Real)(J.n_e - 1)) {
+        k = J.n_e - 2;
+        f = (Real)1;
+    } else {
+        k = (int)xl;
+        f = xl - (Real)k;
+    }
+    const Real n_gas_cell = L.ngas[p.iz];
+    const Real n_ion_cell = J.n_ion_present ? (Real)J.n_ion[(size_t)p.ir * J.n_z + (size_t)p.iz] : (Real)0;
+    const int np = sel2(sp, J.nps[0], J.nps[1]);
+    const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
+    Real sum = (Real)0;
+    for (int j = 0; j < np; ++j) {
+        const int i = pidx[j];
+        Real sig = (Real)0;
+        if (!(exs < L.eth[i])) {
+            const Real* tb = L.xs + (size_t)i * J.n_e;
+            sig = tb[k] + f * (tb[k + 1] - tb[k]);
+        }
+        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+        sum += nt * sig;
+    }
+    const Pair<Real> q0 = draw<Real>(J.seed, p.pid, p.lin, p.s, 0u);
+    const Real eta = q0.d0 + Prec<Real>::eps;
+    const Real xi = q0.d1;
+    const Real inf = (Real)INFINITY;
+    const Real dist = (sum > (Real)0) ? -klog(eta) / sum : inf;
+
+    // distance to the next face of the current segment
+    Real sg = inf;
+    int which = 0;   // 1 z-face, 2 r outer, 3 r inner
+    int zface = -1;
+    if (p.w > (Real)0) {
+        zface = p.iz + 1;
+        sg = (L.zf[zface] - p.z) / p.w;
+        which = 1;
+    } else if (p.w < (Real)0) {
+        zface = p.iz;
+        sg = (L.zf[zface] - p.z) / p.w;
+        which = 1;
+    }
+    if (sg < (Real)0) sg = (Real)0;
+    if (!J.gc) {
+        const Real a = p.u * p.u + p.v * p.v;
+        if (a > (Real)0) {
+            const Real bq = p.x * p.u + p.y * p.v;
+            const Real ro = L.rf[p.ir + 1];
+            const Real cq = p.x * p.x + p.y * p.y - ro * ro;
+            const Real disc = bq * bq - a * cq;
+            Real so = (-bq + ksqrt(kfmax(disc, (Real)0))) / a;
+            if (so < (Real)0) so = (Real)0;
+            if (so < sg) { sg = so; which = 2; }
+            if (p.ir > 0 && bq < (Real)0) {
+                const Real ri = L.rf[p.ir];
+                const Real ci = p.x * p.x + p.y * p.y - ri * ri;
+                const Real di = bq * bq - a * ci;
+                if (di >= (Real)0) {
+                    Real si = (-bq - ksqrt(di)) / a;
+                    if (si < (Real)0) si = (Real)0;
+                    if (si < sg) { sg = si; which = 3; }
+                }
+            }
+        }
+    }
+    if (dist == inf && sg == inf) {
+        kill(J, L, p, KARL_LIFETIME);
+        return;
+    }
+    if (dist != dist || sum != sum) atomicOr(J.status, STATUS_NUMERIC);
+
+    const Real l = (dist < sg) ? dist : sg;
+    const Real dt = l / p.vel;
+    p.t_cell += (double)dt;
+    p.t_alive += (double)dt;
+    if (J.gc) {
+        p.z += l * p.w;
+        p.s_path += l;
+    } else {
+        p.x += l * p.u;
+        p.y += l * p.v;
+        p.z += l * p.w;
+    }
+    if (sp) ++lc.step1; else ++lc.step0;
+
+    if (dist < sg) {
+        // ---- interaction, chosen with weight sigma_i n_i (Sec. 2.1) ----
+        const Real target = xi * sum;
+        Real run = (Real)0;
+        int sel = -1, last = -1;
+        for (int j = 0; j < np; ++j) {
+            const int i = pidx[j];
+            Real sig = (Real)0;
+            if (!(exs < L.eth[i])) {
+                const Real* tb = L.xs + (size_t)i * J.n_e;
+                sig = tb[k] + f * (tb[k + 1] - tb[k]);
+            }
+            const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+            const Real rate = nt * sig;
+            run += rate;
+            if (rate > (Real)0) last = j;
+            if (sel < 0 && target < run) sel = j;
+        }
+        if (sel < 0) sel = last;
+        const int pi = pidx[sel];
+        if (sp) ++lc.coll1; else ++lc.coll0;
+        wave_count(L.cnt, KARL_C_PROC + pi);
+        p.n_int += 1;
+        ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), dig);
+        Real xc = p.x, yc = p.y;
+        if (J.gc) {
+            const Real om = (Real)sel2(sp, J.omega[0], J.omega[1]);
+            const Real al = -(om * (p.s_path / p.vel));
+            Real sa, ca;
+            ksincos(al, &sa, &ca);
+            const Real un = ca * p.u - sa * p.v;
+            const Real vn = sa * p.u + ca * p.v;
+            p.u = un;
+            p.v = vn;
+            xc = p.x - p.vel * p.v / om;
+            yc = p.y + p.vel * p.u / om;
+        }
+        bool killed = false;
+        switch (L.kind[pi]) {
+            case KARL_ELASTIC:
+                k_elastic(J, p);
+                break;
+            case KARL_EXCITATION: {
+                const Real ex = L.eth[pi];
+                p.e = p.e - ex;
+                p.vel = (p.e > (Real)0) ? ksqrt((Real)2 * p.e * (Real)kQE / m) : (Real)0;
+                p.e_exc += (double)ex;
+                break;
+            }
+            case KARL_IONIZATION:
+                k_ionization(J, L, G, p, pi, xc, yc, n_redraw, n_beb);
+                break;
+            default:
+                add_u64(&J.recomb[(size_t)p.ir * J.n_z + (size_t)p.iz], 1ull);
+                kill(J, L, p, KARL_RECOMBINED);
+                killed = true;
+                break;
+        }
+        if (!killed) {
+            if (p.e < (Real)sel2(sp, J.e_cut[0], J.e_cut[1])) kill(J, L, p, KARL_CUTOFF);
+            else if (p.n_int >= sel2(sp, J.cap[0], J.cap[1])) kill(J, L, p, KARL_CAP);
+            else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
+            else if (J.gc) {
+                if (gc_set(J, L, p, lc, xc, yc, false)) {
+                    cross_r(J, p, lc, J.n_r, 1);
+                    kill(J, L, p, KARL_WALL);
+                }
+            }
+        }
+    } else if (which == 1) {
+        // ---- z-face: current collector, spectrum plane, exit ----
+        const int fz = zface;
+        const int dir = (p.w > (Real)0) ? 1 : 0;
+        p.z = L.zf[fz];
+        flush_time(J, p);
+        if (sp) ++lc.zc1; else ++lc.zc0;
+        add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)p.ir) * (J.n_z + 1) + (size_t)fz) * 2 + (size_t)dir], 1ull);
+        ev(p, 3u, (uint32_t)dir, (uint32_t)(p.ir * (J.n_z + 1) + fz), dig);
+        const int pl = J.plane_of[fz];
+        if (pl >= 0) {
+            const double* ed = J.edges + (size_t)sp * (J.n_bins + 1);
+            const double ee = (double)p.e;
+            int bin;
+            if (ee < ed[0]) bin = 0;
+            else if (!(ee < ed[J.n_bins])) bin = J.n_bins + 1;
+            else {
+                int lo = 0, hi = J.n_bins;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (ed[mid] <= ee) lo = mid;
+                    else hi = mid;
+                }
+                bin = lo + 1;
+            }
+            add_u64(&J.spectra[(((size_t)sp * J.n_planes + (size_t)pl) * 2 + (size_t)dir) * (J.n_bins + 2) + (size_t)bin], 1ull);
+            ev(p, 5u, (uint32_t)(pl * 2 + dir), (uint32_t)bin, dig);
+        }
+        if (fz == 0) kill(J, L, p, KARL_EXIT_LOW);
+        else if (fz == J.n_z) kill(J, L, p, KARL_EXIT_HIGH);
+        else p.iz = dir ? fz : fz - 1;
+    } else {
+        // ---- r-face (straight-line transport) ----
+        const int out = (which == 2);
+        const int fr = out ? p.ir + 1 : p.ir;
+        const Real rho = ksqrt(p.x * p.x + p.y * p.y);
+        if (rho > (Real)0) {
+            const Real sc = L.rf[fr] / rho;
+            p.x = p.x * sc;
+            p.y = p.y * sc;
+        }
+        flush_time(J, p);
+        cross_r(J, p, lc, fr, out);
+        if (fr == J.n_r) kill(J, L, p, KARL_WALL);
+        else p.ir = out ? fr : fr - 1;
+    }
+    p.s += 1u;
+    if (p.alive && p.t_alive >= sel2(sp, J.lifetime[0], J.lifetime[1])) kill(J, L, p, KARL_LIFETIME);
+}
+
+// ---------------------------------------------------------------- the kernel
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void transport_kernel(const DevJob J, const GenArgs G) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    unsigned long long* s_cnt = (unsigned long long*)lds_raw;
+    double* s_led = (double*)(lds_raw + kNCnt * 8);
+    int32_t* s_pidx = (int32_t*)(lds_raw + (kNCnt + kNLed) * 8);   // [2][16] then kind[16]
+    int32_t* s_kind = s_pidx + 2 * KARL_MAX_PROC;
+    int32_t* s_tgt = s_kind + KARL_MAX_PROC;
+    Real* s_eth = (Real*)(s_tgt + KARL_MAX_PROC);
+    Real* s_xs = s_eth + KARL_MAX_PROC;
+    Real* s_ngas = s_xs + (size_t)J.n_proc * J.n_e;
+    Real* s_zf = s_ngas + J.n_z;
+    Real* s_rf = s_zf + (J.n_z + 1);
+
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kNCnt; i += blockDim.x) s_cnt[i] = 0ull;
+    for (int i = tid; i < kNLed; i += blockDim.x) s_led[i] = 0.0;
+    for (int i = tid; i < 2 * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
+    for (int i = tid; i < KARL_MAX_PROC; i += blockDim.x) {
+        s_kind[i] = J.kind[i];
+        s_tgt[i] = J.target[i];
+        s_eth[i] = (Real)J.e_th[i];
+    }
+    const Real* g_xs = (const Real*)J.xs;
+    for (int i = tid; i < J.n_proc * J.n_e; i += blockDim.x) s_xs[i] = g_xs[i];
+    const Real* g_ngas = (const Real*)J.n_gas;
+    for (int i = tid; i < J.n_z; i += blockDim.x) s_ngas[i] = g_ngas[i];
+    const Real* g_zf = (const Real*)J.zf;
+    for (int i = tid; i <= J.n_z; i += blockDim.x) s_zf[i] = g_zf[i];
+    const Real* g_rf = (const Real*)J.rf;
+    for (int i = tid; i <= J.n_r; i += blockDim.x) s_rf[i] = g_rf[i];
+    __syncthreads();
+
+    Lds<Real> L{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf};
+    LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t n_redraw = 0u, n_beb = 0u, n_beta = 0u;
+    double e_prim = 0.0;
+    Part<Real> p;
+    p.alive = false;
+    bool done = false;
+    for (;;) {
+        const bool need = !p.alive && !done;
+        if (__ballot(need)) {
+            const unsigned long long idx = wave_reserve(G.fetch, need);
+            if (need) {
+                if (idx < (unsigned long long)G.n_items) {
+                    if (G.mode == 0) {
+                        const uint32_t pid = (uint32_t)(G.pid_begin + (int64_t)idx);
+                        birth(J, L, pid, p, &n_beta);
+                        e_prim += (double)p.e;
+                        if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)pid * KARL_NHIST + 0], (double)p.e);
+                    } else {
+                        const uint32_t meta = G.qin.meta[idx];
+                        p.sp = (int32_t)(meta & 3u);
+                        p.ir = (int32_t)((meta >> 2) & 0x7FFu);
+                        p.iz = (int32_t)(meta >> 13);
+                        p.x = (Real)G.qin.x[idx];
+                        p.y = (Real)G.qin.y[idx];
+                        p.z = (Real)G.qin.z[idx];
+                        p.u = (Real)G.qin.u[idx];
+                        p.v = (Real)G.qin.v[idx];
+                        p.w = (Real)G.qin.w[idx];
+                        p.e = (Real)G.qin.e[idx];
+                        p.lin = G.qin.lin[idx];
+                        p.pid = G.qin.pid[idx];
+                    }
+                    start_particle(J, L, p, lc);
+                } else {
+                    done = true;
+                }
+            }
+        }
+        if (!__ballot(!done)) break;
+        if (p.alive) step(J, L, G, p, lc, &n_redraw, &n_beb);
+    }
+
+    // per-lane counters -> LDS -> HBM
+    atomicAdd(&s_cnt[KARL_C_STEP + 0], (unsigned long long)lc.step0);
+    atomicAdd(&s_cnt[KARL_C_STEP + 1], (unsigned long long)lc.step1);
+    atomicAdd(&s_cnt[KARL_C_COLL + 0], (unsigned long long)lc.coll0);
+    atomicAdd(&s_cnt[KARL_C_COLL + 1], (unsigned long long)lc.coll1);
+    atomicAdd(&s_cnt[KARL_C_ZCROSS + 0], (unsigned long long)lc.zc0);
+    atomicAdd(&s_cnt[KARL_C_ZCROSS + 1], (unsigned long long)lc.zc1);
+    atomicAdd(&s_cnt[KARL_C_RCROSS + 0], (unsigned long long)lc.rc0);
+    atomicAdd(&s_cnt[KARL_C_RCROSS + 1], (unsigned long long)lc.rc1);
+    atomicAdd(&s_cnt[KARL_C_TARGET_REDRAW], (unsigned long long)n_redraw);
+    atomicAdd(&s_cnt[KARL_C_BEB_TRIES], (unsigned long long)n_beb);
+    atomicAdd(&s_cnt[KARL_C_BETA_TRIES], (unsigned long long)n_beta);
+    if (e_prim != 0.0) atomicAdd(&s_led[KARL_L_E_PRIMARY], e_prim);
+    __syncthreads();
+    for (int i = tid; i < kNCnt; i += blockDim.x)
+        if (s_cnt[i]) add_u64(&J.counters[i], s_cnt[i]);
+    for (int i = tid; i < kNLed; i += blockDim.x)
+        if (s_led[i] != 0.0) add_f64(&J.ledger[i], s_led[i]);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long value) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+}  // namespace
+
+size_t lds_bytes(const DevJob& j, int precision) {
+    const size_t rs = precision == KARL_FP32 ? sizeof(float) : sizeof(double);
+    size_t b = (size_t)(kNCnt + kNLed) * 8 + (size_t)4 * KARL_MAX_PROC * sizeof(int32_t);
+    b += rs * KARL_MAX_PROC;
+    b += rs * ((size_t)j.n_proc * j.n_e + (size_t)j.n_z + (size_t)(j.n_z + 1) + (size_t)(j.n_r + 1));
+    return (b + 15) & ~(size_t)15;
+}
+
+hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, int grid, int block,
+                            size_t lds, hipStream_t s) {
+    if (precision == KARL_FP32)
+        hipLaunchKernelGGL(transport_kernel<float>, dim3(grid), dim3(block), lds, s, j, g);
+    else
+        hipLaunchKernelGGL(transport_kernel<double>, dim3(grid), dim3(block), lds, s, j, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t transport_occupancy(int precision, int block, size_t lds, int* blocks_per_cu) {
+    if (precision == KARL_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double>, block, lds);
+}
+
+}  // namespace karl

@@ -1,0 +1,262 @@
+"""ctypes binding of libkarl (include/karl.h).
+
+Argument marshalling only: every step of the transport runs in the HIP library.  PyTorch
+provides the device workspace and the stream.  If libkarl.so is missing the import fails
+loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libkarl.so")
+
+MAX_PROC = 16
+NCOUNTERS = 48
+NLEDGER = 24
+NHIST = 4
+NREASON = 8
+FP64, FP32 = 0, 1
+FLAG_DIGESTS, FLAG_HISTORY = 1, 2
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDEVICE",
+                EOVERFLOW: "KARL_EOVERFLOW", ESTATE: "KARL_ESTATE", ENUMERIC: "KARL_ENUMERIC"}
+
+# names of the entry points declared in include/karl.h
+ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
+                "karl_reset_tallies", "karl_job_stats", "karl_destroy_job", "karl_last_error"]
+
+
+class KarlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("mass", C.c_double), ("charge", C.c_double), ("e_cut", C.c_double),
+                ("lifetime", C.c_double), ("cap", C.c_int64), ("tracked", C.c_int32),
+                ("reserved0", C.c_int32), ("xs_emin", C.c_double), ("xs_emax", C.c_double),
+                ("edges", C.POINTER(C.c_double))]
+
+
+class ProcessDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
+                ("reserved0", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double))]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
+                ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
+                ("n_ion", C.POINTER(C.c_double)), ("t_gas", C.c_double), ("m_gas", C.c_double),
+                ("bz", C.c_double), ("species", SpeciesDesc * 2), ("n_proc", C.c_int32),
+                ("n_e", C.c_int32), ("proc", ProcessDesc * MAX_PROC), ("source", C.c_int32),
+                ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
+                ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
+                ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
+                ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
+                ("reserved0", C.c_int32), ("planes", C.POINTER(C.c_int32)),
+                ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
+                ("queue_capacity", C.c_int64), ("chunk", C.c_int64),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
+
+
+class Tallies(C.Structure):
+    _fields_ = [("counters", C.POINTER(C.c_int64)), ("ledger", C.POINTER(C.c_double)),
+                ("density_time", C.POINTER(C.c_double)), ("recomb", C.POINTER(C.c_int64)),
+                ("jz", C.POINTER(C.c_int64)), ("jr", C.POINTER(C.c_int64)),
+                ("spectra", C.POINTER(C.c_int64)), ("digests", C.POINTER(C.c_uint64)),
+                ("hist", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libkarl.so (built by paper_2503_10263_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        L.karl_workspace_bytes.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
+        L.karl_create_job.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_void_p)]
+        L.karl_transport.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+        L.karl_read_tallies.argtypes = [C.c_void_p, C.POINTER(Tallies), C.c_void_p]
+        L.karl_reset_tallies.argtypes = [C.c_void_p, C.c_void_p]
+        L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.karl_destroy_job.argtypes = [C.c_void_p]
+        for name in ENTRY_POINTS[:-1]:
+            getattr(L, name).restype = C.c_int32
+        L.karl_last_error.argtypes = []
+        L.karl_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != OK:
+        raise KarlError(code, lib().karl_last_error().decode(errors="replace"))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Descriptor:
+    """karl_job_desc built from a workload; keeps its host arrays alive."""
+
+    def __init__(self, w, precision: int = FP64, flags: int = 0, queue_capacity: int = 0,
+                 chunk: int = 0):
+        self.keep = []
+        d = JobDesc()
+        d.radius, d.length, d.n_r, d.n_z = w.radius, w.length, w.n_r, w.n_z
+        d.n_gas = _dptr(self._hold(w.n_gas, np.float64))
+        if w.n_ion is not None:
+            d.n_ion = _dptr(self._hold(w.n_ion, np.float64))
+        d.t_gas, d.m_gas, d.bz = w.t_gas, w.m_gas, w.bz
+        nb = len(w.species[0].edges) - 1
+        for s in range(2):
+            sp = w.species[s]
+            ds = d.species[s]
+            ds.mass, ds.charge, ds.e_cut, ds.lifetime = sp.mass, sp.charge, sp.e_cut, sp.lifetime
+            ds.cap = int(sp.cap)
+            ds.tracked = 1 if sp.tracked else 0
+            ds.xs_emin, ds.xs_emax = sp.xs_emin, sp.xs_emax
+            edges = self._hold(sp.edges, np.float64)
+            if len(edges) != nb + 1:
+                raise ValueError("both species need the same number of spectrum bins")
+            ds.edges = _dptr(edges)
+        d.n_proc = len(w.processes)
+        d.n_e = w.n_e
+        for i, p in enumerate(w.processes):
+            dp = d.proc[i]
+            dp.kind, dp.species, dp.target, dp.e_th = p.kind, p.species, p.target, p.e_th
+            xs = self._hold(p.xs, np.float64)
+            if len(xs) != w.n_e:
+                raise ValueError(f"process {i}: table has {len(xs)} nodes, expected {w.n_e}")
+            dp.xs = _dptr(xs)
+        d.source, d.beam_species = w.source, w.beam_species
+        d.beta_e0, d.beta_z, d.beta_fmax = w.beta_e0, w.beta_z, w.beta_fmax
+        d.beam_energy = w.beam_energy
+        for k in range(3):
+            d.beam_pos[k] = w.beam_pos[k]
+            d.beam_dir[k] = w.beam_dir[k]
+        d.seed = w.seed
+        d.n_bins = nb
+        planes = self._hold(w.planes, np.int32)
+        d.n_planes = len(planes)
+        d.planes = planes.ctypes.data_as(C.POINTER(C.c_int32))
+        d.n_primaries = w.n_primaries
+        d.precision = precision
+        d.flags = flags
+        d.queue_capacity = queue_capacity
+        d.chunk = chunk
+        self.d = d
+
+    def _hold(self, a, dtype):
+        arr = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+        self.keep.append(arr)
+        return arr
+
+    def workspace_bytes(self) -> int:
+        n = C.c_uint64(0)
+        check(lib().karl_workspace_bytes(C.byref(self.d), C.byref(n)))
+        return int(n.value)
+
+
+def tally_shapes(w, digests: bool, history: bool) -> Dict[str, tuple]:
+    nb = len(w.species[0].edges) - 1
+    s = {
+        "counters": ((NCOUNTERS,), np.int64), "ledger": ((NLEDGER,), np.float64),
+        "density_time": ((2, w.n_r, w.n_z), np.float64), "recomb": ((w.n_r, w.n_z), np.int64),
+        "jz": ((2, w.n_r, w.n_z + 1, 2), np.int64), "jr": ((2, w.n_r + 1, w.n_z, 2), np.int64),
+        "spectra": ((2, len(w.planes), 2, nb + 2), np.int64),
+    }
+    if digests:
+        s["digests"] = ((w.n_primaries,), np.uint64)
+    if history:
+        s["hist"] = ((w.n_primaries, NHIST), np.float64)
+    return s
+
+
+class Job:
+    """One transport job on the current HIP device (workspace allocated by torch)."""
+
+    def __init__(self, w, precision: str = "fp64", digests: bool = False, history: bool = False,
+                 queue_capacity: int = 0, chunk: int = 0, device=None):
+        import torch
+        self.w = w
+        self.precision = FP32 if precision == "fp32" else FP64
+        flags = (FLAG_DIGESTS if digests else 0) | (FLAG_HISTORY if history else 0)
+        self.digests, self.history = digests, history
+        self.desc = Descriptor(w, self.precision, flags, queue_capacity, chunk)
+        self.nbytes = self.desc.workspace_bytes()
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        self.desc.d.workspace = self.workspace.data_ptr()
+        self.desc.d.workspace_bytes = self.nbytes
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib().karl_create_job(C.byref(self.desc.d), C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+    def transport(self, pid_begin: int = 0, pid_end: Optional[int] = None, stream=None):
+        if pid_end is None:
+            pid_end = self.w.n_primaries
+        check(lib().karl_transport(self.h, int(pid_begin), int(pid_end), self._stream(stream)))
+
+    def read_tallies(self, stream=None) -> Dict[str, np.ndarray]:
+        shapes = tally_shapes(self.w, self.digests, self.history)
+        out = {k: np.zeros(shp, dt) for k, (shp, dt) in shapes.items()}
+        T = Tallies()
+        for k, arr in out.items():
+            ctype = {np.int64: C.c_int64, np.float64: C.c_double, np.uint64: C.c_uint64}[arr.dtype.type]
+            setattr(T, k, arr.ctypes.data_as(C.POINTER(ctype)))
+        check(lib().karl_read_tallies(self.h, C.byref(T), self._stream(stream)))
+        return out
+
+    def reset(self, stream=None):
+        check(lib().karl_reset_tallies(self.h, self._stream(stream)))
+
+    def stats(self) -> Dict[str, float]:
+        ms, n, g, q = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().karl_job_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
+        return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
+                "max_queue": q.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib().karl_destroy_job(self.h))
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, **kw) -> Dict[str, np.ndarray]:
+    job = Job(w, **kw)
+    try:
+        job.transport(pid_begin, pid_end)
+        return job.read_tallies()
+    finally:
+        job.close()

@@ -1,0 +1,97 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that include/karl.h
+declares, sizes workspaces and rejects invalid descriptors before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_10263_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def karl():
+    from paper_2503_10263_amd import karl as K
+    if not os.path.exists(K.LIB_PATH):
+        from paper_2503_10263_amd import build
+        build.build()
+    return K
+
+
+def declared_entry_points():
+    text = open(os.path.join(ROOT, "include", "karl.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:karl_status|const char\*)\s+(karl_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol(karl):
+    names = declared_entry_points()
+    assert len(names) >= 8
+    lib = karl.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(karl.ENTRY_POINTS) == names
+
+
+def test_workspace_bytes(karl):
+    w = W.cfg_full(n_primaries=1000)
+    d = karl.Descriptor(w, queue_capacity=1 << 20)
+    n = d.workspace_bytes()
+    # two queues of 72-byte entries dominate
+    assert 2 * (1 << 20) * 72 < n < 2 * (1 << 20) * 72 + 32 * 2**20
+    d32 = karl.Descriptor(w, precision=karl.FP32, queue_capacity=1 << 20)
+    assert d32.workspace_bytes() < n
+    dd = karl.Descriptor(w, flags=karl.FLAG_DIGESTS | karl.FLAG_HISTORY, queue_capacity=1 << 20)
+    assert dd.workspace_bytes() >= n + 2 * 1000 * (8 + 32)   # tallies and their snapshot
+
+
+def _create(karl, desc):
+    h = C.c_void_p()
+    return karl.lib().karl_create_job(C.byref(desc.d), C.byref(h))
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda d: setattr(d.d, "n_r", 0), -1),
+    (lambda d: setattr(d.d, "radius", -1.0), -1),
+    (lambda d: setattr(d.d, "n_e", 1), -1),
+    (lambda d: setattr(d.d.proc[0], "kind", 9), -1),
+    (lambda d: setattr(d.d, "precision", 7), -1),
+    (lambda d: setattr(d.d, "n_primaries", -5), -1),
+    (lambda d: setattr(d.d, "workspace", None), -1),
+])
+def test_create_rejects_invalid(karl, mutate, code):
+    w = W.cfg_tiny(n_primaries=10)
+    d = karl.Descriptor(w, queue_capacity=1024)
+    d.d.workspace = 1 << 40
+    d.d.workspace_bytes = d.workspace_bytes()
+    mutate(d)
+    assert _create(karl, d) == code
+    assert len(karl.lib().karl_last_error()) > 0
+
+
+def test_create_rejects_small_workspace(karl):
+    w = W.cfg_tiny(n_primaries=10)
+    d = karl.Descriptor(w, queue_capacity=1024)
+    d.d.workspace = 1 << 40
+    d.d.workspace_bytes = d.workspace_bytes() - 1
+    assert _create(karl, d) == karl.ENOMEM
+
+
+def test_bad_plane_and_nonfinite_density(karl):
+    w = W.cfg_tiny(n_primaries=10)
+    w.planes = [0, 5]
+    d = karl.Descriptor(w, queue_capacity=1024)
+    n = C.c_uint64()
+    assert karl.lib().karl_workspace_bytes(C.byref(d.d), C.byref(n)) == karl.EINVAL
+    w = W.cfg_tiny(n_primaries=10)
+    w.n_gas = np.array([np.nan])
+    d = karl.Descriptor(w, queue_capacity=1024)
+    assert karl.lib().karl_workspace_bytes(C.byref(d.d), C.byref(n)) == karl.EINVAL
+
+
+def test_null_job_is_an_error_not_a_crash(karl):
+    lib = karl.lib()
+    assert lib.karl_transport(None, 0, 1, None) == karl.ESTATE
+    assert lib.karl_destroy_job(None) == karl.EINVAL

@@ -65,3 +65,33 @@ def test_mix64_bijective_sample(oracle_lib):
     xs = np.random.default_rng(3).integers(0, 2**63, size=20000, dtype=np.uint64)
     ys = {lib.ko_mix64(int(x)) for x in xs}
     assert len(ys) == len(set(int(x) for x in xs))
+
+
+def _ulp_err(got, ref):
+    return abs(got - ref) / np.spacing(abs(ref)) if ref != 0 else abs(got)
+
+
+def test_log_against_libm(oracle_lib):
+    """The oracle's own logarithm stays within 2 ulp of the C library's over the ranges the
+    transport uses (eta in (0,1], energy ratios, BEB t)."""
+    rng = np.random.default_rng(17)
+    xs = np.concatenate([rng.uniform(0, 1, 20000) + 2.0**-53, 10.0 ** rng.uniform(-300, 300, 20000),
+                         1.0 + rng.uniform(-1e-6, 1e-6, 2000), [1.0, 2.0, 0.5, 2.0**-53, 1e-308]])
+    worst = max(_ulp_err(oracle_lib.log(float(x)), float(np.log(x))) for x in xs)
+    assert worst <= 2.0, worst
+    assert oracle_lib.log(1.0) == 0.0
+
+
+def test_sincos_against_libm(oracle_lib):
+    """Own sine/cosine within 2e-16 absolute of the C library's, including gyro phases of
+    1e6 rad and beyond."""
+    rng = np.random.default_rng(19)
+    xs = np.concatenate([rng.uniform(-7, 7, 20000), -(10.0 ** rng.uniform(0, 7, 20000)),
+                         10.0 ** rng.uniform(0, 8, 5000), [0.0, np.pi / 4, np.pi / 2, 1e-300]])
+    worst = 0.0
+    for x in xs:
+        s, c = oracle_lib.sincos(float(x))
+        worst = max(worst, abs(s - np.sin(x)), abs(c - np.cos(x)))
+    assert worst <= 2.5e-16, worst
+    s, c = oracle_lib.sincos(1e9)      # beyond the exact reduction: still bounded and finite
+    assert abs(s * s + c * c - 1.0) < 1e-12
