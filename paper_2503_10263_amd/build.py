@@ -23,17 +23,28 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"),
-                                     "-I", os.path.join(PKG, "csrc"), "-o", tmp] + SOURCES
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    tmp = out + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + ["-I", os.path.join(ROOT, "include"),
+                                                   "-I", os.path.join(PKG, "csrc"), "-o", tmp] + SOURCES
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
     if verbose:
         print(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build_calibration() -> str:
+    """Copy kernel of known traffic used to scale the HBM counters (FETCH_SIZE, WRITE_SIZE)."""
+    out = os.path.join(PKG, "copy_calibration")
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-o", out, os.path.join(PKG, "csrc", "copy_calibration.hip")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    return out
 
 
 if __name__ == "__main__":

@@ -39,6 +39,8 @@ constexpr int64_t kDefaultChunk = 65536;
 constexpr int64_t kMaxChunk = int64_t(1) << 26;
 constexpr size_t kMaxLds = 65536;
 
+constexpr size_t kQueueEntryBytes = 7 * 8 + 8 + 4 + 4;
+
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte offsets of every region of the caller's workspace.
@@ -92,7 +94,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.snapshot = take(t);
     L.control = take(64);
     L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
-    L.queues = take(2 * L.queue_entries * (7 * 8 + 8 + 4 + 4));
+    L.queues = take(4 * L.queue_entries * kQueueEntryBytes);
     L.total = off;
     return L;
 }
@@ -200,15 +202,17 @@ struct Job {
     char* ws = nullptr;
     Layout lay{};
     karl::DevJob dj{};
-    karl::QueueSoA q[2]{};
+    karl::QueueSoA q[2]{};      // next-generation queues (ping-pong)
+    karl::QueueSoA dq[2]{};     // deferred queues (append / drain)
     unsigned long long* fetch = nullptr;
     unsigned long long* qcount = nullptr;
     unsigned int* status = nullptr;
+    unsigned long long* dcount = nullptr;   // [2]
     size_t lds = 0;
     int max_blocks = 0;
     int64_t capacity = 0;
     int64_t chunk = 0;
-    unsigned long long* host_ctl = nullptr;   // pinned: [qcount, status]
+    unsigned long long* host_ctl = nullptr;   // pinned: [qcount, status, dcount0, dcount1]
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int64_t launches = 0, generations = 0, max_queue = 0;
@@ -365,6 +369,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.inv_dlog[s] = (double)(d->n_e - 1) / std::log(sp.xs_emax / sp.xs_emin);
         J.omega[s] = sp.charge * d->bz / sp.mass;
         J.nps[s] = 0;
+        J.uses_ion_field[s] = 0;
+        J.defer[s] = 0;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
         J.kind[i] = i < d->n_proc ? d->proc[i].kind : 0;
@@ -374,6 +380,15 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     for (int i = 0; i < d->n_proc; ++i) {
         const int s = d->proc[i].species;
         J.pidx[s][J.nps[s]++] = i;
+        if (d->proc[i].target == KARL_TARGET_ION_FIELD && d->n_ion) J.uses_ion_field[s] = 1;
+    }
+    // A species without ionization never produces secondaries: its particles can wait in the
+    // deferred queue and run together in one launch after the other generations.
+    for (int s = 0; s < 2; ++s) {
+        bool ionizes = false;
+        for (int i = 0; i < d->n_proc; ++i)
+            if (d->proc[i].species == s && d->proc[i].kind == KARL_IONIZATION) ionizes = true;
+        J.defer[s] = ionizes ? 0 : 1;
     }
     J.sigma_v = std::sqrt(kKB * d->t_gas / d->m_gas);
     J.m_gas = d->m_gas;
@@ -410,9 +425,12 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->fetch = ctl;
     j->qcount = ctl + 1;
     j->status = (unsigned int*)(ctl + 2);
+    j->dcount = ctl + 3;
     J.status = j->status;
-    j->q[0] = queue_at(w + L.queues, L.queue_entries);
-    j->q[1] = queue_at(w + L.queues + L.queue_entries * (7 * 8 + 8 + 4 + 4), L.queue_entries);
+    for (int k = 0; k < 2; ++k) {
+        j->q[k] = queue_at(w + L.queues + (size_t)k * L.queue_entries * kQueueEntryBytes, L.queue_entries);
+        j->dq[k] = queue_at(w + L.queues + (size_t)(2 + k) * L.queue_entries * kQueueEntryBytes, L.queue_entries);
+    }
 
     j->lds = karl::lds_bytes(J, d->precision);
     if (j->lds > kMaxLds)
@@ -423,7 +441,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     if (per_cu < 1) per_cu = 1;
     j->max_blocks = per_cu * prop.multiProcessorCount;
 
-    TRY_HIP(hipHostMalloc((void**)&j->host_ctl, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    TRY_HIP(hipHostMalloc((void**)&j->host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
     TRY_HIP(hipEventCreate(&j->ev0));
     TRY_HIP(hipEventCreate(&j->ev1));
     // zero tallies and control words
@@ -440,18 +458,34 @@ static karl_status run_generations(Job* j, int64_t pid_begin, int64_t n, hipStre
                                    bool* overflow, int64_t* max_gen) {
     *overflow = false;
     *max_gen = 0;
-    int mode = 0;
+    int mode = 0;                 // 0: primaries, 1: queued particles
     int64_t items = n;
-    int qin = 0;
-    while (items > 0) {
+    const karl::QueueSoA* in = &j->q[0];
+    int mo = 0;                   // main queue receiving the next generation
+    int di = 0;                   // deferred queue being appended to
+    int64_t ndef = 0;
+    HIP_CHECK(karl::launch_fill_u64(j->dcount, 2, 0ull, s));
+    for (;;) {
+        if (items == 0) {
+            if (ndef == 0) break;
+            // main generations exhausted: drain the deferred queue in one launch
+            in = &j->dq[di];
+            items = ndef;
+            mode = 1;
+            di ^= 1;
+            ndef = 0;
+            HIP_CHECK(karl::launch_fill_u64(j->dcount + di, 1, 0ull, s));
+        }
         karl::GenArgs g{};
         g.mode = mode;
         g.pid_begin = pid_begin;
         g.n_items = items;
         g.fetch = j->fetch;
-        g.qin = j->q[qin];
-        g.qout = j->q[1 - qin];
+        g.qin = *in;
+        g.qout = j->q[mo];
         g.qout_count = j->qcount;
+        g.qdef = j->dq[di];
+        g.qdef_count = j->dcount + di;
         g.capacity = j->capacity;
         HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
         int64_t blocks = (items + kBlock - 1) / kBlock;
@@ -459,7 +493,7 @@ static karl_status run_generations(Job* j, int64_t pid_begin, int64_t n, hipStre
         HIP_CHECK(hipEventRecord(j->ev0, s));
         HIP_CHECK(karl::launch_transport(j->dj, g, j->precision, (int)blocks, kBlock, j->lds, s));
         HIP_CHECK(hipEventRecord(j->ev1, s));
-        HIP_CHECK(hipMemcpyAsync(j->host_ctl, j->qcount, 2 * sizeof(unsigned long long),
+        HIP_CHECK(hipMemcpyAsync(j->host_ctl, j->qcount, 4 * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         float ms = 0.f;
@@ -469,15 +503,17 @@ static karl_status run_generations(Job* j, int64_t pid_begin, int64_t n, hipStre
         if (mode == 1) j->generations += 1;
         const unsigned long long produced = j->host_ctl[0];
         const unsigned int status = (unsigned int)(j->host_ctl[1] & 0xFFFFFFFFull);
+        ndef = (int64_t)j->host_ctl[2 + di];
         if (status & karl::STATUS_OVERFLOW) {
             *overflow = true;
             return KARL_OK;
         }
         items = (int64_t)produced;
-        if (items > *max_gen) *max_gen = items;
-        if (items > j->max_queue) j->max_queue = items;
+        *max_gen = std::max(*max_gen, std::max(items, ndef));
+        j->max_queue = std::max(j->max_queue, std::max(items, ndef));
         mode = 1;
-        qin = 1 - qin;
+        in = &j->q[mo];
+        mo ^= 1;
     }
     return KARL_OK;
 }
@@ -508,8 +544,8 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
             // undo the partial chunk and retry with half as many primaries
             HIP_CHECK(hipMemcpyAsync(tallies, snap, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
             HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
-            j->host_ctl[2] = (unsigned long long)((unsigned int)j->host_ctl[1] & ~karl::STATUS_OVERFLOW);
-            HIP_CHECK(hipMemcpyAsync(j->status, &j->host_ctl[2], sizeof(unsigned int), hipMemcpyHostToDevice, s));
+            j->host_ctl[4] = (unsigned long long)((unsigned int)j->host_ctl[1] & ~karl::STATUS_OVERFLOW);
+            HIP_CHECK(hipMemcpyAsync(j->status, &j->host_ctl[4], sizeof(unsigned int), hipMemcpyHostToDevice, s));
             HIP_CHECK(hipStreamSynchronize(s));
             if (n == 1) {
                 j->failed = true;
@@ -574,7 +610,7 @@ karl_status karl_reset_tallies(void* job, void* hip_stream) {
     HIP_CHECK(hipSetDevice(j->device));
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(karl::launch_fill_u64((unsigned long long*)(j->ws + j->lay.tallies), j->lay.tally_bytes / 8, 0ull, s));
-    HIP_CHECK(karl::launch_fill_u64(j->fetch, 3, 0ull, s));
+    HIP_CHECK(karl::launch_fill_u64(j->fetch, 5, 0ull, s));
     HIP_CHECK(hipStreamSynchronize(s));
     j->kernel_ms = 0.0;
     j->launches = j->generations = j->max_queue = 0;

@@ -31,6 +31,8 @@ struct DevJob {
     uint32_t seed;
     int32_t beam_ir, beam_iz, n_ion_present;
     int32_t nps[2];
+    int32_t uses_ion_field[2];   // a process of the species targets the ion field (and n_ion exists)
+    int32_t defer[2];            // products of this species go to the deferred queue
     int32_t tracked[2];
     int64_t cap[2];
     double mass[2], charge[2], e_cut[2], lifetime[2];
@@ -67,7 +69,9 @@ struct DevJob {
     unsigned int* status;
 };
 
-// One generation: primaries (mode 0) or the secondaries of the previous generation.
+// One generation: primaries (mode 0) or queued secondaries (mode 1).  Products go to the
+// next generation's queue, or -- for species that never produce secondaries -- to the
+// deferred queue, which is processed in one launch once the other generations are done.
 struct GenArgs {
     int32_t mode;
     int32_t pad;
@@ -77,6 +81,8 @@ struct GenArgs {
     QueueSoA qin;
     QueueSoA qout;
     unsigned long long* qout_count;
+    QueueSoA qdef;
+    unsigned long long* qdef_count;
     int64_t capacity;
 };
 

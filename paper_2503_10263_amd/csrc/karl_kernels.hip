@@ -506,19 +506,19 @@ __device__ __forceinline__ Real beta_shape(Real e, Real e0, Real z) {
 
 // ---------------------------------------------------------------- queue
 template <typename Real>
-__device__ __forceinline__ void queue_write(const GenArgs& G, unsigned long long i, Real x, Real y,
+__device__ __forceinline__ void queue_write(const QueueSoA& q, unsigned long long i, Real x, Real y,
                                            Real z, const Real d[3], Real e,
                                            unsigned long long lin, uint32_t pid, uint32_t meta) {
-    G.qout.x[i] = (double)x;
-    G.qout.y[i] = (double)y;
-    G.qout.z[i] = (double)z;
-    G.qout.u[i] = (double)d[0];
-    G.qout.v[i] = (double)d[1];
-    G.qout.w[i] = (double)d[2];
-    G.qout.e[i] = (double)e;
-    G.qout.lin[i] = lin;
-    G.qout.pid[i] = pid;
-    G.qout.meta[i] = meta;
+    q.x[i] = (double)x;
+    q.y[i] = (double)y;
+    q.z[i] = (double)z;
+    q.u[i] = (double)d[0];
+    q.v[i] = (double)d[1];
+    q.w[i] = (double)d[2];
+    q.e[i] = (double)e;
+    q.lin[i] = lin;
+    q.pid[i] = pid;
+    q.meta[i] = meta;
 }
 
 __device__ __forceinline__ uint32_t pack_meta(int sp, int ir, int iz) {
@@ -641,15 +641,18 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
         product_inline(J, L, 1, eion, lin_i, p.pid, p.ir, p.iz, KARL_CUTOFF);
         push_i = false;
     }
-    const unsigned long long se = wave_reserve(G.qout_count, push_e);
-    const unsigned long long si = wave_reserve(G.qout_count, push_i);
+    // destination queues are uniform per product slot: next generation or deferred
+    const QueueSoA& qe = J.defer[0] ? G.qdef : G.qout;
+    const QueueSoA& qi = J.defer[1] ? G.qdef : G.qout;
+    const unsigned long long se = wave_reserve(J.defer[0] ? G.qdef_count : G.qout_count, push_e);
+    const unsigned long long si = wave_reserve(J.defer[1] ? G.qdef_count : G.qout_count, push_i);
     const unsigned long long cap = (unsigned long long)G.capacity;
     if (push_e) {
-        if (se < cap) queue_write(G, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz));
+        if (se < cap) queue_write(qe, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz));
         else atomicOr(J.status, STATUS_OVERFLOW);
     }
     if (push_i) {
-        if (si < cap) queue_write(G, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz));
+        if (si < cap) queue_write(qi, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz));
         else atomicOr(J.status, STATUS_OVERFLOW);
     }
 }
@@ -782,7 +785,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         f = xl - (Real)k;
     }
     const Real n_gas_cell = L.ngas[p.iz];
-    const Real n_ion_cell = J.n_ion_present ? (Real)J.n_ion[(size_t)p.ir * J.n_z + (size_t)p.iz] : (Real)0;
+    const Real n_ion_cell = sel2(sp, J.uses_ion_field[0], J.uses_ion_field[1])
+                                ? (Real)J.n_ion[(size_t)p.ir * J.n_z + (size_t)p.iz] : (Real)0;
     const int np = sel2(sp, J.nps[0], J.nps[1]);
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
@@ -979,7 +983,10 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
 
 // ---------------------------------------------------------------- the kernel
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void transport_kernel(const DevJob J, const GenArgs G) {
+#ifndef KARL_WAVES_PER_SIMD
+#define KARL_WAVES_PER_SIMD 1
+#endif
+__global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(const DevJob J, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     unsigned long long* s_cnt = (unsigned long long*)lds_raw;
     double* s_led = (double*)(lds_raw + kNCnt * 8);
