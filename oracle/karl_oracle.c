@@ -247,6 +247,13 @@ typedef struct {
     int32_t* plane_of;   /* [n_z+1] plane index or -1 */
     double inv_dlog[2];
     double omega[2];     /* q B / m */
+    /* per-species constants of the kinematics, evaluated once */
+    double mfrac[2];     /* m / (m + M) */
+    double gfrac[2];     /* M / (m + M): also E_xs / E (centre-of-mass energy factor) */
+    double inv_emin[2];  /* 1 / first table energy */
+    double inv_om[2];    /* 1 / omega (0 without field) */
+    double e_from_v2[2]; /* E(eV) = v^2 * e_from_v2 = v^2 m / (2 e) */
+    double v2_from_e[2]; /* v^2 = E(eV) * v2_from_e = E 2 e / m */
     double sigma_v;      /* thermal target speed scale sqrt(kT/M) */
     int32_t nps[2];
     int32_t pidx[2][KO_MAX_PROC];
@@ -305,6 +312,13 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
     for (int s = 0; s < 2; ++s) {
         c->inv_dlog[s] = (double)(d->n_e - 1) / log(d->sp[s].xs_emax / d->sp[s].xs_emin);
         c->omega[s] = d->sp[s].charge * d->bz / d->sp[s].mass;
+        double mt = d->sp[s].mass + d->m_gas;
+        c->mfrac[s] = d->sp[s].mass / mt;
+        c->gfrac[s] = d->m_gas / mt;
+        c->inv_emin[s] = 1.0 / d->sp[s].xs_emin;
+        c->inv_om[s] = (c->omega[s] != 0.0) ? 1.0 / c->omega[s] : 0.0;
+        c->e_from_v2[s] = 0.5 * d->sp[s].mass / QE;
+        c->v2_from_e[s] = 2.0 * QE / d->sp[s].mass;
     }
     c->sigma_v = sqrt(KB * d->t_gas / d->m_gas);
     for (int i = 0; i < d->n_proc; ++i) {
@@ -351,7 +365,7 @@ static double xs_lookup(const ctx_t* c, int i, double exs) {
     const ko_process* pr = &d->proc[i];
     if (exs < pr->e_th) return 0.0;
     int s = pr->species;
-    double x = ko_log(exs / d->sp[s].xs_emin) * c->inv_dlog[s];
+    double x = ko_log(exs * c->inv_emin[s]) * c->inv_dlog[s];
     int k;
     double f;
     if (!(x > 0.0)) {
@@ -369,9 +383,7 @@ static double xs_lookup(const ctx_t* c, int i, double exs) {
 }
 
 static void eval_sigmas(const ctx_t* c, part_t* p) {
-    const ko_desc* d = c->d;
-    double m = d->sp[p->sp].mass;
-    double exs = p->e * d->m_gas / (m + d->m_gas);
+    double exs = p->e * c->gfrac[p->sp];
     for (int j = 0; j < c->nps[p->sp]; ++j) p->sig[j] = xs_lookup(c, c->pidx[p->sp][j], exs);
     p->e_rates = p->e;
 }
@@ -423,11 +435,11 @@ static void cross_r(ctx_t* c, part_t* p, int f, int dir) {
    r-face between the old and the new guiding-centre radius is counted as crossed. */
 static int gc_set(ctx_t* c, part_t* p, double xp, double yp, int at_birth) {
     const ko_desc* d = c->d;
-    double om = c->omega[p->sp];
-    double gx = xp + p->vel * p->v / om;
-    double gy = yp - p->vel * p->u / om;
+    double iom = c->inv_om[p->sp];
+    double gx = xp + (p->vel * p->v) * iom;
+    double gy = yp - (p->vel * p->u) * iom;
     double rho = sqrt(gx * gx + gy * gy);
-    double rl = p->vel * sqrt(p->u * p->u + p->v * p->v) / fabs(om);
+    double rl = (p->vel * sqrt(p->u * p->u + p->v * p->v)) * fabs(iom);
     p->x = gx;
     p->y = gy;
     p->s_path = 0.0;
@@ -456,18 +468,19 @@ static void rotate(double u, double v, double w, double mu, double phi, double o
     double a, b, cc;
     if (fabs(w) < 1.0 - 1e-10) {
         double t = sqrt(1.0 - w * w);
-        a = mu * u + s * (u * w * cp - v * sp) / t;
-        b = mu * v + s * (v * w * cp + u * sp) / t;
+        double it = 1.0 / t;
+        a = mu * u + s * (u * w * cp - v * sp) * it;
+        b = mu * v + s * (v * w * cp + u * sp) * it;
         cc = mu * w - s * t * cp;
     } else {
         a = s * cp;
         b = s * sp;
         cc = (w > 0.0) ? mu : -mu;
     }
-    double n = sqrt(a * a + b * b + cc * cc);
-    out[0] = a / n;
-    out[1] = b / n;
-    out[2] = cc / n;
+    double in = 1.0 / sqrt(a * a + b * b + cc * cc);
+    out[0] = a * in;
+    out[1] = b * in;
+    out[2] = cc * in;
 }
 
 /* thermal target velocity from two Box-Muller slots */
@@ -490,20 +503,21 @@ static void thermal(const ctx_t* c, const part_t* p, uint32_t sa, uint32_t sb, d
     V[2] = c->sigma_v * (r2 * c2);
 }
 
-static void set_velocity(part_t* p, double m, const double vv[3]) {
+static void set_velocity(part_t* p, double e_from_v2, const double vv[3]) {
     double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
-    p->e = 0.5 * m * v2 / QE;
+    p->e = v2 * e_from_v2;
     p->vel = sqrt(v2);
     if (p->vel > 0.0) {
-        p->u = vv[0] / p->vel;
-        p->v = vv[1] / p->vel;
-        p->w = vv[2] / p->vel;
+        double iv = 1.0 / p->vel;
+        p->u = vv[0] * iv;
+        p->v = vv[1] * iv;
+        p->w = vv[2] * iv;
     }
 }
 
 static void k_elastic(ctx_t* c, part_t* p, double* gas_out) {
     const ko_desc* d = c->d;
-    double m = d->sp[p->sp].mass, M = d->m_gas;
+    const int s = p->sp;
     double v[3] = {p->vel * p->u, p->vel * p->v, p->vel * p->w};
     double V[3];
     thermal(c, p, 2, 3, V);
@@ -511,21 +525,23 @@ static void k_elastic(ctx_t* c, part_t* p, double* gas_out) {
     double gm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     double gh[3] = {0.0, 0.0, 1.0};
     if (gm > 0.0) {
-        gh[0] = g[0] / gm;
-        gh[1] = g[1] / gm;
-        gh[2] = g[2] / gm;
+        double ig = 1.0 / gm;
+        gh[0] = g[0] * ig;
+        gh[1] = g[1] * ig;
+        gh[2] = g[2] * ig;
     }
-    double mt = m + M;
-    double cm[3] = {(m * v[0] + M * V[0]) / mt, (m * v[1] + M * V[1]) / mt, (m * v[2] + M * V[2]) / mt};
+    /* centre-of-mass velocity (m v + M V)/(m + M) */
+    double mf = c->mfrac[s], gf = c->gfrac[s];
+    double cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     pair_t q = draw(d->seed, p->pid, p->lineage, p->s, 1);
     double mu = 2.0 * q.d0 - 1.0;
     double phi = TWO_PI * q.d1;
     double gn[3];
     rotate(gh[0], gh[1], gh[2], mu, phi, gn);
-    double a = M / mt * gm;
+    double a = gf * gm;
     double vn[3] = {cm[0] + a * gn[0], cm[1] + a * gn[1], cm[2] + a * gn[2]};
     double e0 = p->e;
-    set_velocity(p, m, vn);
+    set_velocity(p, c->e_from_v2[s], vn);
     *gas_out = e0 - p->e;
 }
 
@@ -572,23 +588,23 @@ typedef struct {
 
 static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, products_t* out) {
     const ko_desc* d = c->d;
-    double m = d->sp[p->sp].mass;
+    const double ef2 = c->e_from_v2[p->sp], v2e = c->v2_from_e[p->sp];
     double B = d->proc[pi].e_th;
     double v[3] = {p->vel * p->u, p->vel * p->v, p->vel * p->w};
     double V[3], g[3], er;
     thermal(c, p, 2, 3, V);
     g[0] = v[0] - V[0]; g[1] = v[1] - V[1]; g[2] = v[2] - V[2];
-    er = 0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / QE;
+    er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     for (uint32_t r = 1; er < B && r <= 15; ++r) {
         c->t->counters[KO_C_TARGET_REDRAW] += 1;
         thermal(c, p, 136u + 2u * r, 137u + 2u * r, V);
         g[0] = v[0] - V[0]; g[1] = v[1] - V[1]; g[2] = v[2] - V[2];
-        er = 0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / QE;
+        er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     if (er < B) {
         V[0] = V[1] = V[2] = 0.0;
         g[0] = v[0]; g[1] = v[1]; g[2] = v[2];
-        er = 0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / QE;
+        er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     double t = er / B;
     double w = beb_sample(c, p, t, &c->t->counters[KO_C_BEB_TRIES]);
@@ -604,9 +620,10 @@ static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, prod
     double gm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     double gh[3] = {0.0, 0.0, 1.0};
     if (gm > 0.0) {
-        gh[0] = g[0] / gm;
-        gh[1] = g[1] / gm;
-        gh[2] = g[2] / gm;
+        double ig = 1.0 / gm;
+        gh[0] = g[0] * ig;
+        gh[1] = g[1] * ig;
+        gh[2] = g[2] * ig;
     }
     pair_t q = draw(d->seed, p->pid, p->lineage, p->s, 1);
     double phi = TWO_PI * q.d1;
@@ -614,15 +631,14 @@ static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, prod
     double df[3], ds[3];
     rotate(gh[0], gh[1], gh[2], ctf, phi, df);
     rotate(gh[0], gh[1], gh[2], cts, phis, ds);
-    double sf = sqrt(2.0 * ef * QE / m);
-    double ss = sqrt(2.0 * W * QE / m);
+    double sf = sqrt(ef * v2e);
+    double ss = sqrt(W * v2e);
     double vf[3] = {V[0] + sf * df[0], V[1] + sf * df[1], V[2] + sf * df[2]};
     double vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
-    double mi = d->sp[1].mass;
-    double es = 0.5 * m * (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) / QE;
-    double eion = 0.5 * mi * (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) / QE;
+    double es = (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) * ef2;
+    double eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * c->e_from_v2[1];
     double e0 = p->e;
-    set_velocity(p, m, vf);
+    set_velocity(p, ef2, vf);
     out->gas = e0 - (p->e + es + eion + B);
     out->w = w;
     /* slow electron (product slot 0) and ion (product slot 1) */
@@ -630,14 +646,14 @@ static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, prod
     seed_t* se = &out->s[0];
     se->x = xc; se->y = yc; se->z = p->z;
     double vsm = sqrt(vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]);
-    if (vsm > 0.0) { se->u = vs[0] / vsm; se->v = vs[1] / vsm; se->w = vs[2] / vsm; }
+    if (vsm > 0.0) { double iv = 1.0 / vsm; se->u = vs[0] * iv; se->v = vs[1] * iv; se->w = vs[2] * iv; }
     else { se->u = 0.0; se->v = 0.0; se->w = 1.0; }
     se->e = es; se->sp = 0; se->ir = p->ir; se->iz = p->iz;
     se->lineage = child_lineage(p->lineage, p->s, 0);
     seed_t* si = &out->s[1];
     si->x = xc; si->y = yc; si->z = p->z;
     double Vm = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
-    if (Vm > 0.0) { si->u = V[0] / Vm; si->v = V[1] / Vm; si->w = V[2] / Vm; }
+    if (Vm > 0.0) { double iv = 1.0 / Vm; si->u = V[0] * iv; si->v = V[1] * iv; si->w = V[2] * iv; }
     else { si->u = 0.0; si->v = 0.0; si->w = 1.0; }
     si->e = eion; si->sp = 1; si->ir = p->ir; si->iz = p->iz;
     si->lineage = child_lineage(p->lineage, p->s, 1);
@@ -656,11 +672,10 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
     p->pid = pid; p->s = 0; p->lineage = b->lineage;
     p->x = b->x; p->y = b->y; p->z = b->z;
     p->u = b->u; p->v = b->v; p->w = b->w; p->e = b->e;
-    p->vel = (b->e > 0.0) ? sqrt(2.0 * b->e * QE / d->sp[b->sp].mass) : 0.0;
+    p->vel = (b->e > 0.0) ? sqrt(b->e * c->v2_from_e[b->sp]) : 0.0;
     p->e_rates = -1.0;
     p->dg = ko_mix64(p->lineage ^ DIGEST0);
     const ko_species* S = &d->sp[p->sp];
-    double mass = S->mass;
 
     T->counters[KO_C_BIRTH + p->sp] += 1;
     hist_add(c, p, 2, 1.0);
@@ -766,7 +781,7 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
             ev(p, 2, (uint32_t)pi, (uint32_t)(p->ir * d->n_z + p->iz));
             double xc = p->x, yc = p->y;
             if (c->gc) {
-                double om = c->omega[p->sp];
+                double om = c->omega[p->sp], iom = c->inv_om[p->sp];
                 double al = -(om * (p->s_path / p->vel));
                 double sa, ca;
                 ko_sincos(al, &sa, &ca);
@@ -774,8 +789,8 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
                 double vn = sa * p->u + ca * p->v;
                 p->u = un;
                 p->v = vn;
-                xc = p->x - p->vel * p->v / om;
-                yc = p->y + p->vel * p->u / om;
+                xc = p->x - (p->vel * p->v) * iom;
+                yc = p->y + (p->vel * p->u) * iom;
             }
             int killed = 0;
             if (pr->kind == KO_ELASTIC) {
@@ -784,7 +799,7 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
                 p->e_gas += gas;
             } else if (pr->kind == KO_EXCITATION) {
                 p->e = p->e - pr->e_th;
-                p->vel = (p->e > 0.0) ? sqrt(2.0 * p->e * QE / mass) : 0.0;
+                p->vel = (p->e > 0.0) ? sqrt(p->e * c->v2_from_e[p->sp]) : 0.0;
                 p->e_exc += pr->e_th;
             } else if (pr->kind == KO_IONIZATION) {
                 products_t out;
@@ -965,7 +980,7 @@ int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, 
     P.sp = d->proc[proc].species;
     P.pid = (uint32_t)pid; P.s = s; P.lineage = lineage; P.alive = 1;
     P.u = dir[0]; P.v = dir[1]; P.w = dir[2]; P.e = e;
-    P.vel = sqrt(2.0 * e * QE / d->sp[P.sp].mass);
+    P.vel = sqrt(e * c.v2_from_e[P.sp]);
     for (int k = 0; k < 16; ++k) out[k] = 0.0;
     const ko_process* pr = &d->proc[proc];
     if (pr->kind == KO_ELASTIC) {

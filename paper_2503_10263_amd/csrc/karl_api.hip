@@ -32,6 +32,7 @@ karl_status fail(karl_status code, const char* fmt, ...) {
     } while (0)
 
 constexpr double kKB = 1.380649e-23;
+constexpr double kQE = 1.602176634e-19;
 constexpr size_t kAlign = 256;
 constexpr int kBlock = 256;
 constexpr int64_t kDefaultCapacity = int64_t(1) << 22;
@@ -368,6 +369,13 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.xs_emin[s] = sp.xs_emin;
         J.inv_dlog[s] = (double)(d->n_e - 1) / std::log(sp.xs_emax / sp.xs_emin);
         J.omega[s] = sp.charge * d->bz / sp.mass;
+        const double mt = sp.mass + d->m_gas;
+        J.mfrac[s] = sp.mass / mt;
+        J.gfrac[s] = d->m_gas / mt;
+        J.inv_emin[s] = 1.0 / sp.xs_emin;
+        J.inv_om[s] = (J.omega[s] != 0.0) ? 1.0 / J.omega[s] : 0.0;
+        J.e_from_v2[s] = 0.5 * sp.mass / kQE;
+        J.v2_from_e[s] = 2.0 * kQE / sp.mass;
         J.nps[s] = 0;
         J.uses_ion_field[s] = 0;
         J.defer[s] = 0;

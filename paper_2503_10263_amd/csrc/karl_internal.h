@@ -39,6 +39,12 @@ struct DevJob {
     double msum[2];        // mass + m_gas
     double xs_emin[2], inv_dlog[2];
     double omega[2];       // charge * bz / mass
+    double mfrac[2];       // mass / (mass + m_gas)
+    double gfrac[2];       // m_gas / (mass + m_gas), also E_xs / E
+    double inv_emin[2];    // 1 / xs_emin
+    double inv_om[2];      // 1 / omega (0 without field)
+    double e_from_v2[2];   // E(eV) = v^2 * e_from_v2
+    double v2_from_e[2];   // v^2 = E(eV) * v2_from_e
     double sigma_v;        // sqrt(k T / m_gas)
     double m_gas;
     double beta_e0, beta_z, beta_fmax;

@@ -347,11 +347,11 @@ __device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess
 template <typename Real>
 __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
                        Real yp, bool at_birth) {
-    const Real om = (Real)sel2(p.sp, J.omega[0], J.omega[1]);
-    const Real gx = xp + p.vel * p.v / om;
-    const Real gy = yp - p.vel * p.u / om;
+    const Real iom = (Real)sel2(p.sp, J.inv_om[0], J.inv_om[1]);
+    const Real gx = xp + (p.vel * p.v) * iom;
+    const Real gy = yp - (p.vel * p.u) * iom;
     const Real rho = ksqrt(gx * gx + gy * gy);
-    const Real rl = p.vel * ksqrt(p.u * p.u + p.v * p.v) / kfabs(om);
+    const Real rl = (p.vel * ksqrt(p.u * p.u + p.v * p.v)) * kfabs(iom);
     p.x = gx;
     p.y = gy;
     p.s_path = (Real)0;
@@ -379,18 +379,19 @@ __device__ __forceinline__ void rotate(Real u, Real v, Real w, Real mu, Real phi
     Real a, b, c;
     if (kfabs(w) < (Real)1 - (Real)1e-10) {
         const Real t = ksqrt((Real)1 - w * w);
-        a = mu * u + s * (u * w * cp - v * sp) / t;
-        b = mu * v + s * (v * w * cp + u * sp) / t;
+        const Real it = (Real)1 / t;
+        a = mu * u + s * (u * w * cp - v * sp) * it;
+        b = mu * v + s * (v * w * cp + u * sp) * it;
         c = mu * w - s * t * cp;
     } else {
         a = s * cp;
         b = s * sp;
         c = (w > (Real)0) ? mu : -mu;
     }
-    const Real n = ksqrt(a * a + b * b + c * c);
-    out[0] = a / n;
-    out[1] = b / n;
-    out[2] = c / n;
+    const Real in = (Real)1 / ksqrt(a * a + b * b + c * c);
+    out[0] = a * in;
+    out[1] = b * in;
+    out[2] = c * in;
 }
 
 // thermal target velocity from two Box-Muller slots
@@ -416,21 +417,21 @@ __device__ void thermal(const DevJob& J, const Part<Real>& p, uint32_t sa, uint3
 }
 
 template <typename Real>
-__device__ __forceinline__ void set_velocity(Part<Real>& p, Real m, const Real vv[3]) {
+__device__ __forceinline__ void set_velocity(Part<Real>& p, Real e_from_v2, const Real vv[3]) {
     const Real v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
-    p.e = (Real)0.5 * m * v2 / (Real)kQE;
+    p.e = v2 * e_from_v2;
     p.vel = ksqrt(v2);
     if (p.vel > (Real)0) {
-        p.u = vv[0] / p.vel;
-        p.v = vv[1] / p.vel;
-        p.w = vv[2] / p.vel;
+        const Real iv = (Real)1 / p.vel;
+        p.u = vv[0] * iv;
+        p.v = vv[1] * iv;
+        p.w = vv[2] * iv;
     }
 }
 
 template <typename Real>
 __device__ void k_elastic(const DevJob& J, Part<Real>& p) {
-    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
-    const Real M = (Real)J.m_gas;
+    const int s = p.sp;
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     Real V[3];
     thermal(J, p, 2u, 3u, V);
@@ -438,22 +439,24 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p) {
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     Real gh[3] = {(Real)0, (Real)0, (Real)1};
     if (gm > (Real)0) {
-        gh[0] = g[0] / gm;
-        gh[1] = g[1] / gm;
-        gh[2] = g[2] / gm;
+        const Real ig = (Real)1 / gm;
+        gh[0] = g[0] * ig;
+        gh[1] = g[1] * ig;
+        gh[2] = g[2] * ig;
     }
-    const Real mt = m + M;
-    const Real cm[3] = {(m * v[0] + M * V[0]) / mt, (m * v[1] + M * V[1]) / mt,
-                        (m * v[2] + M * V[2]) / mt};
+    // centre-of-mass velocity (m v + M V)/(m + M)
+    const Real mf = (Real)sel2(s, J.mfrac[0], J.mfrac[1]);
+    const Real gf = (Real)sel2(s, J.gfrac[0], J.gfrac[1]);
+    const Real cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
     const Real mu = (Real)2 * q.d0 - (Real)1;
     const Real phi = (Real)kTWO_PI * q.d1;
     Real gn[3];
     rotate(gh[0], gh[1], gh[2], mu, phi, gn);
-    const Real a = M / mt * gm;
+    const Real a = gf * gm;
     const Real vn[3] = {cm[0] + a * gn[0], cm[1] + a * gn[1], cm[2] + a * gn[2]};
     const Real e0 = p.e;
-    set_velocity(p, m, vn);
+    set_velocity(p, (Real)sel2(s, J.e_from_v2[0], J.e_from_v2[1]), vn);
     p.e_gas += (double)(e0 - p.e);
 }
 
@@ -549,7 +552,8 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
 template <typename Real>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                              int pi, Real xc, Real yc, uint32_t* n_redraw, uint32_t* n_beb) {
-    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
+    const Real ef2 = (Real)sel2(p.sp, J.e_from_v2[0], J.e_from_v2[1]);
+    const Real v2e = (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1]);
     const Real B = L.eth[pi];
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     Real V[3], g[3];
@@ -557,21 +561,21 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     g[0] = v[0] - V[0];
     g[1] = v[1] - V[1];
     g[2] = v[2] - V[2];
-    Real er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+    Real er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     for (uint32_t r = 1; er < B && r <= 15u; ++r) {
         *n_redraw += 1u;
         thermal(J, p, 136u + 2u * r, 137u + 2u * r, V);
         g[0] = v[0] - V[0];
         g[1] = v[1] - V[1];
         g[2] = v[2] - V[2];
-        er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+        er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     if (er < B) {
         V[0] = V[1] = V[2] = (Real)0;
         g[0] = v[0];
         g[1] = v[1];
         g[2] = v[2];
-        er = (Real)0.5 * m * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (Real)kQE;
+        er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     const Real t = er / B;
     const Real w = beb_sample(J, p, t, n_beb);
@@ -587,9 +591,10 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     Real gh[3] = {(Real)0, (Real)0, (Real)1};
     if (gm > (Real)0) {
-        gh[0] = g[0] / gm;
-        gh[1] = g[1] / gm;
-        gh[2] = g[2] / gm;
+        const Real ig = (Real)1 / gm;
+        gh[0] = g[0] * ig;
+        gh[1] = g[1] * ig;
+        gh[2] = g[2] * ig;
     }
     const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
     const Real phi = (Real)kTWO_PI * q.d1;
@@ -597,15 +602,14 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     Real df[3], ds[3];
     rotate(gh[0], gh[1], gh[2], ctf, phi, df);
     rotate(gh[0], gh[1], gh[2], cts, phis, ds);
-    const Real sf = ksqrt((Real)2 * ef * (Real)kQE / m);
-    const Real ss = ksqrt((Real)2 * W * (Real)kQE / m);
+    const Real sf = ksqrt(ef * v2e);
+    const Real ss = ksqrt(W * v2e);
     const Real vf[3] = {V[0] + sf * df[0], V[1] + sf * df[1], V[2] + sf * df[2]};
     const Real vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
-    const Real mi = (Real)J.mass[1];
-    const Real es = (Real)0.5 * m * (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) / (Real)kQE;
-    const Real eion = (Real)0.5 * mi * (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) / (Real)kQE;
+    const Real es = (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) * ef2;
+    const Real eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * (Real)J.e_from_v2[1];
     const Real e0 = p.e;
-    set_velocity(p, m, vf);
+    set_velocity(p, ef2, vf);
     p.e_bind += (double)B;
     p.e_gas += (double)(e0 - (p.e + es + eion + B));
 
@@ -615,16 +619,18 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     Real de[3] = {(Real)0, (Real)0, (Real)1};
     const Real vsm = ksqrt(vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]);
     if (vsm > (Real)0) {
-        de[0] = vs[0] / vsm;
-        de[1] = vs[1] / vsm;
-        de[2] = vs[2] / vsm;
+        const Real iv = (Real)1 / vsm;
+        de[0] = vs[0] * iv;
+        de[1] = vs[1] * iv;
+        de[2] = vs[2] * iv;
     }
     Real di[3] = {(Real)0, (Real)0, (Real)1};
     const Real Vm = ksqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
     if (Vm > (Real)0) {
-        di[0] = V[0] / Vm;
-        di[1] = V[1] / Vm;
-        di[2] = V[2] / Vm;
+        const Real iv = (Real)1 / Vm;
+        di[0] = V[0] * iv;
+        di[1] = V[1] * iv;
+        di[2] = V[2] * iv;
     }
     bool push_e = true, push_i = true;
     if (!J.tracked[0]) {
@@ -737,7 +743,6 @@ __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Re
 template <typename Real>
 __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
-    const Real m = (Real)sel2(p.sp, J.mass[0], J.mass[1]);
     p.s = 0u;
     p.n_int = 0;
     p.t_alive = 0.0;
@@ -745,7 +750,7 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     p.e_exc = p.e_bind = p.e_gas = 0.0;
     p.s_path = (Real)0;
     p.alive = true;
-    p.vel = (p.e > (Real)0) ? ksqrt((Real)2 * p.e * (Real)kQE / m) : (Real)0;
+    p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1])) : (Real)0;
     p.dg = mix64(p.lin ^ kDIGEST0);
     atomicAdd(&L.cnt[KARL_C_BIRTH + p.sp], 1ull);
     if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 2], 1.0);
@@ -767,10 +772,9 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                      LaneCnt& lc, uint32_t* n_redraw, uint32_t* n_beb) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     const int sp = p.sp;
-    const Real m = (Real)sel2(sp, J.mass[0], J.mass[1]);
     // cross sections at the current energy, rates in the current cell (eq. 1)
-    const Real exs = p.e * (Real)J.m_gas / (Real)sel2(sp, J.msum[0], J.msum[1]);
-    const Real xl = klog(exs / (Real)sel2(sp, J.xs_emin[0], J.xs_emin[1])) *
+    const Real exs = p.e * (Real)sel2(sp, J.gfrac[0], J.gfrac[1]);
+    const Real xl = klog(exs * (Real)sel2(sp, J.inv_emin[0], J.inv_emin[1])) *
                     (Real)sel2(sp, J.inv_dlog[0], J.inv_dlog[1]);
     int k;
     Real f;
@@ -889,6 +893,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         Real xc = p.x, yc = p.y;
         if (J.gc) {
             const Real om = (Real)sel2(sp, J.omega[0], J.omega[1]);
+            const Real iom = (Real)sel2(sp, J.inv_om[0], J.inv_om[1]);
             const Real al = -(om * (p.s_path / p.vel));
             Real sa, ca;
             ksincos(al, &sa, &ca);
@@ -896,8 +901,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             const Real vn = sa * p.u + ca * p.v;
             p.u = un;
             p.v = vn;
-            xc = p.x - p.vel * p.v / om;
-            yc = p.y + p.vel * p.u / om;
+            xc = p.x - (p.vel * p.v) * iom;
+            yc = p.y + (p.vel * p.u) * iom;
         }
         bool killed = false;
         switch (L.kind[pi]) {
@@ -907,7 +912,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             case KARL_EXCITATION: {
                 const Real ex = L.eth[pi];
                 p.e = p.e - ex;
-                p.vel = (p.e > (Real)0) ? ksqrt((Real)2 * p.e * (Real)kQE / m) : (Real)0;
+                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)sel2(sp, J.v2_from_e[0], J.v2_from_e[1])) : (Real)0;
                 p.e_exc += (double)ex;
                 break;
             }
