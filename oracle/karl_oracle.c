@@ -24,7 +24,7 @@
  *     E_i^new, phi_e = phi_i - pi, ion given the target velocity; recombination logs one
  *     deletion in the target field and removes the particle.
  *   - current collection N+ / N- through faces (Sec. 2.3), spectra at planes.
- *   - injector with the allowed beta spectrum drawn by rejection (Sec. 3.5, 3.7).
+ *   - injector with the allowed beta spectrum drawn by rejection (Sec. 3.5; Sec. 3.8 "Velocity distribution").
  */
 #include "karl_oracle.h"
 
@@ -208,7 +208,7 @@ static uint64_t digest_event(uint64_t d, uint32_t s, uint32_t kind, uint32_t a, 
 }
 
 /* ------------------------------------------------------------------ */
-/* allowed beta spectrum (Sec. 3.7 "TritiumBetaDecay")                */
+/* allowed beta spectrum (Sec. 3.8, TritiumBetaDecay)               */
 /* ------------------------------------------------------------------ */
 double ko_beta_shape(double e, double e0, double z) {
     if (!(e > 0.0) || !(e < e0)) return 0.0;

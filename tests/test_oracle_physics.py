@@ -173,7 +173,7 @@ def test_excitation_density_profile(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
-# beta spectrum (Sec. 3.7, TritiumBetaDecay) and injection
+# beta spectrum (Sec. 3.8 "Velocity distribution", TritiumBetaDecay) and injection (Sec. 3.5)
 # ---------------------------------------------------------------------------
 def test_beta_shape_physics(oracle_lib):
     e0 = W.BETA_E0
