@@ -169,7 +169,18 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
    job's sticky device status (KARL_EOVERFLOW, KARL_ENUMERIC) if one was raised. */
 karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream);
 
-/* Zero the tallies. */
+/* Normalised fields (S12 readout) from the tallies of all primaries transported since creation
+   or the last reset, N_prim: the simulated time is t_sim = N_prim / activity (eq. 4, activity
+   in decays per second); density[species][r][z] = (time spent in the segment)/(t_sim V) minus,
+   for the ion species, the recombinations in the segment per volume (eq. 3); jz_current
+   [species][r][z-face] and jr_current[species][r-face][z] = (N+ - N-)/(A t_sim) through the
+   face (current collection, Sec. 2.3), in particles per m^2 per s; A of r-face 0 is zero and
+   its current is reported as 0.  Sizes 2*n_r*n_z, 2*n_r*(n_z+1), 2*(n_r+1)*n_z doubles; NULL
+   pointers are skipped.  KARL_ESTATE if nothing was transported. */
+karl_status karl_read_fields(void* job, double activity, double* density, double* jz_current,
+                             double* jr_current, void* hip_stream);
+
+/* Zero the tallies and the count of transported primaries. */
 karl_status karl_reset_tallies(void* job, void* hip_stream);
 
 /* Timing of the transport kernels since creation or the last reset, measured with HIP

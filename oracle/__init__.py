@@ -85,6 +85,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.ko_run.argtypes = [C.POINTER(_Desc), C.c_int64, C.c_int64, C.POINTER(_Tallies)]
         L.ko_run.restype = C.c_int
+        L.ko_fields.argtypes = [C.POINTER(_Desc), C.POINTER(_Tallies), C.c_double, C.c_double,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ko_fields.restype = C.c_int
         L.ko_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
         L.ko_philox.restype = None
         L.ko_u53.argtypes = [C.c_uint32, C.c_uint32]
@@ -224,6 +227,31 @@ def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, digests: bool = Fa
     if rc != 0:
         raise ValueError(f"oracle rejected the job (rc={rc})")
     return t
+
+
+def _tallies_struct(t):
+    T = _Tallies()
+    T.counters = t["counters"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.ledger = _dptr(t["ledger"])
+    T.density_time = _dptr(t["density_time"])
+    T.recomb = t["recomb"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.jz = t["jz"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.jr = t["jr"].ctypes.data_as(C.POINTER(C.c_int64))
+    T.spectra = t["spectra"].ctypes.data_as(C.POINTER(C.c_int64))
+    return T
+
+
+def fields(w, t, n_prim: float, activity: float):
+    """Normalised densities and currents from oracle tallies `t` (eqs. 3-5)."""
+    D = Desc(w)
+    dens = np.zeros((2, w.n_r, w.n_z))
+    jz = np.zeros((2, w.n_r, w.n_z + 1))
+    jr = np.zeros((2, w.n_r + 1, w.n_z))
+    T = _tallies_struct(t)
+    rc = lib().ko_fields(C.byref(D.d), C.byref(T), n_prim, activity, _dptr(dens), _dptr(jz), _dptr(jr))
+    if rc != 0:
+        raise ValueError("invalid normalisation arguments")
+    return {"density": dens, "jz": jz, "jr": jr}
 
 
 def philox(k0, k1, c0, c1, c2, c3):

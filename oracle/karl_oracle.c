@@ -949,6 +949,47 @@ int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t) 
 }
 
 /* ------------------------------------------------------------------ */
+/* normalised fields: density, eq. (3) with t_sim = N_prim / a (eq. 4), */
+/* and currents j = (N+ - N-) / (A t_sim) through segment faces        */
+/* ------------------------------------------------------------------ */
+int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activity,
+              double* density, double* jz_cur, double* jr_cur) {
+    if (!(n_prim > 0.0) || !(activity > 0.0)) return -1;
+    const int nr = d->n_r, nz = d->n_z;
+    const double t_sim = n_prim / activity;
+    const double dz = d->length / (double)nz;
+    for (int s = 0; s < 2; ++s) {
+        for (int ir = 0; ir < nr; ++ir) {
+            double r0 = d->radius * (double)ir / (double)nr;
+            double r1 = d->radius * (double)(ir + 1) / (double)nr;
+            double ring = PI * (r1 * r1 - r0 * r0);        /* area of the ring */
+            double vol = ring * dz;                          /* segment volume */
+            for (int iz = 0; iz < nz; ++iz) {
+                size_t k = ((size_t)s * nr + ir) * nz + iz;
+                double n = t->density_time[k] / (t_sim * vol);
+                if (s == 1) n -= (double)t->recomb[(size_t)ir * nz + iz] / vol;
+                density[k] = n;
+            }
+            for (int f = 0; f <= nz; ++f) {
+                size_t k = ((size_t)s * nr + ir) * (nz + 1) + f;
+                double net = (double)(t->jz[2 * k + 1] - t->jz[2 * k]);
+                jz_cur[k] = net / (ring * t_sim);
+            }
+        }
+        for (int f = 0; f <= nr; ++f) {
+            double rf = d->radius * (double)f / (double)nr;
+            double area = TWO_PI * rf * dz;                  /* cylinder face of one z-segment */
+            for (int iz = 0; iz < nz; ++iz) {
+                size_t k = ((size_t)s * (nr + 1) + f) * nz + iz;
+                double net = (double)(t->jr[2 * k + 1] - t->jr[2 * k]);
+                jr_cur[k] = (area > 0.0) ? net / (area * t_sim) : 0.0;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* single-step entry points for the oracle's own tests                 */
 /* ------------------------------------------------------------------ */
 int ko_birth(const ko_desc* d, int64_t pid, double out[8]) {

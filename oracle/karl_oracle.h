@@ -110,6 +110,12 @@ typedef struct {
 /* Transport primaries pid_begin..pid_end-1 and add their contributions to t. */
 int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t);
 
+/* Densities per species and segment, eq. (3) with t_sim = n_prim/activity, eq. (4), minus the
+   recombinations per volume for the ion species; currents (N+ - N-)/(A t_sim) through the
+   z-faces of each ring ([2][n_r][n_z+1]) and the r-faces of each z-segment ([2][n_r+1][n_z]). */
+int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activity,
+              double* density, double* jz_cur, double* jr_cur);
+
 /* ---- single-step entry points used by the oracle's own pin tests ---- */
 void ko_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                uint32_t out[4]);

@@ -49,7 +49,7 @@ struct Layout {
     size_t xs, n_gas, zf, rf, zcdf, n_ion, edges, plane_of;
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
-    size_t snapshot, control, queues, queue_entries;
+    size_t snapshot, control, fields, queues, queue_entries;
     size_t total;
 };
 
@@ -94,6 +94,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.tallies = take(t);
     L.snapshot = take(t);
     L.control = take(64);
+    L.fields = take(8 * (2 * nr * nz + 2 * nr * (nz + 1) + 2 * (nr + 1) * nz));
     L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
     L.queues = take(4 * L.queue_entries * kQueueEntryBytes);
     L.total = off;
@@ -217,6 +218,7 @@ struct Job {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int64_t launches = 0, generations = 0, max_queue = 0;
+    int64_t n_transported = 0;   // primaries transported since creation or reset
     bool failed = false;
     int device = 0;
 };
@@ -564,6 +566,7 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
             continue;
         }
         b += n;
+        j->n_transported += n;
         // next chunk: keep the largest generation near half the queue capacity
         if (max_gen > 0) {
             const double per_primary = (double)max_gen / (double)n;
@@ -612,6 +615,27 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     return KARL_OK;
 }
 
+karl_status karl_read_fields(void* job, double activity, double* density, double* jz_current,
+                             double* jr_current, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_EINVAL, "job is NULL");
+    if (!(activity > 0.0) || !std::isfinite(activity))
+        return fail(KARL_EINVAL, "activity must be positive and finite");
+    if (j->n_transported <= 0) return fail(KARL_ESTATE, "no primaries transported since the last reset");
+    HIP_CHECK(hipSetDevice(j->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z;
+    const size_t n_dens = 2 * nr * nz, n_jz = 2 * nr * (nz + 1), n_jr = 2 * (nr + 1) * nz;
+    double* f = (double*)(j->ws + j->lay.fields);
+    const double t_sim = (double)j->n_transported / activity;
+    HIP_CHECK(karl::launch_fields(j->dj, t_sim, f, f + n_dens, f + n_dens + n_jz, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (density) HIP_CHECK(hipMemcpy(density, f, 8 * n_dens, hipMemcpyDeviceToHost));
+    if (jz_current) HIP_CHECK(hipMemcpy(jz_current, f + n_dens, 8 * n_jz, hipMemcpyDeviceToHost));
+    if (jr_current) HIP_CHECK(hipMemcpy(jr_current, f + n_dens + n_jz, 8 * n_jr, hipMemcpyDeviceToHost));
+    return KARL_OK;
+}
+
 karl_status karl_reset_tallies(void* job, void* hip_stream) {
     Job* j = (Job*)job;
     if (!j) return fail(KARL_EINVAL, "job is NULL");
@@ -622,6 +646,7 @@ karl_status karl_reset_tallies(void* job, void* hip_stream) {
     HIP_CHECK(hipStreamSynchronize(s));
     j->kernel_ms = 0.0;
     j->launches = j->generations = j->max_queue = 0;
+    j->n_transported = 0;
     j->failed = false;
     return KARL_OK;
 }

@@ -97,6 +97,8 @@ enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 size_t lds_bytes(const DevJob& j, int precision);
 hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, int grid,
                             int block, size_t lds, hipStream_t s);
+hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
+                         hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
                            hipStream_t s);
 hipError_t transport_occupancy(int precision, int block, size_t lds, int* blocks_per_cu);

@@ -1086,6 +1086,49 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
         if (s_led[i] != 0.0) add_f64(&J.ledger[i], s_led[i]);
 }
 
+// Normalised fields (Sec. 2.2 eq. 3 with t_sim = N_prim / activity, eq. 4; Sec. 2.3 currents):
+// density per species and segment minus recombinations per volume for the ion species,
+// currents through the z-faces of each ring and the r-faces of each z-segment.
+__global__ void fields_kernel(const DevJob J, double t_sim, double* density, double* jz_cur,
+                              double* jr_cur) {
+    const int nr = J.n_r, nz = J.n_z;
+    const double dz = J.length / (double)nz;
+    const size_t n_dens = (size_t)2 * nr * nz;
+    const size_t n_jz = (size_t)2 * nr * (nz + 1);
+    const size_t n_jr = (size_t)2 * (nr + 1) * nz;
+    const size_t total = n_dens + n_jz + n_jr;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        if (t < n_dens) {
+            const int s = (int)(t / ((size_t)nr * nz));
+            const int ir = (int)((t / nz) % nr);
+            const int iz = (int)(t % nz);
+            const double r0 = J.radius * (double)ir / (double)nr;
+            const double r1 = J.radius * (double)(ir + 1) / (double)nr;
+            const double ring = kPI * (r1 * r1 - r0 * r0);
+            const double vol = ring * dz;
+            double n = J.dens[t] / (t_sim * vol);
+            if (s == 1) n -= (double)J.recomb[(size_t)ir * nz + iz] / vol;
+            density[t] = n;
+        } else if (t < n_dens + n_jz) {
+            const size_t k = t - n_dens;
+            const int ir = (int)((k / (nz + 1)) % nr);
+            const double r0 = J.radius * (double)ir / (double)nr;
+            const double r1 = J.radius * (double)(ir + 1) / (double)nr;
+            const double ring = kPI * (r1 * r1 - r0 * r0);
+            const double net = (double)((long long)J.jz[2 * k + 1] - (long long)J.jz[2 * k]);
+            jz_cur[k] = net / (ring * t_sim);
+        } else {
+            const size_t k = t - n_dens - n_jz;
+            const int f = (int)((k / nz) % (nr + 1));
+            const double rf = J.radius * (double)f / (double)nr;
+            const double area = kTWO_PI * rf * dz;
+            const double net = (double)((long long)J.jr[2 * k + 1] - (long long)J.jr[2 * k]);
+            jr_cur[k] = (area > 0.0) ? net / (area * t_sim) : 0.0;
+        }
+    }
+}
+
 __global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long value) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -1108,6 +1151,16 @@ hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, in
         hipLaunchKernelGGL(transport_kernel<float>, dim3(grid), dim3(block), lds, s, j, g);
     else
         hipLaunchKernelGGL(transport_kernel<double>, dim3(grid), dim3(block), lds, s, j, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
+                         hipStream_t s) {
+    const size_t total = (size_t)2 * j.n_r * j.n_z + (size_t)2 * j.n_r * (j.n_z + 1) +
+                         (size_t)2 * (j.n_r + 1) * j.n_z;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fields_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, t_sim, density, jz, jr);
     return hipGetLastError();
 }
 

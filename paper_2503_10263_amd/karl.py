@@ -29,7 +29,8 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
-                "karl_reset_tallies", "karl_job_stats", "karl_destroy_job", "karl_last_error"]
+                "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_destroy_job",
+                "karl_last_error"]
 
 
 class KarlError(RuntimeError):
@@ -89,6 +90,8 @@ def lib():
         L.karl_create_job.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_void_p)]
         L.karl_transport.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         L.karl_read_tallies.argtypes = [C.c_void_p, C.POINTER(Tallies), C.c_void_p]
+        L.karl_read_fields.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
         L.karl_reset_tallies.argtypes = [C.c_void_p, C.c_void_p]
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -230,6 +233,16 @@ class Job:
             setattr(T, k, arr.ctypes.data_as(C.POINTER(ctype)))
         check(lib().karl_read_tallies(self.h, C.byref(T), self._stream(stream)))
         return out
+
+    def read_fields(self, activity: float, stream=None) -> Dict[str, np.ndarray]:
+        """Densities (m^-3) and currents (m^-2 s^-1) normalised with t_sim = N_prim/activity."""
+        w = self.w
+        dens = np.zeros((2, w.n_r, w.n_z))
+        jz = np.zeros((2, w.n_r, w.n_z + 1))
+        jr = np.zeros((2, w.n_r + 1, w.n_z))
+        check(lib().karl_read_fields(self.h, float(activity), _dptr(dens), _dptr(jz), _dptr(jr),
+                                     self._stream(stream)))
+        return {"density": dens, "jz": jz, "jr": jr}
 
     def reset(self, stream=None):
         check(lib().karl_reset_tallies(self.h, self._stream(stream)))

@@ -158,3 +158,21 @@ def test_rejects_bad_ranges(oracle_lib):
         oracle_lib.run(w, 0, 11)
     with pytest.raises(ValueError):
         oracle_lib.run(w, 5, 4)
+
+
+def test_fields_pencil_beam_closed_form(oracle_lib):
+    """eq. (3)-(5): a pencil beam of N primaries at speed v with activity a has density
+    a/(v A_ring) in the central ring and current a/A_ring through every z-face it crosses."""
+    N, e, act = 200, 50.0, 3.0e7
+    R, L, n_r, n_z = 0.04, 0.5, 4, 5
+    w = W.beam_problem(e, [], np.zeros(n_z), L, radius=R, n_r=n_r, n_primaries=N)
+    t = oracle_lib.run(w)
+    f = oracle_lib.fields(w, t, N, act)
+    v = speed(e, W.M_E)
+    area = math.pi * (R / n_r) ** 2
+    np.testing.assert_allclose(f["density"][0, 0], act / (v * area), rtol=1e-12)
+    assert np.all(f["density"][0, 1:] == 0.0) and np.all(f["density"][1] == 0.0)
+    # the beam starts on face 0 and crosses faces 1..n_z
+    assert f["jz"][0, 0, 0] == 0.0
+    np.testing.assert_allclose(f["jz"][0, 0, 1:], act / area, rtol=1e-12)
+    assert np.all(f["jr"] == 0.0)
