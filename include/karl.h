@@ -192,6 +192,34 @@ karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches,
 /* Release host resources of the job (the caller still owns the workspace). */
 karl_status karl_destroy_job(void* job);
 
+/* ---- batches: many jobs in one launch (scheduler, continuous batching) ----
+   A batch owns the secondary queues and the job table of a launch over up to max_jobs jobs.
+   Every lane carries the index of its job; each job keeps its own tables and tallies.
+   Results of a job are the same alone and in any batch (integer tallies exactly). */
+
+/* Device bytes of a batch with room for max_jobs jobs and queue_capacity entries per queue
+   (0: 1<<22). */
+karl_status karl_batch_workspace_bytes(int32_t max_jobs, int64_t queue_capacity, uint64_t* bytes);
+
+/* Create a batch on the current HIP device; `workspace` is caller-owned device memory of at
+   least karl_batch_workspace_bytes() bytes that must outlive the batch. */
+karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* workspace,
+                              uint64_t workspace_bytes, void** out);
+
+/* Transport, in one sequence of launches shared by all of them, the primaries
+   ranges[2i] .. ranges[2i+1]-1 of jobs[i] for i < n_jobs (all jobs of one precision, on the
+   batch's device; 0 <= n_jobs <= max_jobs).  Tallies accumulate in each job.  Returns after the
+   last launch has completed. */
+karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* ranges,
+                                 int32_t n_jobs, void* hip_stream);
+
+/* Kernel time, launches, secondary generations and largest generation of the batch. */
+karl_status karl_batch_stats(void* batch, double* kernel_ms, int64_t* n_launches,
+                             int64_t* generations, int64_t* max_queue);
+
+/* Release host resources of the batch (the caller still owns its workspace). */
+karl_status karl_destroy_batch(void* batch);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* karl_last_error(void);
 

@@ -1,5 +1,5 @@
 // C ABI of libkarl (include/karl.h): validation, workspace layout, table upload, and the
-// generation loop that drives the transport kernel for a range of primaries.
+// generation loop that drives the transport kernel for one job or a batch of jobs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,14 +39,14 @@ constexpr int64_t kDefaultCapacity = int64_t(1) << 22;
 constexpr int64_t kDefaultChunk = 65536;
 constexpr int64_t kMaxChunk = int64_t(1) << 26;
 constexpr size_t kMaxLds = 65536;
-
-constexpr size_t kQueueEntryBytes = 7 * 8 + 8 + 4 + 4;
+constexpr size_t kQueueEntryBytes = 7 * 8 + 8 + 4 + 4 + 4;
+constexpr size_t kControlBytes = 64;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-// Byte offsets of every region of the caller's workspace.
+// Byte offsets of every region of a job's workspace.
 struct Layout {
-    size_t xs, n_gas, zf, rf, zcdf, n_ion, edges, plane_of;
+    size_t devjob, xs, n_gas, zf, rf, zcdf, n_ion, edges, plane_of;
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
     size_t snapshot, control, fields, queues, queue_entries;
@@ -65,6 +65,7 @@ Layout make_layout(const karl_job_desc* d) {
         off = align_up(off + bytes);
         return o;
     };
+    L.devjob = take(sizeof(karl::DevJob));
     L.xs = take(rs * (size_t)d->n_proc * (size_t)d->n_e);
     L.n_gas = take(rs * nz);
     L.zf = take(rs * (nz + 1));
@@ -93,7 +94,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.tally_bytes = t;
     L.tallies = take(t);
     L.snapshot = take(t);
-    L.control = take(64);
+    L.control = take(kControlBytes);
     L.fields = take(8 * (2 * nr * nz + 2 * nr * (nz + 1) + 2 * (nr + 1) * nz));
     L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
     L.queues = take(4 * L.queue_entries * kQueueEntryBytes);
@@ -196,6 +197,172 @@ int count_faces_le(const std::vector<double>& faces, int n, double r) {
     return k;
 }
 
+karl::QueueSoA queue_at(char* base, size_t cap) {
+    karl::QueueSoA q;
+    size_t o = 0;
+    auto d = [&]() {
+        double* p = (double*)(base + o);
+        o += 8 * cap;
+        return p;
+    };
+    q.x = d(); q.y = d(); q.z = d(); q.u = d(); q.v = d(); q.w = d(); q.e = d();
+    q.lin = (unsigned long long*)(base + o);
+    o += 8 * cap;
+    q.pid = (uint32_t*)(base + o);
+    o += 4 * cap;
+    q.meta = (uint32_t*)(base + o);
+    o += 4 * cap;
+    q.job = (uint32_t*)(base + o);
+    return q;
+}
+
+// Everything needed to run generations: queues, control words, job table, launch shape.
+struct Launcher {
+    int precision = 0;
+    bool batched = false;
+    karl::DevJob* jobs_dev = nullptr;       // job table in device memory
+    karl::QueueSoA q[2]{};                  // next-generation queues (ping-pong)
+    karl::QueueSoA dq[2]{};                 // deferred queues (append / drain)
+    unsigned long long* ctl = nullptr;      // [0] fetch [1] qcount [2] status [3..4] dcount
+    int64_t capacity = 0;
+    size_t lds = 0;
+    int max_blocks = 0;
+    unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
+    int64_t launches = 0, generations = 0, max_queue = 0;
+
+    karl_status init(char* queues, size_t entries, unsigned long long* control, int prec,
+                     bool is_batched, size_t lds_bytes) {
+        precision = prec;
+        batched = is_batched;
+        capacity = (int64_t)entries;
+        ctl = control;
+        lds = lds_bytes;
+        for (int k = 0; k < 2; ++k) {
+            q[k] = queue_at(queues + (size_t)k * entries * kQueueEntryBytes, entries);
+            dq[k] = queue_at(queues + (size_t)(2 + k) * entries * kQueueEntryBytes, entries);
+        }
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+        int per_cu = 0;
+        HIP_CHECK(karl::transport_occupancy(prec, is_batched, kBlock, lds, &per_cu));
+        if (per_cu < 1) per_cu = 1;
+        max_blocks = per_cu * prop.multiProcessorCount;
+        HIP_CHECK(hipHostMalloc((void**)&host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+        HIP_CHECK(hipEventCreate(&ev0));
+        HIP_CHECK(hipEventCreate(&ev1));
+        HIP_CHECK(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
+        HIP_CHECK(hipDeviceSynchronize());
+        return KARL_OK;
+    }
+
+    void release() {
+        if (host_ctl) (void)hipHostFree(host_ctl);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        host_ctl = nullptr;
+        ev0 = ev1 = nullptr;
+    }
+
+    void reset_stats() {
+        kernel_ms = 0.0;
+        launches = generations = max_queue = 0;
+    }
+
+    // Run every generation of n primary items (chunk of the item space starting at item_base;
+    // for a single job the item i is primary pid_begin0 + i).  Returns with *overflow set if a
+    // queue overflowed; *max_gen receives the largest generation.
+    karl_status run(const karl::GenArgs& base, int64_t n, hipStream_t s, bool* overflow,
+                    int64_t* max_gen) {
+        *overflow = false;
+        *max_gen = 0;
+        int mode = 0;
+        int64_t items = n;
+        const karl::QueueSoA* in = &q[0];
+        int mo = 0;
+        int di = 0;
+        int64_t ndef = 0;
+        unsigned long long* fetch = ctl;
+        unsigned long long* qcount = ctl + 1;
+        unsigned long long* dcount = ctl + 3;
+        HIP_CHECK(karl::launch_fill_u64(dcount, 2, 0ull, s));
+        for (;;) {
+            if (items == 0) {
+                if (ndef == 0) break;
+                // the generations are exhausted: drain the deferred queue in one launch
+                in = &dq[di];
+                items = ndef;
+                mode = 1;
+                di ^= 1;
+                ndef = 0;
+                HIP_CHECK(karl::launch_fill_u64(dcount + di, 1, 0ull, s));
+            }
+            karl::GenArgs g = base;
+            g.mode = mode;
+            g.n_items = items;
+            g.fetch = fetch;
+            g.qin = *in;
+            g.qout = q[mo];
+            g.qout_count = qcount;
+            g.qdef = dq[di];
+            g.qdef_count = dcount + di;
+            g.capacity = capacity;
+            g.status = (unsigned int*)(ctl + 2);
+            HIP_CHECK(karl::launch_fill_u64(fetch, 2, 0ull, s));
+            int64_t blocks = (items + kBlock - 1) / kBlock;
+            if (blocks > max_blocks) blocks = max_blocks;
+            HIP_CHECK(hipEventRecord(ev0, s));
+            HIP_CHECK(karl::launch_transport(jobs_dev, karl::DevJob{}, batched, g, precision,
+                                             (int)blocks, kBlock, lds, s));
+            HIP_CHECK(hipEventRecord(ev1, s));
+            HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+            kernel_ms += ms;
+            launches += 1;
+            if (mode == 1) generations += 1;
+            const unsigned long long produced = host_ctl[0];
+            const unsigned int status = (unsigned int)(host_ctl[1] & 0xFFFFFFFFull);
+            ndef = (int64_t)host_ctl[2 + di];
+            if (status & karl::STATUS_OVERFLOW) {
+                *overflow = true;
+                return KARL_OK;
+            }
+            items = (int64_t)produced;
+            *max_gen = std::max(*max_gen, std::max(items, ndef));
+            max_queue = std::max(max_queue, std::max(items, ndef));
+            mode = 1;
+            in = &q[mo];
+            mo ^= 1;
+        }
+        return KARL_OK;
+    }
+
+    // after an overflow: clear the fetch/queue counters and the overflow bit
+    karl_status clear_overflow(hipStream_t s) {
+        HIP_CHECK(karl::launch_fill_u64(ctl, 2, 0ull, s));
+        host_ctl[4] = (unsigned long long)((unsigned int)host_ctl[1] & ~karl::STATUS_OVERFLOW);
+        HIP_CHECK(hipMemcpyAsync(ctl + 2, &host_ctl[4], sizeof(unsigned int), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return KARL_OK;
+    }
+};
+
+// next chunk: keep the largest generation near half the queue capacity
+int64_t next_chunk(int64_t cur, int64_t n_done, int64_t max_gen, int64_t capacity) {
+    if (max_gen > 0) {
+        const double per_primary = (double)max_gen / (double)n_done;
+        const double target = 0.5 * (double)capacity / per_primary;
+        return std::max<int64_t>(1, std::min<int64_t>(kMaxChunk, (int64_t)target));
+    }
+    return std::min<int64_t>(kMaxChunk, std::max<int64_t>(cur, 2 * n_done));
+}
+
 struct Job {
     int precision = 0;
     uint32_t flags = 0;
@@ -204,24 +371,41 @@ struct Job {
     char* ws = nullptr;
     Layout lay{};
     karl::DevJob dj{};
-    karl::QueueSoA q[2]{};      // next-generation queues (ping-pong)
-    karl::QueueSoA dq[2]{};     // deferred queues (append / drain)
-    unsigned long long* fetch = nullptr;
-    unsigned long long* qcount = nullptr;
+    Launcher run;
     unsigned int* status = nullptr;
-    unsigned long long* dcount = nullptr;   // [2]
-    size_t lds = 0;
-    int max_blocks = 0;
-    int64_t capacity = 0;
     int64_t chunk = 0;
-    unsigned long long* host_ctl = nullptr;   // pinned: [qcount, status, dcount0, dcount1]
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_ms = 0.0;
-    int64_t launches = 0, generations = 0, max_queue = 0;
     int64_t n_transported = 0;   // primaries transported since creation or reset
     bool failed = false;
     int device = 0;
 };
+
+struct Batch {
+    int32_t max_jobs = 0;
+    char* ws = nullptr;
+    int64_t* item_offs = nullptr;   // device [max_jobs+1]
+    int64_t* pid_begin = nullptr;   // device [max_jobs]
+    int64_t* host_i64 = nullptr;    // pinned staging [2*max_jobs+1]
+    karl::DevJob* host_jobs = nullptr;   // pinned staging of the job table
+    Launcher run[2];                // FP64 and FP32 launchers share the queues
+    int64_t chunk = kDefaultChunk;
+    int device = 0;
+};
+
+size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o_offs,
+                    size_t* o_pid, size_t* o_ctl, size_t* o_queues) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    *o_jobs = take(sizeof(karl::DevJob) * (size_t)max_jobs);
+    *o_offs = take(8 * ((size_t)max_jobs + 1));
+    *o_pid = take(8 * (size_t)max_jobs);
+    *o_ctl = take(kControlBytes);
+    *o_queues = take(4 * (size_t)entries * kQueueEntryBytes);
+    return off;
+}
 
 template <typename T>
 std::vector<T> convert(const double* src, size_t n) {
@@ -239,23 +423,6 @@ karl_status upload_real(const Job& j, size_t off, const std::vector<double>& v) 
         HIP_CHECK(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     return KARL_OK;
-}
-
-karl::QueueSoA queue_at(char* base, size_t cap) {
-    karl::QueueSoA q;
-    size_t o = 0;
-    auto d = [&]() {
-        double* p = (double*)(base + o);
-        o += 8 * cap;
-        return p;
-    };
-    q.x = d(); q.y = d(); q.z = d(); q.u = d(); q.v = d(); q.w = d(); q.e = d();
-    q.lin = (unsigned long long*)(base + o);
-    o += 8 * cap;
-    q.pid = (uint32_t*)(base + o);
-    o += 4 * cap;
-    q.meta = (uint32_t*)(base + o);
-    return q;
 }
 
 }  // namespace
@@ -288,13 +455,10 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->n_bins = d->n_bins;
     j->ws = (char*)d->workspace;
     j->lay = make_layout(d);
-    j->capacity = (int64_t)j->lay.queue_entries;
     j->chunk = d->chunk > 0 ? d->chunk : kDefaultChunk;
     const Layout& L = j->lay;
     auto cleanup = [&](karl_status s) {
-        if (j->host_ctl) (void)hipHostFree(j->host_ctl);
-        if (j->ev0) (void)hipEventDestroy(j->ev0);
-        if (j->ev1) (void)hipEventDestroy(j->ev1);
+        j->run.release();
         delete j;
         return s;
     };
@@ -311,8 +475,6 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     } while (0)
 
     TRY_HIP(hipGetDevice(&j->device));
-    hipDeviceProp_t prop;
-    TRY_HIP(hipGetDeviceProperties(&prop, j->device));
 
     // ---- host-side tables
     const int nz = d->n_z, nr = d->n_r;
@@ -386,6 +548,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.kind[i] = i < d->n_proc ? d->proc[i].kind : 0;
         J.target[i] = i < d->n_proc ? d->proc[i].target : 0;
         J.e_th[i] = i < d->n_proc ? d->proc[i].e_th : 0.0;
+        J.e_th_f[i] = (float)J.e_th[i];
     }
     for (int i = 0; i < d->n_proc; ++i) {
         const int s = d->proc[i].species;
@@ -432,99 +595,21 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.digests = (d->flags & KARL_FLAG_DIGESTS) ? (unsigned long long*)(t + L.t_digests) : nullptr;
     J.hist = (d->flags & KARL_FLAG_HISTORY) ? (double*)(t + L.t_hist) : nullptr;
     unsigned long long* ctl = (unsigned long long*)(w + L.control);
-    j->fetch = ctl;
-    j->qcount = ctl + 1;
-    j->status = (unsigned int*)(ctl + 2);
-    j->dcount = ctl + 3;
+    j->status = (unsigned int*)(ctl + 5);     // the job's own sticky status (NaN met)
     J.status = j->status;
-    for (int k = 0; k < 2; ++k) {
-        j->q[k] = queue_at(w + L.queues + (size_t)k * L.queue_entries * kQueueEntryBytes, L.queue_entries);
-        j->dq[k] = queue_at(w + L.queues + (size_t)(2 + k) * L.queue_entries * kQueueEntryBytes, L.queue_entries);
-    }
 
-    j->lds = karl::lds_bytes(J, d->precision);
-    if (j->lds > kMaxLds)
+    const size_t lds = karl::lds_bytes(J, d->precision);
+    if (lds > kMaxLds)
         return cleanup(fail(KARL_EINVAL, "tables need %zu bytes of LDS per workgroup (max %zu)",
-                            j->lds, kMaxLds));
-    int per_cu = 0;
-    TRY_HIP(karl::transport_occupancy(d->precision, kBlock, j->lds, &per_cu));
-    if (per_cu < 1) per_cu = 1;
-    j->max_blocks = per_cu * prop.multiProcessorCount;
-
-    TRY_HIP(hipHostMalloc((void**)&j->host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
-    TRY_HIP(hipEventCreate(&j->ev0));
-    TRY_HIP(hipEventCreate(&j->ev1));
-    // zero tallies and control words
+                            lds, kMaxLds));
+    TRY_HIP(hipMemcpy(w + L.devjob, &J, sizeof(J), hipMemcpyHostToDevice));
+    TRY(j->run.init(w + L.queues, L.queue_entries, ctl, d->precision, false, lds));
+    j->run.jobs_dev = (karl::DevJob*)(w + L.devjob);
     TRY_HIP(karl::launch_fill_u64((unsigned long long*)t, L.tally_bytes / 8, 0ull, nullptr));
-    TRY_HIP(karl::launch_fill_u64(ctl, 8, 0ull, nullptr));
     TRY_HIP(hipDeviceSynchronize());
 #undef TRY
 #undef TRY_HIP
     *out = j;
-    return KARL_OK;
-}
-
-static karl_status run_generations(Job* j, int64_t pid_begin, int64_t n, hipStream_t s,
-                                   bool* overflow, int64_t* max_gen) {
-    *overflow = false;
-    *max_gen = 0;
-    int mode = 0;                 // 0: primaries, 1: queued particles
-    int64_t items = n;
-    const karl::QueueSoA* in = &j->q[0];
-    int mo = 0;                   // main queue receiving the next generation
-    int di = 0;                   // deferred queue being appended to
-    int64_t ndef = 0;
-    HIP_CHECK(karl::launch_fill_u64(j->dcount, 2, 0ull, s));
-    for (;;) {
-        if (items == 0) {
-            if (ndef == 0) break;
-            // main generations exhausted: drain the deferred queue in one launch
-            in = &j->dq[di];
-            items = ndef;
-            mode = 1;
-            di ^= 1;
-            ndef = 0;
-            HIP_CHECK(karl::launch_fill_u64(j->dcount + di, 1, 0ull, s));
-        }
-        karl::GenArgs g{};
-        g.mode = mode;
-        g.pid_begin = pid_begin;
-        g.n_items = items;
-        g.fetch = j->fetch;
-        g.qin = *in;
-        g.qout = j->q[mo];
-        g.qout_count = j->qcount;
-        g.qdef = j->dq[di];
-        g.qdef_count = j->dcount + di;
-        g.capacity = j->capacity;
-        HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
-        int64_t blocks = (items + kBlock - 1) / kBlock;
-        if (blocks > j->max_blocks) blocks = j->max_blocks;
-        HIP_CHECK(hipEventRecord(j->ev0, s));
-        HIP_CHECK(karl::launch_transport(j->dj, g, j->precision, (int)blocks, kBlock, j->lds, s));
-        HIP_CHECK(hipEventRecord(j->ev1, s));
-        HIP_CHECK(hipMemcpyAsync(j->host_ctl, j->qcount, 4 * sizeof(unsigned long long),
-                                 hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        float ms = 0.f;
-        HIP_CHECK(hipEventElapsedTime(&ms, j->ev0, j->ev1));
-        j->kernel_ms += ms;
-        j->launches += 1;
-        if (mode == 1) j->generations += 1;
-        const unsigned long long produced = j->host_ctl[0];
-        const unsigned int status = (unsigned int)(j->host_ctl[1] & 0xFFFFFFFFull);
-        ndef = (int64_t)j->host_ctl[2 + di];
-        if (status & karl::STATUS_OVERFLOW) {
-            *overflow = true;
-            return KARL_OK;
-        }
-        items = (int64_t)produced;
-        *max_gen = std::max(*max_gen, std::max(items, ndef));
-        j->max_queue = std::max(j->max_queue, std::max(items, ndef));
-        mode = 1;
-        in = &j->q[mo];
-        mo ^= 1;
-    }
     return KARL_OK;
 }
 
@@ -543,9 +628,12 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
     while (b < pid_end) {
         const int64_t n = std::min<int64_t>(j->chunk, pid_end - b);
         HIP_CHECK(hipMemcpyAsync(snap, tallies, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
+        karl::GenArgs g{};
+        g.n_jobs = 1;
+        g.pid_begin0 = b;
         bool overflow = false;
         int64_t max_gen = 0;
-        karl_status st = run_generations(j, b, n, s, &overflow, &max_gen);
+        karl_status st = j->run.run(g, n, s, &overflow, &max_gen);
         if (st != KARL_OK) {
             j->failed = true;
             return st;
@@ -553,28 +641,21 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
         if (overflow) {
             // undo the partial chunk and retry with half as many primaries
             HIP_CHECK(hipMemcpyAsync(tallies, snap, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
-            HIP_CHECK(karl::launch_fill_u64(j->fetch, 2, 0ull, s));
-            j->host_ctl[4] = (unsigned long long)((unsigned int)j->host_ctl[1] & ~karl::STATUS_OVERFLOW);
-            HIP_CHECK(hipMemcpyAsync(j->status, &j->host_ctl[4], sizeof(unsigned int), hipMemcpyHostToDevice, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            if ((st = j->run.clear_overflow(s)) != KARL_OK) {
+                j->failed = true;
+                return st;
+            }
             if (n == 1) {
                 j->failed = true;
                 return fail(KARL_EOVERFLOW, "primary %lld alone overflows a queue of %lld entries",
-                            (long long)b, (long long)j->capacity);
+                            (long long)b, (long long)j->run.capacity);
             }
             j->chunk = std::max<int64_t>(1, n / 2);
             continue;
         }
         b += n;
         j->n_transported += n;
-        // next chunk: keep the largest generation near half the queue capacity
-        if (max_gen > 0) {
-            const double per_primary = (double)max_gen / (double)n;
-            const double target = 0.5 * (double)j->capacity / per_primary;
-            j->chunk = std::max<int64_t>(1, std::min<int64_t>(kMaxChunk, (int64_t)target));
-        } else {
-            j->chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(j->chunk, 2 * n));
-        }
+        j->chunk = next_chunk(j->chunk, n, max_gen, j->run.capacity);
     }
     return KARL_OK;
 }
@@ -642,10 +723,9 @@ karl_status karl_reset_tallies(void* job, void* hip_stream) {
     HIP_CHECK(hipSetDevice(j->device));
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(karl::launch_fill_u64((unsigned long long*)(j->ws + j->lay.tallies), j->lay.tally_bytes / 8, 0ull, s));
-    HIP_CHECK(karl::launch_fill_u64(j->fetch, 5, 0ull, s));
+    HIP_CHECK(karl::launch_fill_u64(j->run.ctl, kControlBytes / 8, 0ull, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    j->kernel_ms = 0.0;
-    j->launches = j->generations = j->max_queue = 0;
+    j->run.reset_stats();
     j->n_transported = 0;
     j->failed = false;
     return KARL_OK;
@@ -655,20 +735,166 @@ karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches, in
                            int64_t* max_queue) {
     Job* j = (Job*)job;
     if (!j) return fail(KARL_EINVAL, "job is NULL");
-    if (kernel_ms) *kernel_ms = j->kernel_ms;
-    if (n_launches) *n_launches = j->launches;
-    if (generations) *generations = j->generations;
-    if (max_queue) *max_queue = j->max_queue;
+    if (kernel_ms) *kernel_ms = j->run.kernel_ms;
+    if (n_launches) *n_launches = j->run.launches;
+    if (generations) *generations = j->run.generations;
+    if (max_queue) *max_queue = j->run.max_queue;
     return KARL_OK;
 }
 
 karl_status karl_destroy_job(void* job) {
     Job* j = (Job*)job;
     if (!j) return fail(KARL_EINVAL, "job is NULL");
-    if (j->host_ctl) (void)hipHostFree(j->host_ctl);
-    if (j->ev0) (void)hipEventDestroy(j->ev0);
-    if (j->ev1) (void)hipEventDestroy(j->ev1);
+    j->run.release();
     delete j;
+    return KARL_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+karl_status karl_batch_workspace_bytes(int32_t max_jobs, int64_t queue_capacity, uint64_t* bytes) {
+    if (!bytes || max_jobs < 1 || queue_capacity < 0)
+        return fail(KARL_EINVAL, "need max_jobs >= 1, queue_capacity >= 0 and a result pointer");
+    size_t a, b, c, d, e;
+    *bytes = batch_layout(max_jobs, queue_capacity > 0 ? queue_capacity : kDefaultCapacity, &a, &b, &c, &d, &e);
+    return KARL_OK;
+}
+
+karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* workspace,
+                              uint64_t workspace_bytes, void** out) {
+    g_err[0] = '\0';
+    if (!out) return fail(KARL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_jobs < 1 || queue_capacity < 0) return fail(KARL_EINVAL, "need max_jobs >= 1 and queue_capacity >= 0");
+    if (!workspace) return fail(KARL_EINVAL, "workspace is NULL");
+    const int64_t entries = queue_capacity > 0 ? queue_capacity : kDefaultCapacity;
+    size_t o_jobs, o_offs, o_pid, o_ctl, o_q;
+    const size_t need = batch_layout(max_jobs, entries, &o_jobs, &o_offs, &o_pid, &o_ctl, &o_q);
+    if (workspace_bytes < need)
+        return fail(KARL_ENOMEM, "batch workspace has %llu bytes, needs %llu",
+                    (unsigned long long)workspace_bytes, (unsigned long long)need);
+    Batch* b = new Batch();
+    b->max_jobs = max_jobs;
+    b->ws = (char*)workspace;
+    b->item_offs = (int64_t*)(b->ws + o_offs);
+    b->pid_begin = (int64_t*)(b->ws + o_pid);
+    auto cleanup = [&](karl_status s) {
+        b->run[0].release();
+        b->run[1].release();
+        if (b->host_i64) (void)hipHostFree(b->host_i64);
+        if (b->host_jobs) (void)hipHostFree(b->host_jobs);
+        delete b;
+        return s;
+    };
+    if (hipGetDevice(&b->device) != hipSuccess) return cleanup(fail(KARL_EDEVICE, "hipGetDevice failed"));
+    unsigned long long* ctl = (unsigned long long*)(b->ws + o_ctl);
+    for (int p = 0; p < 2; ++p) {
+        karl_status st = b->run[p].init(b->ws + o_q, (size_t)entries, ctl, p == 0 ? KARL_FP64 : KARL_FP32,
+                                        true, karl::batched_lds_bytes());
+        if (st != KARL_OK) return cleanup(st);
+        b->run[p].jobs_dev = (karl::DevJob*)(b->ws + o_jobs);
+    }
+    if (hipHostMalloc((void**)&b->host_i64, 8 * (2 * (size_t)max_jobs + 1), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->host_jobs, sizeof(karl::DevJob) * (size_t)max_jobs, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(KARL_EDEVICE, "pinned staging allocation failed"));
+    *out = b;
+    return KARL_OK;
+}
+
+karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* ranges, int32_t n_jobs,
+                                 void* hip_stream) {
+    Batch* B = (Batch*)batch;
+    if (!B) return fail(KARL_ESTATE, "batch is NULL");
+    if (n_jobs < 0 || n_jobs > B->max_jobs)
+        return fail(KARL_EINVAL, "n_jobs %d outside 0..%d", n_jobs, B->max_jobs);
+    if (n_jobs == 0) return KARL_OK;
+    if (!jobs || !ranges) return fail(KARL_EINVAL, "jobs or ranges is NULL");
+    const int prec = ((Job*)jobs[0])->precision;
+    int64_t total = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        Job* j = (Job*)jobs[i];
+        if (!j) return fail(KARL_ESTATE, "job %d is NULL", i);
+        if (j->failed) return fail(KARL_ESTATE, "job %d failed earlier", i);
+        if (j->precision != prec) return fail(KARL_EINVAL, "jobs of one batch share the precision");
+        if (j->device != B->device) return fail(KARL_EINVAL, "job %d lives on another device", i);
+        const int64_t b = ranges[2 * i], e = ranges[2 * i + 1];
+        if (b < 0 || e < b || e > j->n_primaries)
+            return fail(KARL_EINVAL, "job %d: pid range [%lld, %lld) invalid", i, (long long)b, (long long)e);
+        B->host_jobs[i] = j->dj;
+        B->host_i64[i] = total;                     // item_offs
+        B->host_i64[n_jobs + 1 + i] = b;            // pid_begin
+        total += e - b;
+    }
+    B->host_i64[n_jobs] = total;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(hipSetDevice(B->device));
+    Launcher& R = B->run[prec == KARL_FP32 ? 1 : 0];
+    HIP_CHECK(hipMemcpyAsync(R.jobs_dev, B->host_jobs, sizeof(karl::DevJob) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(B->item_offs, B->host_i64, 8 * ((size_t)n_jobs + 1), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(B->pid_begin, B->host_i64 + n_jobs + 1, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+    std::vector<int64_t> offs(B->host_i64, B->host_i64 + n_jobs + 1);
+    int64_t c0 = 0;
+    while (c0 < total) {
+        const int64_t n = std::min<int64_t>(B->chunk, total - c0);
+        // jobs touched by items [c0, c0+n): snapshot their tallies for an overflow retry
+        const int j_lo = (int)(std::upper_bound(offs.begin(), offs.end(), c0) - offs.begin()) - 1;
+        const int j_hi = (int)(std::lower_bound(offs.begin(), offs.end(), c0 + n) - offs.begin());
+        for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
+            Job* j = (Job*)jobs[i];
+            HIP_CHECK(hipMemcpyAsync(j->ws + j->lay.snapshot, j->ws + j->lay.tallies, j->lay.tally_bytes,
+                                     hipMemcpyDeviceToDevice, s));
+        }
+        karl::GenArgs g{};
+        g.n_jobs = n_jobs;
+        g.item_base = c0;
+        g.item_offs = B->item_offs;
+        g.pid_begin = B->pid_begin;
+        bool overflow = false;
+        int64_t max_gen = 0;
+        karl_status st = R.run(g, n, s, &overflow, &max_gen);
+        if (st != KARL_OK) return st;
+        if (overflow) {
+            for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
+                Job* j = (Job*)jobs[i];
+                HIP_CHECK(hipMemcpyAsync(j->ws + j->lay.tallies, j->ws + j->lay.snapshot, j->lay.tally_bytes,
+                                         hipMemcpyDeviceToDevice, s));
+            }
+            if ((st = R.clear_overflow(s)) != KARL_OK) return st;
+            if (n == 1) return fail(KARL_EOVERFLOW, "one primary alone overflows the batch queue");
+            B->chunk = std::max<int64_t>(1, n / 2);
+            continue;
+        }
+        // credit the transported primaries to their jobs
+        for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
+            const int64_t lo = std::max(c0, offs[i]), hi = std::min(c0 + n, offs[i + 1]);
+            if (hi > lo) ((Job*)jobs[i])->n_transported += hi - lo;
+        }
+        c0 += n;
+        B->chunk = next_chunk(B->chunk, n, max_gen, R.capacity);
+    }
+    return KARL_OK;
+}
+
+karl_status karl_batch_stats(void* batch, double* kernel_ms, int64_t* n_launches, int64_t* generations,
+                             int64_t* max_queue) {
+    Batch* B = (Batch*)batch;
+    if (!B) return fail(KARL_EINVAL, "batch is NULL");
+    const Launcher* R[2] = {&B->run[0], &B->run[1]};
+    if (kernel_ms) *kernel_ms = R[0]->kernel_ms + R[1]->kernel_ms;
+    if (n_launches) *n_launches = R[0]->launches + R[1]->launches;
+    if (generations) *generations = R[0]->generations + R[1]->generations;
+    if (max_queue) *max_queue = std::max(R[0]->max_queue, R[1]->max_queue);
+    return KARL_OK;
+}
+
+karl_status karl_destroy_batch(void* batch) {
+    Batch* B = (Batch*)batch;
+    if (!B) return fail(KARL_EINVAL, "batch is NULL");
+    B->run[0].release();
+    B->run[1].release();
+    if (B->host_i64) (void)hipHostFree(B->host_i64);
+    if (B->host_jobs) (void)hipHostFree(B->host_jobs);
+    delete B;
     return KARL_OK;
 }
 

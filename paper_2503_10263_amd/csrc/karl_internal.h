@@ -21,6 +21,7 @@ struct QueueSoA {
     unsigned long long* lin;   // lineage
     uint32_t* pid;             // primary id
     uint32_t* meta;            // species | r-cell << 2 | z-cell << 13
+    uint32_t* job;             // index into the launch's job table
 };
 
 // Everything the transport kernel needs about one job, passed by value.
@@ -53,6 +54,7 @@ struct DevJob {
     int32_t kind[KARL_MAX_PROC];
     int32_t target[KARL_MAX_PROC];
     double e_th[KARL_MAX_PROC];
+    float e_th_f[KARL_MAX_PROC];
     // device tables (Real = double or float according to the precision)
     const void* xs;        // [n_proc][n_e]
     const void* n_gas;     // [n_z]
@@ -75,14 +77,19 @@ struct DevJob {
     unsigned int* status;
 };
 
-// One generation: primaries (mode 0) or queued secondaries (mode 1).  Products go to the
-// next generation's queue, or -- for species that never produce secondaries -- to the
-// deferred queue, which is processed in one launch once the other generations are done.
+// One generation of a launch over a table of jobs: primaries (mode 0; item i belongs to the job
+// j with item_offs[j] <= i < item_offs[j+1] and has id pid_begin[j] + i - item_offs[j]) or
+// queued particles (mode 1).  Products go to the next generation's queue, or -- for species
+// that never produce secondaries -- to the deferred queue, which is processed in one launch
+// once the other generations are done.
 struct GenArgs {
     int32_t mode;
-    int32_t pad;
-    int64_t pid_begin;
+    int32_t n_jobs;
     int64_t n_items;
+    int64_t pid_begin0;            // single-job launches: id of item 0
+    int64_t item_base;             // batched launches: item i is item item_base + i of the batch
+    const int64_t* item_offs;      // [n_jobs+1] (batched mode 0)
+    const int64_t* pid_begin;      // [n_jobs]   (batched mode 0)
     unsigned long long* fetch;
     QueueSoA qin;
     QueueSoA qout;
@@ -90,17 +97,21 @@ struct GenArgs {
     QueueSoA qdef;
     unsigned long long* qdef_count;
     int64_t capacity;
+    unsigned int* status;          // launch status (queue overflow)
 };
 
 enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 
 size_t lds_bytes(const DevJob& j, int precision);
-hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, int grid,
-                            int block, size_t lds, hipStream_t s);
+hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool batched,
+                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            hipStream_t s);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
                            hipStream_t s);
-hipError_t transport_occupancy(int precision, int block, size_t lds, int* blocks_per_cu);
+hipError_t transport_occupancy(int precision, bool batched, int block, size_t lds,
+                               int* blocks_per_cu);
+size_t batched_lds_bytes();
 
 }  // namespace karl

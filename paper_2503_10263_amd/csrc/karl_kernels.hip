@@ -264,9 +264,10 @@ struct Part {
     double t_alive, t_cell, e_exc, e_bind, e_gas;
     unsigned long long lin, dg;
     uint32_t pid, s;
-    int32_t sp, ir, iz;
+    int32_t sp, ir, iz, job;
     int64_t n_int;
     bool alive;
+    bool start;            // fetched, not yet started
 };
 
 template <typename Real>
@@ -283,9 +284,25 @@ struct Lds {
     const Real* rf;            // [n_r+1]
 };
 
+// Per-lane event counts of one job, added to that job's counters when the lane moves to
+// another job and at the end of the launch.
 struct LaneCnt {
-    uint32_t step0, step1, coll0, coll1, zc0, zc1, rc0, rc1;
+    uint32_t step0, step1, coll0, coll1, zc0, zc1, rc0, rc1, redraw, beb, beta;
+    double e_prim;
 };
+
+__device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt, double* led) {
+    const uint32_t v[11] = {lc.step0, lc.step1, lc.coll0, lc.coll1, lc.zc0, lc.zc1, lc.rc0, lc.rc1,
+                            lc.redraw, lc.beb, lc.beta};
+    const int idx[11] = {KARL_C_STEP, KARL_C_STEP + 1, KARL_C_COLL, KARL_C_COLL + 1, KARL_C_ZCROSS,
+                         KARL_C_ZCROSS + 1, KARL_C_RCROSS, KARL_C_RCROSS + 1, KARL_C_TARGET_REDRAW,
+                         KARL_C_BEB_TRIES, KARL_C_BETA_TRIES};
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+        if (v[k]) atomicAdd(&cnt[idx[k]], (unsigned long long)v[k]);
+    if (lc.e_prim != 0.0) atomicAdd(&led[KARL_L_E_PRIMARY], lc.e_prim);
+    lc = LaneCnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
+}
 
 template <typename T>
 __device__ __forceinline__ T sel2(int sp, T a, T b) { return sp ? b : a; }
@@ -511,7 +528,8 @@ __device__ __forceinline__ Real beta_shape(Real e, Real e0, Real z) {
 template <typename Real>
 __device__ __forceinline__ void queue_write(const QueueSoA& q, unsigned long long i, Real x, Real y,
                                            Real z, const Real d[3], Real e,
-                                           unsigned long long lin, uint32_t pid, uint32_t meta) {
+                                           unsigned long long lin, uint32_t pid, uint32_t meta,
+                                           uint32_t job) {
     q.x[i] = (double)x;
     q.y[i] = (double)y;
     q.z[i] = (double)z;
@@ -522,6 +540,7 @@ __device__ __forceinline__ void queue_write(const QueueSoA& q, unsigned long lon
     q.lin[i] = lin;
     q.pid[i] = pid;
     q.meta[i] = meta;
+    q.job[i] = job;
 }
 
 __device__ __forceinline__ uint32_t pack_meta(int sp, int ir, int iz) {
@@ -551,7 +570,7 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
 
 template <typename Real>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                             int pi, Real xc, Real yc, uint32_t* n_redraw, uint32_t* n_beb) {
+                             int pi, Real xc, Real yc, LaneCnt& lc) {
     const Real ef2 = (Real)sel2(p.sp, J.e_from_v2[0], J.e_from_v2[1]);
     const Real v2e = (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1]);
     const Real B = L.eth[pi];
@@ -563,7 +582,7 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     g[2] = v[2] - V[2];
     Real er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     for (uint32_t r = 1; er < B && r <= 15u; ++r) {
-        *n_redraw += 1u;
+        lc.redraw += 1u;
         thermal(J, p, 136u + 2u * r, 137u + 2u * r, V);
         g[0] = v[0] - V[0];
         g[1] = v[1] - V[1];
@@ -578,7 +597,7 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
         er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     const Real t = er / B;
-    const Real w = beb_sample(J, p, t, n_beb);
+    const Real w = beb_sample(J, p, t, &lc.beb);
     const Real W = w * B;
     Real ef = er - B - W;
     if (ef < (Real)0) ef = (Real)0;
@@ -654,19 +673,19 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     const unsigned long long si = wave_reserve(J.defer[1] ? G.qdef_count : G.qout_count, push_i);
     const unsigned long long cap = (unsigned long long)G.capacity;
     if (push_e) {
-        if (se < cap) queue_write(qe, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz));
-        else atomicOr(J.status, STATUS_OVERFLOW);
+        if (se < cap) queue_write(qe, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz), (uint32_t)p.job);
+        else atomicOr(G.status, STATUS_OVERFLOW);
     }
     if (push_i) {
-        if (si < cap) queue_write(qi, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz));
-        else atomicOr(J.status, STATUS_OVERFLOW);
+        if (si < cap) queue_write(qi, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz), (uint32_t)p.job);
+        else atomicOr(G.status, STATUS_OVERFLOW);
     }
 }
 
 // ---------------------------------------------------------------- birth (Sec. 3.5)
 template <typename Real>
 __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Real>& p,
-                      uint32_t* n_beta) {
+                      LaneCnt& lc) {
     p.lin = 0ull;
     p.pid = pid;
     if (J.source == KARL_SOURCE_BEAM) {
@@ -733,7 +752,7 @@ __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Re
     for (uint32_t j = 0; j < 64u; ++j) {
         const Pair<Real> q = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 3u + j);
         e = e0 * (q.d0 + Prec<Real>::eps);
-        *n_beta += 1u;
+        lc.beta += 1u;
         if (q.d1 * fmax_ < beta_shape(e, e0, bz)) break;
     }
     p.e = e;
@@ -769,7 +788,7 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
 // ---------------------------------------------------------------- one flight segment
 template <typename Real>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                     LaneCnt& lc, uint32_t* n_redraw, uint32_t* n_beb) {
+                     LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     const int sp = p.sp;
     // cross sections at the current energy, rates in the current cell (eq. 1)
@@ -917,7 +936,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                 break;
             }
             case KARL_IONIZATION:
-                k_ionization(J, L, G, p, pi, xc, yc, n_redraw, n_beb);
+                k_ionization(J, L, G, p, pi, xc, yc, lc);
                 break;
             default:
                 add_u64(&J.recomb[(size_t)p.ir * J.n_z + (size_t)p.iz], 1ull);
@@ -987,103 +1006,181 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
 }
 
 // ---------------------------------------------------------------- the kernel
+template <typename Real> struct EthOf;
+template <> struct EthOf<double> {
+    static __device__ __forceinline__ const double* get(const DevJob& J) { return J.e_th; }
+};
+template <> struct EthOf<float> {
+    static __device__ __forceinline__ const float* get(const DevJob& J) { return J.e_th_f; }
+};
+
+// Tables and counters of a job read directly from HBM (batched launches: the lanes of a
+// workgroup may work for different jobs; the tables stay resident in L2).
 template <typename Real>
+__device__ __forceinline__ Lds<Real> global_view(const DevJob& J) {
+    return Lds<Real>{J.counters, J.ledger, &J.pidx[0][0], J.kind, J.target, EthOf<Real>::get(J),
+                     (const Real*)J.xs, (const Real*)J.n_gas, (const Real*)J.zf, (const Real*)J.rf};
+}
+
+// Load the fetched work item into the lane: a primary (born from its id) or a queued particle.
+template <typename Real, bool kBatched>
+__device__ __forceinline__ void fetch_item(const GenArgs& G, unsigned long long idx, Part<Real>& p,
+                                           uint32_t* pid_out) {
+    if (G.mode == 0) {
+        int jb = 0;
+        int64_t base = 0, first = G.pid_begin0;
+        if (kBatched) {
+            const int64_t gi = G.item_base + (int64_t)idx;
+            int lo = 0, hi = G.n_jobs - 1;      // last j with item_offs[j] <= gi
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (G.item_offs[mid] <= gi) lo = mid;
+                else hi = mid - 1;
+            }
+            jb = lo;
+            base = G.item_offs[jb] - G.item_base;
+            first = G.pid_begin[jb];
+        }
+        p.job = jb;
+        *pid_out = (uint32_t)(first + ((int64_t)idx - base));
+    } else {
+        const uint32_t meta = G.qin.meta[idx];
+        p.sp = (int32_t)(meta & 3u);
+        p.ir = (int32_t)((meta >> 2) & 0x7FFu);
+        p.iz = (int32_t)(meta >> 13);
+        p.x = (Real)G.qin.x[idx];
+        p.y = (Real)G.qin.y[idx];
+        p.z = (Real)G.qin.z[idx];
+        p.u = (Real)G.qin.u[idx];
+        p.v = (Real)G.qin.v[idx];
+        p.w = (Real)G.qin.w[idx];
+        p.e = (Real)G.qin.e[idx];
+        p.lin = G.qin.lin[idx];
+        p.pid = G.qin.pid[idx];
+        p.job = kBatched ? (int32_t)G.qin.job[idx] : 0;
+    }
+}
+
+// One unit of work for a lane: start its fetched particle, or move it by one flight segment.
+template <typename Real>
+__device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, const GenArgs& G,
+                                        Part<Real>& p, LaneCnt& lc) {
+    if (p.start) {
+        p.start = false;
+        if (G.mode == 0) {
+            birth(J, L, p.pid, p, lc);
+            lc.e_prim += (double)p.e;
+            if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 0], (double)p.e);
+        }
+        start_particle(J, L, p, lc);
+    } else {
+        step(J, L, G, p, lc);
+    }
+}
+
 #ifndef KARL_WAVES_PER_SIMD
 #define KARL_WAVES_PER_SIMD 1
 #endif
-__global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(const DevJob J, const GenArgs G) {
+
+// kBatched = false: one job (jobs[0]); its tables are staged in LDS and its event counters
+// reduced in LDS.  kBatched = true: every lane carries a job index; the lanes of a wave are
+// served job by job (one pass per distinct job, normally one) so that the job's parameters are
+// read with scalar loads.
+template <typename Real, bool kBatched>
+__global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
+    const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    unsigned long long* s_cnt = (unsigned long long*)lds_raw;
-    double* s_led = (double*)(lds_raw + kNCnt * 8);
-    int32_t* s_pidx = (int32_t*)(lds_raw + (kNCnt + kNLed) * 8);   // [2][16] then kind[16]
-    int32_t* s_kind = s_pidx + 2 * KARL_MAX_PROC;
-    int32_t* s_tgt = s_kind + KARL_MAX_PROC;
-    Real* s_eth = (Real*)(s_tgt + KARL_MAX_PROC);
-    Real* s_xs = s_eth + KARL_MAX_PROC;
-    Real* s_ngas = s_xs + (size_t)J.n_proc * J.n_e;
-    Real* s_zf = s_ngas + J.n_z;
-    Real* s_rf = s_zf + (J.n_z + 1);
-
     const int tid = threadIdx.x;
-    for (int i = tid; i < kNCnt; i += blockDim.x) s_cnt[i] = 0ull;
-    for (int i = tid; i < kNLed; i += blockDim.x) s_led[i] = 0.0;
-    for (int i = tid; i < 2 * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
-    for (int i = tid; i < KARL_MAX_PROC; i += blockDim.x) {
-        s_kind[i] = J.kind[i];
-        s_tgt[i] = J.target[i];
-        s_eth[i] = (Real)J.e_th[i];
+    Lds<Real> L0;
+    if (!kBatched) {
+        const DevJob& J = jobs[0];
+        unsigned long long* s_cnt = (unsigned long long*)lds_raw;
+        double* s_led = (double*)(lds_raw + kNCnt * 8);
+        int32_t* s_pidx = (int32_t*)(lds_raw + (kNCnt + kNLed) * 8);
+        int32_t* s_kind = s_pidx + 2 * KARL_MAX_PROC;
+        int32_t* s_tgt = s_kind + KARL_MAX_PROC;
+        Real* s_eth = (Real*)(s_tgt + KARL_MAX_PROC);
+        Real* s_xs = s_eth + KARL_MAX_PROC;
+        Real* s_ngas = s_xs + (size_t)J.n_proc * J.n_e;
+        Real* s_zf = s_ngas + J.n_z;
+        Real* s_rf = s_zf + (J.n_z + 1);
+        for (int i = tid; i < kNCnt; i += blockDim.x) s_cnt[i] = 0ull;
+        for (int i = tid; i < kNLed; i += blockDim.x) s_led[i] = 0.0;
+        for (int i = tid; i < 2 * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
+        for (int i = tid; i < KARL_MAX_PROC; i += blockDim.x) {
+            s_kind[i] = J.kind[i];
+            s_tgt[i] = J.target[i];
+            s_eth[i] = (Real)J.e_th[i];
+        }
+        const Real* g_xs = (const Real*)J.xs;
+        for (int i = tid; i < J.n_proc * J.n_e; i += blockDim.x) s_xs[i] = g_xs[i];
+        const Real* g_ngas = (const Real*)J.n_gas;
+        for (int i = tid; i < J.n_z; i += blockDim.x) s_ngas[i] = g_ngas[i];
+        const Real* g_zf = (const Real*)J.zf;
+        for (int i = tid; i <= J.n_z; i += blockDim.x) s_zf[i] = g_zf[i];
+        const Real* g_rf = (const Real*)J.rf;
+        for (int i = tid; i <= J.n_r; i += blockDim.x) s_rf[i] = g_rf[i];
+        __syncthreads();
+        L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf};
     }
-    const Real* g_xs = (const Real*)J.xs;
-    for (int i = tid; i < J.n_proc * J.n_e; i += blockDim.x) s_xs[i] = g_xs[i];
-    const Real* g_ngas = (const Real*)J.n_gas;
-    for (int i = tid; i < J.n_z; i += blockDim.x) s_ngas[i] = g_ngas[i];
-    const Real* g_zf = (const Real*)J.zf;
-    for (int i = tid; i <= J.n_z; i += blockDim.x) s_zf[i] = g_zf[i];
-    const Real* g_rf = (const Real*)J.rf;
-    for (int i = tid; i <= J.n_r; i += blockDim.x) s_rf[i] = g_rf[i];
-    __syncthreads();
 
-    Lds<Real> L{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf};
-    LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    uint32_t n_redraw = 0u, n_beb = 0u, n_beta = 0u;
-    double e_prim = 0.0;
+    LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
+    int lc_job = 0;
     Part<Real> p;
     p.alive = false;
+    p.start = false;
+    p.job = 0;
     bool done = false;
     for (;;) {
-        const bool need = !p.alive && !done;
+        const bool need = !p.alive && !p.start && !done;
         if (__ballot(need)) {
             const unsigned long long idx = wave_reserve(G.fetch, need);
             if (need) {
                 if (idx < (unsigned long long)G.n_items) {
-                    if (G.mode == 0) {
-                        const uint32_t pid = (uint32_t)(G.pid_begin + (int64_t)idx);
-                        birth(J, L, pid, p, &n_beta);
-                        e_prim += (double)p.e;
-                        if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)pid * KARL_NHIST + 0], (double)p.e);
-                    } else {
-                        const uint32_t meta = G.qin.meta[idx];
-                        p.sp = (int32_t)(meta & 3u);
-                        p.ir = (int32_t)((meta >> 2) & 0x7FFu);
-                        p.iz = (int32_t)(meta >> 13);
-                        p.x = (Real)G.qin.x[idx];
-                        p.y = (Real)G.qin.y[idx];
-                        p.z = (Real)G.qin.z[idx];
-                        p.u = (Real)G.qin.u[idx];
-                        p.v = (Real)G.qin.v[idx];
-                        p.w = (Real)G.qin.w[idx];
-                        p.e = (Real)G.qin.e[idx];
-                        p.lin = G.qin.lin[idx];
-                        p.pid = G.qin.pid[idx];
-                    }
-                    start_particle(J, L, p, lc);
+                    uint32_t pid = 0u;
+                    fetch_item<Real, kBatched>(G, idx, p, &pid);
+                    if (G.mode == 0) p.pid = pid;
+                    p.start = true;
                 } else {
                     done = true;
                 }
             }
         }
         if (!__ballot(!done)) break;
-        if (p.alive) step(J, L, G, p, lc, &n_redraw, &n_beb);
+        if (!kBatched) {
+            if (p.alive || p.start) advance(jobs[0], L0, G, p, lc);
+        } else {
+            bool todo = p.alive || p.start;
+            for (;;) {
+                const unsigned long long m = __ballot(todo);
+                if (!m) break;
+                const int leader = __ffsll((long long)m) - 1;
+                const int j0 = __shfl(p.job, leader);
+                if (todo && p.job == j0) {
+                    const int ju = __builtin_amdgcn_readfirstlane(p.job);
+                    const DevJob& J = jobs[ju];
+                    if (lc_job != ju) {
+                        flush_lane(lc, jobs[lc_job].counters, jobs[lc_job].ledger);
+                        lc_job = ju;
+                    }
+                    advance(J, global_view<Real>(J), G, p, lc);
+                    todo = false;
+                }
+            }
+        }
     }
 
-    // per-lane counters -> LDS -> HBM
-    atomicAdd(&s_cnt[KARL_C_STEP + 0], (unsigned long long)lc.step0);
-    atomicAdd(&s_cnt[KARL_C_STEP + 1], (unsigned long long)lc.step1);
-    atomicAdd(&s_cnt[KARL_C_COLL + 0], (unsigned long long)lc.coll0);
-    atomicAdd(&s_cnt[KARL_C_COLL + 1], (unsigned long long)lc.coll1);
-    atomicAdd(&s_cnt[KARL_C_ZCROSS + 0], (unsigned long long)lc.zc0);
-    atomicAdd(&s_cnt[KARL_C_ZCROSS + 1], (unsigned long long)lc.zc1);
-    atomicAdd(&s_cnt[KARL_C_RCROSS + 0], (unsigned long long)lc.rc0);
-    atomicAdd(&s_cnt[KARL_C_RCROSS + 1], (unsigned long long)lc.rc1);
-    atomicAdd(&s_cnt[KARL_C_TARGET_REDRAW], (unsigned long long)n_redraw);
-    atomicAdd(&s_cnt[KARL_C_BEB_TRIES], (unsigned long long)n_beb);
-    atomicAdd(&s_cnt[KARL_C_BETA_TRIES], (unsigned long long)n_beta);
-    if (e_prim != 0.0) atomicAdd(&s_led[KARL_L_E_PRIMARY], e_prim);
-    __syncthreads();
-    for (int i = tid; i < kNCnt; i += blockDim.x)
-        if (s_cnt[i]) add_u64(&J.counters[i], s_cnt[i]);
-    for (int i = tid; i < kNLed; i += blockDim.x)
-        if (s_led[i] != 0.0) add_f64(&J.ledger[i], s_led[i]);
+    if (!kBatched) {
+        flush_lane(lc, L0.cnt, L0.led);
+        __syncthreads();
+        const DevJob& J = jobs[0];
+        for (int i = tid; i < kNCnt; i += blockDim.x)
+            if (L0.cnt[i]) add_u64(&J.counters[i], L0.cnt[i]);
+        for (int i = tid; i < kNLed; i += blockDim.x)
+            if (L0.led[i] != 0.0) add_f64(&J.ledger[i], L0.led[i]);
+    } else {
+        flush_lane(lc, jobs[lc_job].counters, jobs[lc_job].ledger);
+    }
 }
 
 // Normalised fields (Sec. 2.2 eq. 3 with t_sim = N_prim / activity, eq. 4; Sec. 2.3 currents):
@@ -1145,14 +1242,25 @@ size_t lds_bytes(const DevJob& j, int precision) {
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_transport(const DevJob& j, const GenArgs& g, int precision, int grid, int block,
-                            size_t lds, hipStream_t s) {
-    if (precision == KARL_FP32)
-        hipLaunchKernelGGL(transport_kernel<float>, dim3(grid), dim3(block), lds, s, j, g);
-    else
-        hipLaunchKernelGGL(transport_kernel<double>, dim3(grid), dim3(block), lds, s, j, g);
+hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool batched,
+                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            hipStream_t s) {
+    (void)job0;
+    if (precision == KARL_FP32) {
+        if (batched)
+            hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    } else {
+        if (batched)
+            hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<double, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    }
     return hipGetLastError();
 }
+
+size_t batched_lds_bytes() { return 0; }
 
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s) {
@@ -1172,10 +1280,15 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int precision, int block, size_t lds, int* blocks_per_cu) {
-    if (precision == KARL_FP32)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float>, block, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double>, block, lds);
+hipError_t transport_occupancy(int precision, bool batched, int block, size_t lds, int* blocks_per_cu) {
+    if (precision == KARL_FP32) {
+        if (batched)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false>, block, lds);
+    }
+    if (batched)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false>, block, lds);
 }
 
 }  // namespace karl

@@ -30,7 +30,8 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
                 "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_destroy_job",
-                "karl_last_error"]
+                "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
+                "karl_batch_stats", "karl_destroy_batch", "karl_last_error"]
 
 
 class KarlError(RuntimeError):
@@ -96,6 +97,14 @@ def lib():
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.karl_destroy_job.argtypes = [C.c_void_p]
+        L.karl_batch_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_uint64)]
+        L.karl_create_batch.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_uint64,
+                                        C.POINTER(C.c_void_p)]
+        L.karl_transport_batch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                           C.c_int32, C.c_void_p]
+        L.karl_batch_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.karl_destroy_batch.argtypes = [C.c_void_p]
         for name in ENTRY_POINTS[:-1]:
             getattr(L, name).restype = C.c_int32
         L.karl_last_error.argtypes = []
@@ -256,6 +265,49 @@ class Job:
     def close(self):
         if getattr(self, "h", None):
             check(lib().karl_destroy_job(self.h))
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Secondary queues and job table for launches over many jobs (workspace from torch)."""
+
+    def __init__(self, max_jobs: int, queue_capacity: int = 0, device=None):
+        import torch
+        n = C.c_uint64(0)
+        check(lib().karl_batch_workspace_bytes(int(max_jobs), int(queue_capacity), C.byref(n)))
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.max_jobs = max_jobs
+        self.nbytes = int(n.value)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib().karl_create_batch(int(max_jobs), int(queue_capacity), self.workspace.data_ptr(),
+                                          self.nbytes, C.byref(h)))
+        self.h = h
+
+    def transport(self, jobs, ranges, stream=None):
+        """Transport ranges[i] = (begin, end) of jobs[i] in one sequence of launches."""
+        n = len(jobs)
+        handles = (C.c_void_p * max(n, 1))(*[j.h for j in jobs])
+        flat = (C.c_int64 * max(2 * n, 1))(*[int(x) for r in ranges for x in r])
+        check(lib().karl_transport_batch(self.h, handles, flat, n, Job._stream(stream)))
+
+    def stats(self) -> Dict[str, float]:
+        ms, n, g, q = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().karl_batch_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
+        return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
+                "max_queue": q.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib().karl_destroy_batch(self.h))
             self.h = None
         self.workspace = None
 

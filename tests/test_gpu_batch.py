@@ -1,0 +1,94 @@
+"""Batched launches: many jobs of uneven size in one sequence of launches.  Each job's
+result must be the same as alone (integer tallies exactly) and as the oracle's."""
+import numpy as np
+import pytest
+
+from paper_2503_10263_amd import workloads as W
+from parity_util import compare_tallies, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import oracle
+    oracle.build(force=False)
+
+
+def _jobs():
+    ws = W.cfg_batched(n_jobs=12, scale=0.002)
+    for i, w in enumerate(ws):
+        w.n_primaries = min(max(w.n_primaries, 3 + 17 * i), 300)
+    ws[3].n_r, ws[3].n_z = 4, 8
+    ws[3].n_gas = np.full(8, ws[3].n_gas[0])
+    ws[3].planes = [0, 4, 8]
+    return ws
+
+
+def test_batch_equals_alone_and_oracle():
+    from paper_2503_10263_amd import karl
+    ws = _jobs()
+    jobs = [karl.Job(w, digests=True, queue_capacity=1 << 14) for w in ws]
+    batch = karl.Batch(max_jobs=16, queue_capacity=1 << 16)
+    ranges = [(0, w.n_primaries) for w in ws]
+    batch.transport(jobs, ranges)
+    st = batch.stats()
+    assert st["launches"] >= 1
+    for w, job in zip(ws, jobs):
+        g = job.read_tallies()
+        alone, _ = run_gpu(w, [(0, w.n_primaries)], digests=True)
+        o = run_oracle(w, [(0, w.n_primaries)], digests=True)
+        np.testing.assert_array_equal(g["digests"], alone["digests"])
+        np.testing.assert_array_equal(g["digests"], o["digests"])
+        compare_tallies(g, o, abs(o["ledger"][0]))
+        job.close()
+    batch.close()
+
+
+def test_batch_overflow_retry_and_partial_ranges():
+    """A tiny batch queue forces overflow retries across job boundaries; sub-ranges of jobs
+    accumulate like single-job transports."""
+    from paper_2503_10263_amd import karl
+    ws = _jobs()[:5]
+    jobs = [karl.Job(w, queue_capacity=1 << 12) for w in ws]
+    batch = karl.Batch(max_jobs=8, queue_capacity=96)
+    half = [(0, w.n_primaries // 2) for w in ws]
+    rest = [(w.n_primaries // 2, w.n_primaries) for w in ws]
+    batch.transport(jobs, half)
+    batch.transport(jobs[::-1], rest[::-1])
+    for w, job in zip(ws, jobs):
+        g = job.read_tallies()
+        o = run_oracle(w, [(0, w.n_primaries)])
+        compare_tallies(g, o, abs(o["ledger"][0]))
+        job.close()
+    batch.close()
+
+
+def test_fp32_batch_matches_fp32_alone():
+    from paper_2503_10263_amd import karl
+    ws = _jobs()[:6]
+    jobs = [karl.Job(w, precision="fp32", queue_capacity=1 << 14) for w in ws]
+    batch = karl.Batch(max_jobs=6, queue_capacity=1 << 16)
+    batch.transport(jobs, [(0, w.n_primaries) for w in ws])
+    for w, job in zip(ws, jobs):
+        g = job.read_tallies()
+        alone, _ = run_gpu(w, [(0, w.n_primaries)], precision="fp32")
+        for k in ["counters", "recomb", "jz", "jr", "spectra"]:
+            np.testing.assert_array_equal(g[k], alone[k], err_msg=k)
+        job.close()
+    batch.close()
+
+
+def test_batch_rejects_mixed_precision():
+    from paper_2503_10263_amd import karl
+    ws = _jobs()[:2]
+    a = karl.Job(ws[0], queue_capacity=1024)
+    b = karl.Job(ws[1], precision="fp32", queue_capacity=1024)
+    batch = karl.Batch(max_jobs=2, queue_capacity=1024)
+    with pytest.raises(karl.KarlError) as ei:
+        batch.transport([a, b], [(0, 1), (0, 1)])
+    assert ei.value.code == karl.EINVAL
+    a.close(), b.close(), batch.close()
