@@ -231,6 +231,13 @@ struct Launcher {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int64_t launches = 0, generations = 0, max_queue = 0;
+    // batched launches: per-job item ranges, fetch counters and the queue sort's scratch
+    int32_t n_jobs = 1;
+    int64_t* job_first = nullptr;
+    int64_t* job_count = nullptr;
+    unsigned long long* job_fetch = nullptr;
+    unsigned long long* sort_counts = nullptr;
+    unsigned long long* sort_cursor = nullptr;
 
     karl_status init(char* queues, size_t entries, unsigned long long* control, int prec,
                      bool is_batched, size_t lds_bytes) {
@@ -300,10 +307,22 @@ struct Launcher {
                 ndef = 0;
                 HIP_CHECK(karl::launch_fill_u64(dcount + di, 1, 0ull, s));
             }
+            if (batched && mode == 1) {
+                // group the input by job (into the free generation buffer) so that waves can
+                // work through one job at a time; the output then reuses buffer 0
+                HIP_CHECK(karl::launch_sort_by_job(*in, q[1], items, n_jobs, sort_counts, job_first,
+                                                   job_count, sort_cursor, s));
+                in = &q[1];
+                mo = 0;
+            }
             karl::GenArgs g = base;
             g.mode = mode;
+            g.n_jobs = batched ? n_jobs : 1;
             g.n_items = items;
             g.fetch = fetch;
+            g.job_first = job_first;
+            g.job_count = job_count;
+            g.job_fetch = job_fetch;
             g.qin = *in;
             g.qout = q[mo];
             g.qout_count = qcount;
@@ -312,6 +331,7 @@ struct Launcher {
             g.capacity = capacity;
             g.status = (unsigned int*)(ctl + 2);
             HIP_CHECK(karl::launch_fill_u64(fetch, 2, 0ull, s));
+            if (batched) HIP_CHECK(karl::launch_fill_u64(job_fetch, (size_t)n_jobs, 0ull, s));
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > max_blocks) blocks = max_blocks;
             HIP_CHECK(hipEventRecord(ev0, s));
@@ -338,7 +358,7 @@ struct Launcher {
             max_queue = std::max(max_queue, std::max(items, ndef));
             mode = 1;
             in = &q[mo];
-            mo ^= 1;
+            if (!batched) mo ^= 1;
         }
         return KARL_OK;
     }
@@ -382,17 +402,18 @@ struct Job {
 struct Batch {
     int32_t max_jobs = 0;
     char* ws = nullptr;
-    int64_t* item_offs = nullptr;   // device [max_jobs+1]
-    int64_t* pid_begin = nullptr;   // device [max_jobs]
-    int64_t* host_i64 = nullptr;    // pinned staging [2*max_jobs+1]
+    int64_t* job_first = nullptr;   // device [max_jobs]
+    int64_t* job_count = nullptr;   // device [max_jobs]
+    int64_t* host_i64 = nullptr;    // pinned staging [2*max_jobs]
     karl::DevJob* host_jobs = nullptr;   // pinned staging of the job table
     Launcher run[2];                // FP64 and FP32 launchers share the queues
     int64_t chunk = kDefaultChunk;
     int device = 0;
 };
 
-size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o_offs,
-                    size_t* o_pid, size_t* o_ctl, size_t* o_queues) {
+// job table, per-job first/count/fetch, sort counts and cursors, control words, four queues
+size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o_perjob,
+                    size_t* o_ctl, size_t* o_queues) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -400,8 +421,7 @@ size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o
         return o;
     };
     *o_jobs = take(sizeof(karl::DevJob) * (size_t)max_jobs);
-    *o_offs = take(8 * ((size_t)max_jobs + 1));
-    *o_pid = take(8 * (size_t)max_jobs);
+    *o_perjob = take(5 * 8 * (size_t)max_jobs);
     *o_ctl = take(kControlBytes);
     *o_queues = take(4 * (size_t)entries * kQueueEntryBytes);
     return off;
@@ -755,8 +775,8 @@ karl_status karl_destroy_job(void* job) {
 karl_status karl_batch_workspace_bytes(int32_t max_jobs, int64_t queue_capacity, uint64_t* bytes) {
     if (!bytes || max_jobs < 1 || queue_capacity < 0)
         return fail(KARL_EINVAL, "need max_jobs >= 1, queue_capacity >= 0 and a result pointer");
-    size_t a, b, c, d, e;
-    *bytes = batch_layout(max_jobs, queue_capacity > 0 ? queue_capacity : kDefaultCapacity, &a, &b, &c, &d, &e);
+    size_t a, b, c, d;
+    *bytes = batch_layout(max_jobs, queue_capacity > 0 ? queue_capacity : kDefaultCapacity, &a, &b, &c, &d);
     return KARL_OK;
 }
 
@@ -768,16 +788,17 @@ karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* wo
     if (max_jobs < 1 || queue_capacity < 0) return fail(KARL_EINVAL, "need max_jobs >= 1 and queue_capacity >= 0");
     if (!workspace) return fail(KARL_EINVAL, "workspace is NULL");
     const int64_t entries = queue_capacity > 0 ? queue_capacity : kDefaultCapacity;
-    size_t o_jobs, o_offs, o_pid, o_ctl, o_q;
-    const size_t need = batch_layout(max_jobs, entries, &o_jobs, &o_offs, &o_pid, &o_ctl, &o_q);
+    size_t o_jobs, o_pj, o_ctl, o_q;
+    const size_t need = batch_layout(max_jobs, entries, &o_jobs, &o_pj, &o_ctl, &o_q);
     if (workspace_bytes < need)
         return fail(KARL_ENOMEM, "batch workspace has %llu bytes, needs %llu",
                     (unsigned long long)workspace_bytes, (unsigned long long)need);
     Batch* b = new Batch();
     b->max_jobs = max_jobs;
     b->ws = (char*)workspace;
-    b->item_offs = (int64_t*)(b->ws + o_offs);
-    b->pid_begin = (int64_t*)(b->ws + o_pid);
+    int64_t* pj = (int64_t*)(b->ws + o_pj);
+    b->job_first = pj;
+    b->job_count = pj + max_jobs;
     auto cleanup = [&](karl_status s) {
         b->run[0].release();
         b->run[1].release();
@@ -793,8 +814,13 @@ karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* wo
                                         true, karl::batched_lds_bytes());
         if (st != KARL_OK) return cleanup(st);
         b->run[p].jobs_dev = (karl::DevJob*)(b->ws + o_jobs);
+        b->run[p].job_first = pj;
+        b->run[p].job_count = pj + max_jobs;
+        b->run[p].job_fetch = (unsigned long long*)(pj + 2 * (size_t)max_jobs);
+        b->run[p].sort_counts = (unsigned long long*)(pj + 3 * (size_t)max_jobs);
+        b->run[p].sort_cursor = (unsigned long long*)(pj + 4 * (size_t)max_jobs);
     }
-    if (hipHostMalloc((void**)&b->host_i64, 8 * (2 * (size_t)max_jobs + 1), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&b->host_i64, 8 * (2 * (size_t)max_jobs), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->host_jobs, sizeof(karl::DevJob) * (size_t)max_jobs, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(KARL_EDEVICE, "pinned staging allocation failed"));
     *out = b;
@@ -810,7 +836,7 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
     if (n_jobs == 0) return KARL_OK;
     if (!jobs || !ranges) return fail(KARL_EINVAL, "jobs or ranges is NULL");
     const int prec = ((Job*)jobs[0])->precision;
-    int64_t total = 0;
+    std::vector<int64_t> offs(n_jobs + 1, 0);      // items of job i: [offs[i], offs[i+1])
     for (int32_t i = 0; i < n_jobs; ++i) {
         Job* j = (Job*)jobs[i];
         if (!j) return fail(KARL_ESTATE, "job %d is NULL", i);
@@ -821,34 +847,34 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
         if (b < 0 || e < b || e > j->n_primaries)
             return fail(KARL_EINVAL, "job %d: pid range [%lld, %lld) invalid", i, (long long)b, (long long)e);
         B->host_jobs[i] = j->dj;
-        B->host_i64[i] = total;                     // item_offs
-        B->host_i64[n_jobs + 1 + i] = b;            // pid_begin
-        total += e - b;
+        offs[i + 1] = offs[i] + (e - b);
     }
-    B->host_i64[n_jobs] = total;
+    const int64_t total = offs[n_jobs];
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(hipSetDevice(B->device));
     Launcher& R = B->run[prec == KARL_FP32 ? 1 : 0];
+    R.n_jobs = n_jobs;
     HIP_CHECK(hipMemcpyAsync(R.jobs_dev, B->host_jobs, sizeof(karl::DevJob) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(B->item_offs, B->host_i64, 8 * ((size_t)n_jobs + 1), hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(B->pid_begin, B->host_i64 + n_jobs + 1, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
-    std::vector<int64_t> offs(B->host_i64, B->host_i64 + n_jobs + 1);
     int64_t c0 = 0;
     while (c0 < total) {
         const int64_t n = std::min<int64_t>(B->chunk, total - c0);
-        // jobs touched by items [c0, c0+n): snapshot their tallies for an overflow retry
+        // the chunk's primaries per job: first id and count
         const int j_lo = (int)(std::upper_bound(offs.begin(), offs.end(), c0) - offs.begin()) - 1;
         const int j_hi = (int)(std::lower_bound(offs.begin(), offs.end(), c0 + n) - offs.begin());
+        for (int i = 0; i < n_jobs; ++i) {
+            const int64_t lo = std::max(c0, offs[i]), hi = std::min(c0 + n, offs[i + 1]);
+            B->host_i64[i] = ranges[2 * i] + (lo - offs[i]);
+            B->host_i64[n_jobs + i] = hi > lo ? hi - lo : 0;
+        }
+        HIP_CHECK(hipMemcpyAsync(B->job_first, B->host_i64, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(B->job_count, B->host_i64 + n_jobs, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+        // snapshot the tallies of the jobs in the chunk for an overflow retry
         for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
             Job* j = (Job*)jobs[i];
             HIP_CHECK(hipMemcpyAsync(j->ws + j->lay.snapshot, j->ws + j->lay.tallies, j->lay.tally_bytes,
                                      hipMemcpyDeviceToDevice, s));
         }
         karl::GenArgs g{};
-        g.n_jobs = n_jobs;
-        g.item_base = c0;
-        g.item_offs = B->item_offs;
-        g.pid_begin = B->pid_begin;
         bool overflow = false;
         int64_t max_gen = 0;
         karl_status st = R.run(g, n, s, &overflow, &max_gen);

@@ -87,9 +87,12 @@ struct GenArgs {
     int32_t n_jobs;
     int64_t n_items;
     int64_t pid_begin0;            // single-job launches: id of item 0
-    int64_t item_base;             // batched launches: item i is item item_base + i of the batch
-    const int64_t* item_offs;      // [n_jobs+1] (batched mode 0)
-    const int64_t* pid_begin;      // [n_jobs]   (batched mode 0)
+    // batched launches: the items of job j are job_count[j] consecutive items starting at
+    // job_first[j] -- the first primary id (mode 0) or the first entry of the job-sorted queue
+    // (mode 1); each wave fetches from one job at a time through job_fetch[j]
+    const int64_t* job_first;
+    const int64_t* job_count;
+    unsigned long long* job_fetch;
     unsigned long long* fetch;
     QueueSoA qin;
     QueueSoA qout;
@@ -108,6 +111,10 @@ hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool bat
                             hipStream_t s);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
+// Regroup n queue entries by job: count per job, exclusive scan into first/count, scatter.
+hipError_t launch_sort_by_job(const QueueSoA& in, const QueueSoA& out, int64_t n, int32_t n_jobs,
+                              unsigned long long* counts, int64_t* first, int64_t* count,
+                              unsigned long long* cursor, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
                            hipStream_t s);
 hipError_t transport_occupancy(int precision, bool batched, int block, size_t lds,

@@ -282,6 +282,7 @@ struct Lds {
     const Real* ngas;          // [n_z]
     const Real* zf;            // [n_z+1]
     const Real* rf;            // [n_r+1]
+    bool direct;               // per-event counts go straight to cnt (wave-aggregated)
 };
 
 // Per-lane event counts of one job, added to that job's counters when the lane moves to
@@ -290,6 +291,31 @@ struct LaneCnt {
     uint32_t step0, step1, coll0, coll1, zc0, zc1, rc0, rc1, redraw, beb, beta;
     double e_prim;
 };
+
+// Count one event of kind idx + sp: in a per-lane register, or -- when the lane's counters are
+// not kept per lane -- with one LDS atomic per distinct key of the wave.
+template <typename Real>
+__device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int idx, int sp) {
+    if (L.direct) {
+        wave_count(L.cnt, idx + sp);
+        return;
+    }
+    switch (idx) {
+        case KARL_C_STEP: if (sp) ++lc.step1; else ++lc.step0; break;
+        case KARL_C_COLL: if (sp) ++lc.coll1; else ++lc.coll0; break;
+        case KARL_C_ZCROSS: if (sp) ++lc.zc1; else ++lc.zc0; break;
+        default: if (sp) ++lc.rc1; else ++lc.rc0; break;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void count_n(const Lds<Real>& L, uint32_t& reg, int idx, uint32_t n) {
+    if (L.direct) {
+        if (n) atomicAdd(&L.cnt[idx], (unsigned long long)n);
+    } else {
+        reg += n;
+    }
+}
 
 __device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt, double* led) {
     const uint32_t v[11] = {lc.step0, lc.step1, lc.coll0, lc.coll1, lc.zc0, lc.zc1, lc.rc0, lc.rc1,
@@ -343,8 +369,9 @@ __device__ void kill(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int rea
 }
 
 template <typename Real>
-__device__ __forceinline__ void cross_r(const DevJob& J, Part<Real>& p, LaneCnt& lc, int f, int dir) {
-    if (p.sp) ++lc.rc1; else ++lc.rc0;
+__device__ __forceinline__ void cross_r(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc,
+                                       int f, int dir) {
+    count_ev(L, lc, KARL_C_RCROSS, p.sp);
     add_u64(&J.jr[(((size_t)p.sp * (J.n_r + 1) + (size_t)f) * J.n_z + (size_t)p.iz) * 2 + (size_t)dir], 1ull);
     ev(p, 4u, (uint32_t)dir, (uint32_t)(f * J.n_z + p.iz), (J.flags & KARL_FLAG_DIGESTS) != 0);
 }
@@ -378,9 +405,9 @@ __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneC
     } else if (nir != p.ir) {
         flush_time(J, p);
         if (nir > p.ir) {
-            for (int f = p.ir + 1; f <= nir; ++f) cross_r(J, p, lc, f, 1);
+            for (int f = p.ir + 1; f <= nir; ++f) cross_r(J, L, p, lc, f, 1);
         } else {
-            for (int f = p.ir; f > nir; --f) cross_r(J, p, lc, f, 0);
+            for (int f = p.ir; f > nir; --f) cross_r(J, L, p, lc, f, 0);
         }
         p.ir = nir;
     }
@@ -582,7 +609,7 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     g[2] = v[2] - V[2];
     Real er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     for (uint32_t r = 1; er < B && r <= 15u; ++r) {
-        lc.redraw += 1u;
+        count_n(L, lc.redraw, KARL_C_TARGET_REDRAW, 1u);
         thermal(J, p, 136u + 2u * r, 137u + 2u * r, V);
         g[0] = v[0] - V[0];
         g[1] = v[1] - V[1];
@@ -597,7 +624,9 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
         er = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * ef2;
     }
     const Real t = er / B;
-    const Real w = beb_sample(J, p, t, &lc.beb);
+    uint32_t tries = 0u;
+    const Real w = beb_sample(J, p, t, &tries);
+    count_n(L, lc.beb, KARL_C_BEB_TRIES, tries);
     const Real W = w * B;
     Real ef = er - B - W;
     if (ef < (Real)0) ef = (Real)0;
@@ -752,7 +781,7 @@ __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Re
     for (uint32_t j = 0; j < 64u; ++j) {
         const Pair<Real> q = draw<Real>(J.seed, pid, 0ull, kBIRTH_STEP, 3u + j);
         e = e0 * (q.d0 + Prec<Real>::eps);
-        lc.beta += 1u;
+        count_n(L, lc.beta, KARL_C_BETA_TRIES, 1u);
         if (q.d1 * fmax_ < beta_shape(e, e0, bz)) break;
     }
     p.e = e;
@@ -779,7 +808,7 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     if (!(p.vel > (Real)0)) { kill(J, L, p, KARL_LIFETIME); return; }
     if (J.gc) {
         if (gc_set(J, L, p, lc, p.x, p.y, true)) {
-            cross_r(J, p, lc, J.n_r, 1);
+            cross_r(J, L, p, lc, J.n_r, 1);
             kill(J, L, p, KARL_WALL);
         }
     }
@@ -790,7 +819,9 @@ template <typename Real>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
-    const int sp = p.sp;
+    // batched launches serve the lanes of a wave by (job, species): the species is uniform and
+    // the process metadata below become scalar loads
+    const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
     // cross sections at the current energy, rates in the current cell (eq. 1)
     const Real exs = p.e * (Real)sel2(sp, J.gfrac[0], J.gfrac[1]);
     const Real xl = klog(exs * (Real)sel2(sp, J.inv_emin[0], J.inv_emin[1])) *
@@ -883,7 +914,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         p.y += l * p.v;
         p.z += l * p.w;
     }
-    if (sp) ++lc.step1; else ++lc.step0;
+    count_ev(L, lc, KARL_C_STEP, sp);
 
     if (dist < sg) {
         // ---- interaction, chosen with weight sigma_i n_i (Sec. 2.1) ----
@@ -905,7 +936,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         }
         if (sel < 0) sel = last;
         const int pi = pidx[sel];
-        if (sp) ++lc.coll1; else ++lc.coll0;
+        count_ev(L, lc, KARL_C_COLL, sp);
         wave_count(L.cnt, KARL_C_PROC + pi);
         p.n_int += 1;
         ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), dig);
@@ -950,7 +981,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
             else if (J.gc) {
                 if (gc_set(J, L, p, lc, xc, yc, false)) {
-                    cross_r(J, p, lc, J.n_r, 1);
+                    cross_r(J, L, p, lc, J.n_r, 1);
                     kill(J, L, p, KARL_WALL);
                 }
             }
@@ -961,7 +992,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         const int dir = (p.w > (Real)0) ? 1 : 0;
         p.z = L.zf[fz];
         flush_time(J, p);
-        if (sp) ++lc.zc1; else ++lc.zc0;
+        count_ev(L, lc, KARL_C_ZCROSS, sp);
         add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)p.ir) * (J.n_z + 1) + (size_t)fz) * 2 + (size_t)dir], 1ull);
         ev(p, 3u, (uint32_t)dir, (uint32_t)(p.ir * (J.n_z + 1) + fz), dig);
         const int pl = J.plane_of[fz];
@@ -997,7 +1028,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             p.y = p.y * sc;
         }
         flush_time(J, p);
-        cross_r(J, p, lc, fr, out);
+        cross_r(J, L, p, lc, fr, out);
         if (fr == J.n_r) kill(J, L, p, KARL_WALL);
         else p.ir = out ? fr : fr - 1;
     }
@@ -1017,47 +1048,114 @@ template <> struct EthOf<float> {
 // Tables and counters of a job read directly from HBM (batched launches: the lanes of a
 // workgroup may work for different jobs; the tables stay resident in L2).
 template <typename Real>
-__device__ __forceinline__ Lds<Real> global_view(const DevJob& J) {
-    return Lds<Real>{J.counters, J.ledger, &J.pidx[0][0], J.kind, J.target, EthOf<Real>::get(J),
-                     (const Real*)J.xs, (const Real*)J.n_gas, (const Real*)J.zf, (const Real*)J.rf};
+__device__ __forceinline__ Lds<Real> global_view(const DevJob& J, unsigned long long* cnt, double* led) {
+    return Lds<Real>{cnt, led, &J.pidx[0][0], J.kind, J.target, EthOf<Real>::get(J),
+                     (const Real*)J.xs, (const Real*)J.n_gas, (const Real*)J.zf, (const Real*)J.rf,
+                     true};
 }
 
-// Load the fetched work item into the lane: a primary (born from its id) or a queued particle.
-template <typename Real, bool kBatched>
-__device__ __forceinline__ void fetch_item(const GenArgs& G, unsigned long long idx, Part<Real>& p,
-                                           uint32_t* pid_out) {
-    if (G.mode == 0) {
-        int jb = 0;
-        int64_t base = 0, first = G.pid_begin0;
-        if (kBatched) {
-            const int64_t gi = G.item_base + (int64_t)idx;
-            int lo = 0, hi = G.n_jobs - 1;      // last j with item_offs[j] <= gi
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (G.item_offs[mid] <= gi) lo = mid;
-                else hi = mid - 1;
-            }
-            jb = lo;
-            base = G.item_offs[jb] - G.item_base;
-            first = G.pid_begin[jb];
+// Per-wave LDS counter slots of batched launches: each wave keeps the counters and ledger of up
+// to kSlots jobs (tagged by job index) and adds a slot to its job's tallies in HBM only when the
+// slot is reused for another job or at the end of the launch.
+constexpr int kSlots = 4;
+constexpr int kSlotWords = kNCnt + kNLed;   // 48 counters + 24 ledger entries, 8 bytes each
+
+__device__ __forceinline__ void slot_flush(const DevJob* jobs, int job, unsigned long long* w) {
+    // called by one lane
+    const DevJob& J = jobs[job];
+    for (int i = 0; i < kNCnt; ++i)
+        if (w[i]) {
+            add_u64(&J.counters[i], w[i]);
+            w[i] = 0ull;
         }
-        p.job = jb;
-        *pid_out = (uint32_t)(first + ((int64_t)idx - base));
-    } else {
-        const uint32_t meta = G.qin.meta[idx];
-        p.sp = (int32_t)(meta & 3u);
-        p.ir = (int32_t)((meta >> 2) & 0x7FFu);
-        p.iz = (int32_t)(meta >> 13);
-        p.x = (Real)G.qin.x[idx];
-        p.y = (Real)G.qin.y[idx];
-        p.z = (Real)G.qin.z[idx];
-        p.u = (Real)G.qin.u[idx];
-        p.v = (Real)G.qin.v[idx];
-        p.w = (Real)G.qin.w[idx];
-        p.e = (Real)G.qin.e[idx];
-        p.lin = G.qin.lin[idx];
-        p.pid = G.qin.pid[idx];
-        p.job = kBatched ? (int32_t)G.qin.job[idx] : 0;
+    double* d = (double*)(w + kNCnt);
+    for (int i = 0; i < kNLed; ++i)
+        if (d[i] != 0.0) {
+            add_f64(&J.ledger[i], d[i]);
+            d[i] = 0.0;
+        }
+}
+
+// Load a queued particle into the lane.
+template <typename Real, bool kBatched>
+__device__ __forceinline__ void load_queued(const GenArgs& G, int64_t idx, Part<Real>& p) {
+    const uint32_t meta = G.qin.meta[idx];
+    p.sp = (int32_t)(meta & 3u);
+    p.ir = (int32_t)((meta >> 2) & 0x7FFu);
+    p.iz = (int32_t)(meta >> 13);
+    p.x = (Real)G.qin.x[idx];
+    p.y = (Real)G.qin.y[idx];
+    p.z = (Real)G.qin.z[idx];
+    p.u = (Real)G.qin.u[idx];
+    p.v = (Real)G.qin.v[idx];
+    p.w = (Real)G.qin.w[idx];
+    p.e = (Real)G.qin.e[idx];
+    p.lin = G.qin.lin[idx];
+    p.pid = G.qin.pid[idx];
+    p.job = kBatched ? (int32_t)G.qin.job[idx] : 0;
+}
+
+// next job at or after j (cyclic) that still has items to fetch, or -1
+__device__ __forceinline__ int next_job_with_items(const GenArgs& G, int j) {
+    for (int k = 0; k < G.n_jobs; ++k) {
+        const int c = (j + k) % G.n_jobs;
+        const unsigned long long taken = __atomic_load_n(&G.job_fetch[c], __ATOMIC_RELAXED);
+        if ((int64_t)taken < G.job_count[c]) return c;
+    }
+    return -1;
+}
+
+// Give every lane with `need` a work item.  Plain launches take the next items of one global
+// counter.  Batched launches keep each wave on one job (wjob) and move it to another job only
+// when the current one has no items left, so that the lanes of a wave stay on few jobs.
+template <typename Real, bool kBatched>
+__device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool need, bool& done,
+                                       int& wjob) {
+    if (!kBatched) {
+        const unsigned long long idx = wave_reserve(G.fetch, need);
+        if (!need) return;
+        if (idx >= (unsigned long long)G.n_items) {
+            done = true;
+            return;
+        }
+        if (G.mode == 0) {
+            p.job = 0;
+            p.pid = (uint32_t)(G.pid_begin0 + (int64_t)idx);
+        } else {
+            load_queued<Real, kBatched>(G, (int64_t)idx, p);
+        }
+        p.start = true;
+        return;
+    }
+    unsigned long long m = __ballot(need);
+    while (m) {
+        if (wjob < 0) {
+            if (need) done = true;
+            return;
+        }
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned long long base = 0;
+        if ((int)lane_id() == leader) base = atomicAdd(&G.job_fetch[wjob], (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+        const int64_t avail = G.job_count[wjob] - (int64_t)base;
+        const int64_t rank = (int64_t)rank_in(m);
+        if (need && rank < avail) {
+            const int64_t local = (int64_t)base + rank;
+            if (G.mode == 0) {
+                p.job = wjob;
+                p.pid = (uint32_t)(G.job_first[wjob] + local);
+            } else {
+                load_queued<Real, kBatched>(G, G.job_first[wjob] + local, p);
+            }
+            p.start = true;
+            need = false;
+        }
+        m = __ballot(need);
+        if (m) {
+            int nj = 0;
+            if ((int)lane_id() == __ffsll((long long)m) - 1) nj = next_job_with_items(G, (wjob + 1) % G.n_jobs);
+            wjob = __shfl(nj, __ffsll((long long)m) - 1);
+        }
     }
 }
 
@@ -1069,7 +1167,8 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
         p.start = false;
         if (G.mode == 0) {
             birth(J, L, p.pid, p, lc);
-            lc.e_prim += (double)p.e;
+            if (L.direct) atomicAdd(&L.led[KARL_L_E_PRIMARY], (double)p.e);
+            else lc.e_prim += (double)p.e;
             if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 0], (double)p.e);
         }
         start_particle(J, L, p, lc);
@@ -1121,49 +1220,68 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
         const Real* g_rf = (const Real*)J.rf;
         for (int i = tid; i <= J.n_r; i += blockDim.x) s_rf[i] = g_rf[i];
         __syncthreads();
-        L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf};
+        L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf, false};
     }
 
+    // batched: this wave's counter slots and their job tags
+    const int wid = tid >> 6;
+    unsigned long long* wslots = (unsigned long long*)lds_raw + (size_t)wid * kSlots * kSlotWords;
+    int32_t* wtags = (int32_t*)((unsigned long long*)lds_raw + (size_t)(kBlock / 64) * kSlots * kSlotWords) + wid * kSlots;
+    if (kBatched) {
+        for (int i = (tid & 63); i < kSlots * kSlotWords; i += 64) wslots[i] = 0ull;
+        if ((tid & 63) < kSlots) wtags[tid & 63] = -1;
+        __builtin_amdgcn_wave_barrier();
+    }
+    int next_victim = 0;
+
     LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
-    int lc_job = 0;
     Part<Real> p;
     p.alive = false;
     p.start = false;
     p.job = 0;
     bool done = false;
+    // batched: the wave's current job, first spread over the jobs by wave index
+    int wjob = 0;
+    if (kBatched) {
+        int nj = 0;
+        const int gw = (int)((blockIdx.x * (kBlock / 64) + wid) % (unsigned)G.n_jobs);
+        if (lane_id() == 0) nj = next_job_with_items(G, gw);
+        wjob = __shfl(nj, 0);
+    }
     for (;;) {
         const bool need = !p.alive && !p.start && !done;
-        if (__ballot(need)) {
-            const unsigned long long idx = wave_reserve(G.fetch, need);
-            if (need) {
-                if (idx < (unsigned long long)G.n_items) {
-                    uint32_t pid = 0u;
-                    fetch_item<Real, kBatched>(G, idx, p, &pid);
-                    if (G.mode == 0) p.pid = pid;
-                    p.start = true;
-                } else {
-                    done = true;
-                }
-            }
-        }
+        if (__ballot(need)) refill<Real, kBatched>(G, p, need, done, wjob);
         if (!__ballot(!done)) break;
         if (!kBatched) {
             if (p.alive || p.start) advance(jobs[0], L0, G, p, lc);
         } else {
             bool todo = p.alive || p.start;
+            const int key = 2 * p.job + (p.start ? 0 : p.sp);
             for (;;) {
                 const unsigned long long m = __ballot(todo);
                 if (!m) break;
                 const int leader = __ffsll((long long)m) - 1;
-                const int j0 = __shfl(p.job, leader);
-                if (todo && p.job == j0) {
+                const int k0 = __shfl(key, leader);
+                if (todo && key == k0) {
                     const int ju = __builtin_amdgcn_readfirstlane(p.job);
                     const DevJob& J = jobs[ju];
-                    if (lc_job != ju) {
-                        flush_lane(lc, jobs[lc_job].counters, jobs[lc_job].ledger);
-                        lc_job = ju;
+                    // find this job's slot, or take one over (flushing the job that held it)
+                    int slot = -1;
+                    for (int k = 0; k < kSlots; ++k)
+                        if (wtags[k] == ju) slot = k;
+                    if (slot < 0) {
+                        slot = next_victim;
+                        next_victim = (next_victim + 1) % kSlots;
+                        const int old = wtags[slot];
+                        const unsigned long long mine = __ballot(true);
+                        if ((int)lane_id() == __ffsll((long long)mine) - 1) {
+                            if (old >= 0) slot_flush(jobs, old, wslots + (size_t)slot * kSlotWords);
+                            wtags[slot] = ju;
+                        }
+                        __builtin_amdgcn_wave_barrier();
                     }
-                    advance(J, global_view<Real>(J), G, p, lc);
+                    unsigned long long* sc = wslots + (size_t)slot * kSlotWords;
+                    advance(J, global_view<Real>(J, sc, (double*)(sc + kNCnt)), G, p, lc);
                     todo = false;
                 }
             }
@@ -1179,7 +1297,10 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
         for (int i = tid; i < kNLed; i += blockDim.x)
             if (L0.led[i] != 0.0) add_f64(&J.ledger[i], L0.led[i]);
     } else {
-        flush_lane(lc, jobs[lc_job].counters, jobs[lc_job].ledger);
+        __builtin_amdgcn_wave_barrier();
+        if ((tid & 63) == 0)
+            for (int k = 0; k < kSlots; ++k)
+                if (wtags[k] >= 0) slot_flush(jobs, wtags[k], wslots + (size_t)k * kSlotWords);
     }
 }
 
@@ -1226,6 +1347,44 @@ __global__ void fields_kernel(const DevJob J, double t_sim, double* density, dou
     }
 }
 
+__global__ void sort_count_kernel(const uint32_t* __restrict__ job, int64_t n,
+                                  unsigned long long* counts) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        wave_count(counts, (int)job[i]);
+}
+
+__global__ void sort_scan_kernel(const unsigned long long* counts, int32_t n_jobs, int64_t* first,
+                                 int64_t* count, unsigned long long* cursor) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t acc = 0;
+        for (int j = 0; j < n_jobs; ++j) {
+            first[j] = acc;
+            count[j] = (int64_t)counts[j];
+            cursor[j] = 0ull;
+            acc += (int64_t)counts[j];
+        }
+    }
+}
+
+__global__ void sort_scatter_kernel(const QueueSoA in, const QueueSoA out, int64_t n, const int64_t* first,
+                                    unsigned long long* cursor) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = in.job[i];
+        const int64_t d = first[j] + (int64_t)atomicAdd(&cursor[j], 1ull);
+        out.x[d] = in.x[i];
+        out.y[d] = in.y[i];
+        out.z[d] = in.z[i];
+        out.u[d] = in.u[i];
+        out.v[d] = in.v[i];
+        out.w[d] = in.w[i];
+        out.e[d] = in.e[i];
+        out.lin[d] = in.lin[i];
+        out.pid[d] = in.pid[i];
+        out.meta[d] = in.meta[i];
+        out.job[d] = j;
+    }
+}
+
 __global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long value) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -1260,7 +1419,9 @@ hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool bat
     return hipGetLastError();
 }
 
-size_t batched_lds_bytes() { return 0; }
+size_t batched_lds_bytes() {
+    return (size_t)(kBlock / 64) * (kSlots * kSlotWords * 8 + kSlots * 4);
+}
 
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s) {
@@ -1269,6 +1430,20 @@ hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double*
     size_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fields_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, t_sim, density, jz, jr);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_by_job(const QueueSoA& in, const QueueSoA& out, int64_t n, int32_t n_jobs,
+                              unsigned long long* counts, int64_t* first, int64_t* count,
+                              unsigned long long* cursor, hipStream_t s) {
+    hipError_t e = launch_fill_u64(counts, (size_t)n_jobs, 0ull, s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(sort_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in.job, n, counts);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(64), 0, s, counts, n_jobs, first, count, cursor);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, first, cursor);
     return hipGetLastError();
 }
 
