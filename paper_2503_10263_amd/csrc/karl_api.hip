@@ -235,7 +235,9 @@ struct Launcher {
     int32_t n_jobs = 1;
     int64_t* job_first = nullptr;
     int64_t* job_count = nullptr;
+    int64_t* job_cum = nullptr;
     unsigned long long* job_fetch = nullptr;
+    unsigned long long* job_waves = nullptr;
     unsigned long long* sort_counts = nullptr;
     unsigned long long* sort_cursor = nullptr;
 
@@ -322,7 +324,10 @@ struct Launcher {
             g.fetch = fetch;
             g.job_first = job_first;
             g.job_count = job_count;
+            // the job-sorted queue starts of job j at the items of the jobs before it
+            g.job_cum = mode == 1 ? job_first : job_cum;
             g.job_fetch = job_fetch;
+            g.job_waves = job_waves;
             g.qin = *in;
             g.qout = q[mo];
             g.qout_count = qcount;
@@ -331,7 +336,10 @@ struct Launcher {
             g.capacity = capacity;
             g.status = (unsigned int*)(ctl + 2);
             HIP_CHECK(karl::launch_fill_u64(fetch, 2, 0ull, s));
-            if (batched) HIP_CHECK(karl::launch_fill_u64(job_fetch, (size_t)n_jobs, 0ull, s));
+            if (batched) {
+                HIP_CHECK(karl::launch_fill_u64(job_fetch, (size_t)n_jobs, 0ull, s));
+                HIP_CHECK(karl::launch_fill_u64(job_waves, (size_t)n_jobs, 0ull, s));
+            }
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > max_blocks) blocks = max_blocks;
             HIP_CHECK(hipEventRecord(ev0, s));
@@ -404,14 +412,15 @@ struct Batch {
     char* ws = nullptr;
     int64_t* job_first = nullptr;   // device [max_jobs]
     int64_t* job_count = nullptr;   // device [max_jobs]
-    int64_t* host_i64 = nullptr;    // pinned staging [2*max_jobs]
+    int64_t* job_cum = nullptr;     // device [max_jobs]
+    int64_t* host_i64 = nullptr;    // pinned staging [3*max_jobs]
     karl::DevJob* host_jobs = nullptr;   // pinned staging of the job table
     Launcher run[2];                // FP64 and FP32 launchers share the queues
     int64_t chunk = kDefaultChunk;
     int device = 0;
 };
 
-// job table, per-job first/count/fetch, sort counts and cursors, control words, four queues
+// job table, per-job first/count/cum/fetch/waves, sort counts and cursors, control words, four queues
 size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o_perjob,
                     size_t* o_ctl, size_t* o_queues) {
     size_t off = 0;
@@ -421,7 +430,7 @@ size_t batch_layout(int32_t max_jobs, int64_t entries, size_t* o_jobs, size_t* o
         return o;
     };
     *o_jobs = take(sizeof(karl::DevJob) * (size_t)max_jobs);
-    *o_perjob = take(5 * 8 * (size_t)max_jobs);
+    *o_perjob = take(7 * 8 * (size_t)max_jobs);
     *o_ctl = take(kControlBytes);
     *o_queues = take(4 * (size_t)entries * kQueueEntryBytes);
     return off;
@@ -799,6 +808,7 @@ karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* wo
     int64_t* pj = (int64_t*)(b->ws + o_pj);
     b->job_first = pj;
     b->job_count = pj + max_jobs;
+    b->job_cum = pj + 2 * (size_t)max_jobs;
     auto cleanup = [&](karl_status s) {
         b->run[0].release();
         b->run[1].release();
@@ -816,11 +826,13 @@ karl_status karl_create_batch(int32_t max_jobs, int64_t queue_capacity, void* wo
         b->run[p].jobs_dev = (karl::DevJob*)(b->ws + o_jobs);
         b->run[p].job_first = pj;
         b->run[p].job_count = pj + max_jobs;
-        b->run[p].job_fetch = (unsigned long long*)(pj + 2 * (size_t)max_jobs);
-        b->run[p].sort_counts = (unsigned long long*)(pj + 3 * (size_t)max_jobs);
-        b->run[p].sort_cursor = (unsigned long long*)(pj + 4 * (size_t)max_jobs);
+        b->run[p].job_cum = pj + 2 * (size_t)max_jobs;
+        b->run[p].job_fetch = (unsigned long long*)(pj + 3 * (size_t)max_jobs);
+        b->run[p].job_waves = (unsigned long long*)(pj + 4 * (size_t)max_jobs);
+        b->run[p].sort_counts = (unsigned long long*)(pj + 5 * (size_t)max_jobs);
+        b->run[p].sort_cursor = (unsigned long long*)(pj + 6 * (size_t)max_jobs);
     }
-    if (hipHostMalloc((void**)&b->host_i64, 8 * (2 * (size_t)max_jobs), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&b->host_i64, 8 * (3 * (size_t)max_jobs), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->host_jobs, sizeof(karl::DevJob) * (size_t)max_jobs, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(KARL_EDEVICE, "pinned staging allocation failed"));
     *out = b;
@@ -861,13 +873,18 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
         // the chunk's primaries per job: first id and count
         const int j_lo = (int)(std::upper_bound(offs.begin(), offs.end(), c0) - offs.begin()) - 1;
         const int j_hi = (int)(std::lower_bound(offs.begin(), offs.end(), c0 + n) - offs.begin());
+        int64_t cum = 0;
         for (int i = 0; i < n_jobs; ++i) {
             const int64_t lo = std::max(c0, offs[i]), hi = std::min(c0 + n, offs[i + 1]);
-            B->host_i64[i] = ranges[2 * i] + (lo - offs[i]);
-            B->host_i64[n_jobs + i] = hi > lo ? hi - lo : 0;
+            const int64_t cnt = hi > lo ? hi - lo : 0;
+            B->host_i64[i] = ranges[2 * i] + (cnt > 0 ? lo - offs[i] : 0);
+            B->host_i64[n_jobs + i] = cnt;
+            B->host_i64[2 * n_jobs + i] = cum;
+            cum += cnt;
         }
         HIP_CHECK(hipMemcpyAsync(B->job_first, B->host_i64, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(B->job_count, B->host_i64 + n_jobs, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(B->job_cum, B->host_i64 + 2 * n_jobs, 8 * (size_t)n_jobs, hipMemcpyHostToDevice, s));
         // snapshot the tallies of the jobs in the chunk for an overflow retry
         for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
             Job* j = (Job*)jobs[i];

@@ -92,7 +92,11 @@ struct GenArgs {
     // (mode 1); each wave fetches from one job at a time through job_fetch[j]
     const int64_t* job_first;
     const int64_t* job_count;
+    // job_cum[j]: number of items of jobs 0..j-1 (waves start on jobs in proportion to their
+    // items); job_waves[j]: waves currently fetching from job j
+    const int64_t* job_cum;
     unsigned long long* job_fetch;
+    unsigned long long* job_waves;
     unsigned long long* fetch;
     QueueSoA qin;
     QueueSoA qout;

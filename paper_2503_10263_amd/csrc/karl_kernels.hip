@@ -1095,14 +1095,52 @@ __device__ __forceinline__ void load_queued(const GenArgs& G, int64_t idx, Part<
     p.job = kBatched ? (int32_t)G.qin.job[idx] : 0;
 }
 
-// next job at or after j (cyclic) that still has items to fetch, or -1
-__device__ __forceinline__ int next_job_with_items(const GenArgs& G, int j) {
-    for (int k = 0; k < G.n_jobs; ++k) {
-        const int c = (j + k) % G.n_jobs;
-        const unsigned long long taken = __atomic_load_n(&G.job_fetch[c], __ATOMIC_RELAXED);
-        if ((int64_t)taken < G.job_count[c]) return c;
+// Job choice of batched launches (all 64 lanes of the wave active).  A wave starts on the job
+// that holds the item at its share of the launch's items, so that waves are spread over the jobs
+// in proportion to their work, and a wave whose job has run out moves to the job with the most
+// unfetched items per wave already on it; both keep each wave on few jobs.
+__device__ __forceinline__ int first_job(const GenArgs& G, int gwave, int n_waves) {
+    int j = 0;
+    if (lane_id() == 0) {
+        const int64_t t = ((2 * (int64_t)gwave + 1) * G.n_items) / (2 * (int64_t)n_waves);
+        int lo = 0, hi = G.n_jobs - 1;   // last job with job_cum <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (G.job_cum[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        j = lo;
+        atomicAdd(&G.job_waves[j], 1ull);
     }
-    return -1;
+    return __shfl(j, 0);
+}
+
+__device__ __forceinline__ int pick_job(const GenArgs& G, int leave) {
+    if (leave >= 0 && lane_id() == 0) atomicSub(&G.job_waves[leave], 1ull);
+    double best = -1.0;
+    int bj = -1;
+    for (int j = (int)lane_id(); j < G.n_jobs; j += 64) {
+        const int64_t rem = G.job_count[j] - (int64_t)__atomic_load_n(&G.job_fetch[j], __ATOMIC_RELAXED);
+        if (rem > 0) {
+            const double w = (double)__atomic_load_n(&G.job_waves[j], __ATOMIC_RELAXED);
+            const double score = (double)rem / (1.0 + w);
+            if (score > best) {
+                best = score;
+                bj = j;
+            }
+        }
+    }
+    // wave-wide arg-max, ties to the lower job index: every lane ends with the same pair
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oj = __shfl_xor(bj, off);
+        if (ob > best || (ob == best && (unsigned)oj < (unsigned)bj)) {
+            best = ob;
+            bj = oj;
+        }
+    }
+    if (bj >= 0 && lane_id() == 0) atomicAdd(&G.job_waves[bj], 1ull);
+    return bj;
 }
 
 // Give every lane with `need` a work item.  Plain launches take the next items of one global
@@ -1151,11 +1189,7 @@ __device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool nee
             need = false;
         }
         m = __ballot(need);
-        if (m) {
-            int nj = 0;
-            if ((int)lane_id() == __ffsll((long long)m) - 1) nj = next_job_with_items(G, (wjob + 1) % G.n_jobs);
-            wjob = __shfl(nj, __ffsll((long long)m) - 1);
-        }
+        if (m) wjob = pick_job(G, wjob);
     }
 }
 
@@ -1242,12 +1276,7 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
     bool done = false;
     // batched: the wave's current job, first spread over the jobs by wave index
     int wjob = 0;
-    if (kBatched) {
-        int nj = 0;
-        const int gw = (int)((blockIdx.x * (kBlock / 64) + wid) % (unsigned)G.n_jobs);
-        if (lane_id() == 0) nj = next_job_with_items(G, gw);
-        wjob = __shfl(nj, 0);
-    }
+    if (kBatched) wjob = first_job(G, (int)(blockIdx.x * (kBlock / 64) + wid), (int)(gridDim.x * (kBlock / 64)));
     for (;;) {
         const bool need = !p.alive && !p.start && !done;
         if (__ballot(need)) refill<Real, kBatched>(G, p, need, done, wjob);
