@@ -220,6 +220,91 @@ karl_status karl_batch_stats(void* batch, double* kernel_ms, int64_t* n_launches
 /* Release host resources of the batch (the caller still owns its workspace). */
 karl_status karl_destroy_batch(void* batch);
 
+/* ---- serving: continuous batching of transport requests ----
+   A server takes job descriptors as they arrive, admits them while the HBM they need for
+   tables, tallies and queues fits into its arena (device memory it sub-allocates, first fit),
+   and transports them in rounds of one karl_transport_batch each: every round gives each of a
+   worker's jobs up to a quantum of its next primaries; the quantum starts at max_quantum and
+   follows a target round time (the larger of round_ms and twice the shortest recent round,
+   since no round is shorter than its longest chain of histories).  Each admitted job belongs to one of n_workers workers (the least loaded); a worker
+   owns a batch and a stream.  Rounds run either in the calling thread (karl_server_step) or,
+   after karl_server_start, in one thread per worker, so that the rounds of different workers
+   run concurrently and one round's tail (its longest histories) overlaps another's work.  Jobs
+   admitted while others run join their worker's next round; a job leaves when its last
+   primary is done and keeps its arena space, with its tallies, until it is released.  Because a history depends
+   only on (seed, primary id), a job's tallies are the same served in any mix as transported
+   alone (integer tallies exactly, FP64 sums up to the order of addition).  The paper's
+   parallel runs balance uneven work over processes (Sec. 3.6); this is the single-device
+   counterpart for many independent jobs.  A server is driven by one host thread. */
+typedef struct {
+    int32_t max_jobs;        /* jobs transported together (admission slots), >= 1 */
+    int32_t precision;       /* KARL_FP64 or KARL_FP32: every submitted job must match */
+    int64_t queue_capacity;  /* entries per secondary queue of the shared batch (0: 1<<22) */
+    uint64_t arena_bytes;    /* device bytes for job workspaces: the admission budget */
+    double round_ms;         /* target wall time of one round (<= 0: 50 ms) */
+    int64_t min_quantum;     /* bounds of the primaries per job per round (0: 64 and 1<<22) */
+    int64_t max_quantum;
+    int32_t n_workers;       /* concurrent rounds, one batch and stream each (0: 2; max 4) */
+    void* workspace;         /* caller-owned device memory of karl_server_workspace_bytes() */
+    uint64_t workspace_bytes;
+} karl_server_desc;
+
+typedef struct {
+    int64_t submitted, admitted, completed, released, rounds;
+    int64_t primaries;       /* primaries transported by all rounds */
+    double kernel_ms;        /* transport kernel time of all rounds (HIP events) */
+    double busy_ms;          /* host wall time spent inside rounds */
+    uint64_t arena_used, arena_peak;   /* bytes held by admitted, unreleased jobs */
+    int64_t quantum;         /* current primaries per job per round */
+} karl_server_stats;
+
+/* Device bytes of a server (n_workers batch regions plus arena_bytes). */
+karl_status karl_server_workspace_bytes(const karl_server_desc* desc, uint64_t* bytes);
+
+/* Create a server on the current HIP device. */
+karl_status karl_create_server(const karl_server_desc* desc, void** out);
+
+/* Queue a job (deep-copied; its workspace fields are ignored: the arena provides them).
+   *ticket identifies it from now on.  KARL_EINVAL for an invalid descriptor, a precision other
+   than the server's, or a job larger than the whole arena. */
+karl_status karl_server_submit(void* server, const karl_job_desc* desc, int64_t* ticket);
+
+/* Without worker threads: admit queued jobs in arrival order while they fit, then run one
+   round of every worker, one after the other on `hip_stream` (returns at once if no job is
+   active).  *n_active and *n_pending (either may be NULL) are the counts afterwards.
+   KARL_ESTATE while worker threads run. */
+karl_status karl_server_step(void* server, void* hip_stream, int32_t* n_active, int32_t* n_pending);
+
+/* Start one thread per worker; from now on admission and rounds run in the background on
+   non-blocking streams of the server's own (default priority).  Submit, poll, job, release
+   and stats may be called from the host thread meanwhile. */
+karl_status karl_server_start(void* server);
+
+/* Block until a completed job is waiting to be polled, a worker failed, or timeout_ms passed.
+   Returns a worker's failure status (with its message) once one occurred. */
+karl_status karl_server_wait(void* server, double timeout_ms, int32_t* n_active, int32_t* n_pending);
+
+/* Let every worker finish its current round and join the threads (jobs not yet done stay
+   active and can be continued by karl_server_step or another start). */
+karl_status karl_server_stop(void* server);
+
+/* Tickets of jobs completed since the last poll, oldest first, up to `capacity`. */
+karl_status karl_server_poll(void* server, int64_t* tickets, int32_t capacity, int32_t* n);
+
+/* The job handle of a ticket (valid until the ticket is released) for karl_read_tallies,
+   karl_read_fields and karl_job_stats.  KARL_ESTATE while the job is not yet admitted. */
+karl_status karl_server_job(void* server, int64_t ticket, void** job);
+
+/* Return a completed job's arena space (its handle becomes invalid).  KARL_ESTATE if the job
+   has not completed. */
+karl_status karl_server_release(void* server, int64_t ticket);
+
+karl_status karl_server_stats_get(void* server, karl_server_stats* out);
+
+/* Stop the workers if they run, then destroy the server and every job it still holds (the
+   caller still owns the workspace). */
+karl_status karl_destroy_server(void* server);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* karl_last_error(void);
 

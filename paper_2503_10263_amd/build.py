@@ -6,7 +6,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libkarl.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("karl_kernels.hip", "karl_api.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("karl_kernels.hip", "karl_api.hip", "karl_server.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

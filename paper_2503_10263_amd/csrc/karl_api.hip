@@ -240,6 +240,7 @@ struct Launcher {
     unsigned long long* job_waves = nullptr;
     unsigned long long* sort_counts = nullptr;
     unsigned long long* sort_cursor = nullptr;
+    bool ready = false;
 
     karl_status init(char* queues, size_t entries, unsigned long long* control, int prec,
                      bool is_batched, size_t lds_bytes) {
@@ -264,7 +265,8 @@ struct Launcher {
         HIP_CHECK(hipEventCreate(&ev0));
         HIP_CHECK(hipEventCreate(&ev1));
         HIP_CHECK(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
-        HIP_CHECK(hipDeviceSynchronize());
+        HIP_CHECK(hipStreamSynchronize(nullptr));
+        ready = true;
         return KARL_OK;
     }
 
@@ -274,6 +276,7 @@ struct Launcher {
         if (ev1) (void)hipEventDestroy(ev1);
         host_ctl = nullptr;
         ev0 = ev1 = nullptr;
+        ready = false;
     }
 
     void reset_stats() {
@@ -405,7 +408,19 @@ struct Job {
     int64_t n_transported = 0;   // primaries transported since creation or reset
     bool failed = false;
     int device = 0;
+    size_t lds = 0;              // launch shape of the job's own launcher, set up on first use
 };
+
+// The job's own launcher (pinned words, events) is created by its first karl_transport, so that
+// jobs transported only in batches hold no host resources whose release synchronizes the device.
+karl_status ensure_launcher(Job* j) {
+    if (j->run.ready) return KARL_OK;
+    unsigned long long* ctl = j->run.ctl;
+    karl::DevJob* table = j->run.jobs_dev;
+    karl_status s = j->run.init(j->ws + j->lay.queues, j->lay.queue_entries, ctl, j->precision, false, j->lds);
+    j->run.jobs_dev = table;
+    return s;
+}
 
 struct Batch {
     int32_t max_jobs = 0;
@@ -459,6 +474,13 @@ karl_status upload_real(const Job& j, size_t off, const std::vector<double>& v) 
 extern "C" {
 
 const char* karl_last_error(void) { return g_err; }
+
+// error reporting for the serving layer, which lives in its own translation unit
+__attribute__((visibility("hidden"))) karl_status karl_internal_set_error(karl_status code,
+                                                                          const char* msg) {
+    snprintf(g_err, sizeof(g_err), "%s", msg);
+    return code;
+}
 
 karl_status karl_workspace_bytes(const karl_job_desc* desc, uint64_t* bytes) {
     if (!bytes) return fail(KARL_EINVAL, "bytes is NULL");
@@ -632,10 +654,12 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         return cleanup(fail(KARL_EINVAL, "tables need %zu bytes of LDS per workgroup (max %zu)",
                             lds, kMaxLds));
     TRY_HIP(hipMemcpy(w + L.devjob, &J, sizeof(J), hipMemcpyHostToDevice));
-    TRY(j->run.init(w + L.queues, L.queue_entries, ctl, d->precision, false, lds));
+    j->lds = lds;
+    j->run.ctl = ctl;
     j->run.jobs_dev = (karl::DevJob*)(w + L.devjob);
+    TRY_HIP(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
     TRY_HIP(karl::launch_fill_u64((unsigned long long*)t, L.tally_bytes / 8, 0ull, nullptr));
-    TRY_HIP(hipDeviceSynchronize());
+    TRY_HIP(hipStreamSynchronize(nullptr));
 #undef TRY
 #undef TRY_HIP
     *out = j;
@@ -651,6 +675,8 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
                     (long long)pid_end, (long long)j->n_primaries);
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(hipSetDevice(j->device));
+    karl_status st0 = ensure_launcher(j);
+    if (st0 != KARL_OK) return st0;
     int64_t b = pid_begin;
     char* tallies = j->ws + j->lay.tallies;
     char* snap = j->ws + j->lay.snapshot;

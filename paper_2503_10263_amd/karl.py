@@ -22,6 +22,9 @@ NHIST = 4
 NREASON = 8
 FP64, FP32 = 0, 1
 FLAG_DIGESTS, FLAG_HISTORY = 1, 2
+# counter indices (KARL_C_* of include/karl.h); pairs are [electron, ion]
+C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 2, 4, 6, 8
+C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES, C_PROC, C_DEATH = 10, 11, 12, 16, 32
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDEVICE",
@@ -31,7 +34,11 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
                 "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
-                "karl_batch_stats", "karl_destroy_batch", "karl_last_error"]
+                "karl_batch_stats", "karl_destroy_batch",
+                "karl_server_workspace_bytes", "karl_create_server", "karl_server_submit",
+                "karl_server_step", "karl_server_start", "karl_server_wait", "karl_server_stop",
+                "karl_server_poll", "karl_server_job", "karl_server_release",
+                "karl_server_stats_get", "karl_destroy_server", "karl_last_error"]
 
 
 class KarlError(RuntimeError):
@@ -66,6 +73,20 @@ class JobDesc(C.Structure):
                 ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
                 ("queue_capacity", C.c_int64), ("chunk", C.c_int64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
+
+
+class ServerDesc(C.Structure):
+    _fields_ = [("max_jobs", C.c_int32), ("precision", C.c_int32), ("queue_capacity", C.c_int64),
+                ("arena_bytes", C.c_uint64), ("round_ms", C.c_double), ("min_quantum", C.c_int64),
+                ("max_quantum", C.c_int64), ("n_workers", C.c_int32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("released", C.c_int64), ("rounds", C.c_int64), ("primaries", C.c_int64),
+                ("kernel_ms", C.c_double), ("busy_ms", C.c_double), ("arena_used", C.c_uint64),
+                ("arena_peak", C.c_uint64), ("quantum", C.c_int64)]
 
 
 class Tallies(C.Structure):
@@ -105,6 +126,21 @@ def lib():
         L.karl_batch_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.karl_destroy_batch.argtypes = [C.c_void_p]
+        L.karl_server_workspace_bytes.argtypes = [C.POINTER(ServerDesc), C.POINTER(C.c_uint64)]
+        L.karl_create_server.argtypes = [C.POINTER(ServerDesc), C.POINTER(C.c_void_p)]
+        L.karl_server_submit.argtypes = [C.c_void_p, C.POINTER(JobDesc), C.POINTER(C.c_int64)]
+        L.karl_server_step.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
+        L.karl_server_start.argtypes = [C.c_void_p]
+        L.karl_server_wait.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
+        L.karl_server_stop.argtypes = [C.c_void_p]
+        L.karl_server_poll.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int32,
+                                       C.POINTER(C.c_int32)]
+        L.karl_server_job.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]
+        L.karl_server_release.argtypes = [C.c_void_p, C.c_int64]
+        L.karl_server_stats_get.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+        L.karl_destroy_server.argtypes = [C.c_void_p]
         for name in ENTRY_POINTS[:-1]:
             getattr(L, name).restype = C.c_int32
         L.karl_last_error.argtypes = []
@@ -233,25 +269,12 @@ class Job:
             pid_end = self.w.n_primaries
         check(lib().karl_transport(self.h, int(pid_begin), int(pid_end), self._stream(stream)))
 
-    def read_tallies(self, stream=None) -> Dict[str, np.ndarray]:
-        shapes = tally_shapes(self.w, self.digests, self.history)
-        out = {k: np.zeros(shp, dt) for k, (shp, dt) in shapes.items()}
-        T = Tallies()
-        for k, arr in out.items():
-            ctype = {np.int64: C.c_int64, np.float64: C.c_double, np.uint64: C.c_uint64}[arr.dtype.type]
-            setattr(T, k, arr.ctypes.data_as(C.POINTER(ctype)))
-        check(lib().karl_read_tallies(self.h, C.byref(T), self._stream(stream)))
-        return out
+    def read_tallies(self, stream=None, only=None) -> Dict[str, np.ndarray]:
+        return _read_tallies(self.h, self.w, self.digests, self.history, stream, only)
 
     def read_fields(self, activity: float, stream=None) -> Dict[str, np.ndarray]:
         """Densities (m^-3) and currents (m^-2 s^-1) normalised with t_sim = N_prim/activity."""
-        w = self.w
-        dens = np.zeros((2, w.n_r, w.n_z))
-        jz = np.zeros((2, w.n_r, w.n_z + 1))
-        jr = np.zeros((2, w.n_r + 1, w.n_z))
-        check(lib().karl_read_fields(self.h, float(activity), _dptr(dens), _dptr(jz), _dptr(jr),
-                                     self._stream(stream)))
-        return {"density": dens, "jz": jz, "jr": jr}
+        return _read_fields(self.h, self.w, activity, stream)
 
     def reset(self, stream=None):
         check(lib().karl_reset_tallies(self.h, self._stream(stream)))
@@ -273,6 +296,29 @@ class Job:
             self.close()
         except Exception:
             pass
+
+
+def _read_tallies(h, w, digests, history, stream=None, only=None) -> Dict[str, np.ndarray]:
+    """karl_read_tallies into fresh arrays; `only` restricts the copy to some of them."""
+    shapes = tally_shapes(w, digests, history)
+    if only is not None:
+        shapes = {k: v for k, v in shapes.items() if k in only}
+    out = {k: np.zeros(shp, dt) for k, (shp, dt) in shapes.items()}
+    T = Tallies()
+    for k, arr in out.items():
+        ctype = {np.int64: C.c_int64, np.float64: C.c_double, np.uint64: C.c_uint64}[arr.dtype.type]
+        setattr(T, k, arr.ctypes.data_as(C.POINTER(ctype)))
+    check(lib().karl_read_tallies(h, C.byref(T), Job._stream(stream)))
+    return out
+
+
+def _read_fields(h, w, activity, stream=None) -> Dict[str, np.ndarray]:
+    dens = np.zeros((2, w.n_r, w.n_z))
+    jz = np.zeros((2, w.n_r, w.n_z + 1))
+    jr = np.zeros((2, w.n_r + 1, w.n_z))
+    check(lib().karl_read_fields(h, float(activity), _dptr(dens), _dptr(jz), _dptr(jr),
+                                 Job._stream(stream)))
+    return {"density": dens, "jz": jz, "jr": jr}
 
 
 class Batch:
@@ -325,3 +371,102 @@ def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, **kw) -> Dict[str,
         return job.read_tallies()
     finally:
         job.close()
+
+
+class Server:
+    """Continuous batching of transport requests (karl_create_server): jobs are admitted while
+    their workspaces fit into an arena of `arena_bytes` device bytes and transported together
+    in rounds.  The device memory (batch region + arena) is one torch allocation."""
+
+    def __init__(self, max_jobs: int = 256, arena_bytes: int = 8 << 30, precision: str = "fp32",
+                 queue_capacity: int = 0, round_ms: float = 50.0, min_quantum: int = 0,
+                 max_quantum: int = 0, n_workers: int = 0, device=None):
+        import torch
+        self.precision = FP32 if precision == "fp32" else FP64
+        d = ServerDesc()
+        d.max_jobs, d.precision, d.queue_capacity = int(max_jobs), self.precision, int(queue_capacity)
+        d.arena_bytes, d.round_ms = int(arena_bytes), float(round_ms)
+        d.min_quantum, d.max_quantum = int(min_quantum), int(max_quantum)
+        d.n_workers = int(n_workers)
+        n = C.c_uint64(0)
+        check(lib().karl_server_workspace_bytes(C.byref(d), C.byref(n)))
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.nbytes = int(n.value)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        d.workspace, d.workspace_bytes = self.workspace.data_ptr(), self.nbytes
+        self.d = d
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib().karl_create_server(C.byref(d), C.byref(h)))
+        self.h = h
+        self.workloads = {}
+        self.threaded = False
+
+    def submit(self, w, queue_capacity: int = 256, digests: bool = False) -> int:
+        """Queue workload w; the job's own queues stay small (the server's batch holds the
+        secondaries).  Returns its ticket."""
+        desc = Descriptor(w, self.precision, FLAG_DIGESTS if digests else 0, queue_capacity, 0)
+        t = C.c_int64(0)
+        check(lib().karl_server_submit(self.h, C.byref(desc.d), C.byref(t)))
+        self.workloads[t.value] = w
+        return t.value
+
+    def step(self, stream=None):
+        """Admit what fits, run one round; returns (n_active, n_pending)."""
+        a, p = C.c_int32(0), C.c_int32(0)
+        check(lib().karl_server_step(self.h, Job._stream(stream), C.byref(a), C.byref(p)))
+        return a.value, p.value
+
+    def start(self):
+        """Run admission and rounds in worker threads from now on."""
+        check(lib().karl_server_start(self.h))
+        self.threaded = True
+
+    def wait(self, timeout_ms: float = 50.0):
+        """Wait for a completion (or the timeout); returns (n_active, n_pending)."""
+        a, p = C.c_int32(0), C.c_int32(0)
+        check(lib().karl_server_wait(self.h, float(timeout_ms), C.byref(a), C.byref(p)))
+        return a.value, p.value
+
+    def stop(self):
+        check(lib().karl_server_stop(self.h))
+        self.threaded = False
+
+    def poll(self, capacity: int = 1024):
+        buf = (C.c_int64 * capacity)()
+        n = C.c_int32(0)
+        check(lib().karl_server_poll(self.h, buf, capacity, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def _handle(self, ticket: int):
+        h = C.c_void_p()
+        check(lib().karl_server_job(self.h, int(ticket), C.byref(h)))
+        return h
+
+    def read_tallies(self, ticket: int, only=None, stream=None, digests: bool = False) -> Dict[str, np.ndarray]:
+        return _read_tallies(self._handle(ticket), self.workloads[ticket], digests, False, stream, only)
+
+    def read_fields(self, ticket: int, activity: float, stream=None) -> Dict[str, np.ndarray]:
+        return _read_fields(self._handle(ticket), self.workloads[ticket], activity, stream)
+
+    def release(self, ticket: int):
+        check(lib().karl_server_release(self.h, int(ticket)))
+        self.workloads.pop(ticket, None)
+
+    def stats(self) -> Dict[str, float]:
+        s = ServerStats()
+        check(lib().karl_server_stats_get(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib().karl_destroy_server(self.h))
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+"""Request loop over a libkarl server: replays a stream of transport requests (arrival time,
+workload) against karl.Server in real time and reports job latency and throughput.
+
+Admission, the arena allocator and the rounds of batched transport are native (libkarl);
+this loop only submits requests when they arrive, steps the server and collects completions.
+"""
+import time
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+from . import karl
+
+
+def collisions_of(counters: np.ndarray) -> int:
+    """Performed interactions of both species (KARL_C_COLL pair of the counters)."""
+    return int(counters[karl.C_COLL] + counters[karl.C_COLL + 1])
+
+
+def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], realtime: bool = True,
+           keep_tallies: bool = False, threaded: bool = True, on_complete=None) -> Dict[str, object]:
+    """Submit request i at its arrival time (seconds after the start; all at once when
+    `realtime` is False) until every request has completed; read each job's counters (or all
+    its tallies with keep_tallies) and release it.  With `threaded` the server's worker
+    threads run the rounds and this loop only submits, waits and collects; otherwise the loop
+    steps the server itself.
+
+    Latency of a job = completion time - arrival time, where completion is the end of the
+    round that transported its last primary (as seen by this loop).  Returns per-job
+    latency/collisions, their p50/p99, the throughput and the server's statistics."""
+    n = len(requests)
+    order = sorted(range(n), key=lambda k: requests[k][0])
+    arrival: Dict[int, float] = {}
+    index_of: Dict[int, int] = {}
+    latency = np.zeros(n)
+    collisions = np.zeros(n, dtype=np.int64)
+    tallies: List[object] = [None] * n
+    backlog = []
+    nxt = 0
+    done = 0
+    if threaded:
+        server.start()
+    t0 = time.perf_counter()
+    try:
+        while done < n:
+            now = time.perf_counter() - t0
+            while nxt < n and (not realtime or requests[order[nxt]][0] <= now):
+                k = order[nxt]
+                t = server.submit(requests[k][1])
+                index_of[t] = k
+                arrival[t] = requests[k][0] if realtime else now
+                nxt += 1
+            if threaded:
+                until_next = requests[order[nxt]][0] - now if (realtime and nxt < n) else 0.05
+                n_active, n_pending = server.wait(1e3 * min(max(until_next, 0.0), 0.05))
+            else:
+                n_active, n_pending = server.step()
+            backlog.append((time.perf_counter() - t0, n_active + n_pending))
+            for t in server.poll():
+                end = time.perf_counter() - t0
+                k = index_of[t]
+                if keep_tallies:
+                    tallies[k] = server.read_tallies(t)
+                    c = tallies[k]["counters"]
+                else:
+                    c = server.read_tallies(t, only=("counters",))["counters"]
+                latency[k] = end - arrival[t]
+                collisions[k] = collisions_of(c)
+                if on_complete is not None:
+                    on_complete(k, t)
+                server.release(t)
+                done += 1
+            if not threaded and n_active == 0 and n_pending == 0 and nxt < n and realtime:
+                wait = requests[order[nxt]][0] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+    finally:
+        if threaded:
+            server.stop()
+    wall = time.perf_counter() - t0
+    first = min(r[0] for r in requests) if realtime else 0.0
+    st = server.stats()
+    return {
+        "latency_s": latency,
+        "collisions": collisions,
+        "tallies": tallies,
+        "p50_s": float(np.percentile(latency, 50)),
+        "p99_s": float(np.percentile(latency, 99)),
+        "mean_s": float(latency.mean()),
+        "wall_s": wall,
+        "collisions_per_s": float(collisions.sum() / max(wall - first, 1e-9)),
+        "busy_fraction": st["busy_ms"] / 1e3 / max(wall, 1e-9),
+        "max_backlog": max(b for _, b in backlog) if backlog else 0,
+        "stats": st,
+    }
