@@ -1260,13 +1260,17 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
     // batched: this wave's counter slots and their job tags
     const int wid = tid >> 6;
     unsigned long long* wslots = (unsigned long long*)lds_raw + (size_t)wid * kSlots * kSlotWords;
-    int32_t* wtags = (int32_t*)((unsigned long long*)lds_raw + (size_t)(kBlock / 64) * kSlots * kSlotWords) + wid * kSlots;
+    // per wave: kSlots job tags, then the index of the next slot to take over; kept in LDS so
+    // that every lane of the wave sees the same values whichever lanes ran the last pass
+    volatile int32_t* wtags =
+        (volatile int32_t*)((unsigned long long*)lds_raw + (size_t)(kBlock / 64) * kSlots * kSlotWords) +
+        wid * (kSlots + 1);
     if (kBatched) {
         for (int i = (tid & 63); i < kSlots * kSlotWords; i += 64) wslots[i] = 0ull;
         if ((tid & 63) < kSlots) wtags[tid & 63] = -1;
+        if ((tid & 63) == kSlots) wtags[kSlots] = 0;
         __builtin_amdgcn_wave_barrier();
     }
-    int next_victim = 0;
 
     LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
     Part<Real> p;
@@ -1299,13 +1303,13 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
                     for (int k = 0; k < kSlots; ++k)
                         if (wtags[k] == ju) slot = k;
                     if (slot < 0) {
-                        slot = next_victim;
-                        next_victim = (next_victim + 1) % kSlots;
+                        slot = wtags[kSlots];
                         const int old = wtags[slot];
                         const unsigned long long mine = __ballot(true);
                         if ((int)lane_id() == __ffsll((long long)mine) - 1) {
                             if (old >= 0) slot_flush(jobs, old, wslots + (size_t)slot * kSlotWords);
                             wtags[slot] = ju;
+                            wtags[kSlots] = (slot + 1) % kSlots;
                         }
                         __builtin_amdgcn_wave_barrier();
                     }
@@ -1449,7 +1453,7 @@ hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool bat
 }
 
 size_t batched_lds_bytes() {
-    return (size_t)(kBlock / 64) * (kSlots * kSlotWords * 8 + kSlots * 4);
+    return (size_t)(kBlock / 64) * (kSlots * kSlotWords * 8 + (kSlots + 1) * 4);
 }
 
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,

@@ -92,3 +92,26 @@ def test_batch_rejects_mixed_precision():
         batch.transport([a, b], [(0, 1), (0, 1)])
     assert ei.value.code == karl.EINVAL
     a.close(), b.close(), batch.close()
+
+
+def test_many_jobs_counters_equal_alone():
+    """64 jobs in one batch: waves meet more jobs than they have counter slots, so slots are
+    taken over and flushed; every job's counters (and all integer tallies) must still equal
+    the job transported alone, and births/deletions must balance per job."""
+    from paper_2503_10263_amd import karl
+    ws = W.cfg_batched(n_jobs=64, scale=0.004)
+    for w in ws:
+        w.n_primaries = min(max(w.n_primaries, 20), 400)
+    jobs = [karl.Job(w, precision="fp32", queue_capacity=1024) for w in ws]
+    batch = karl.Batch(max_jobs=64, queue_capacity=1 << 18)
+    batch.transport(jobs, [(0, w.n_primaries) for w in ws])
+    for k, (w, job) in enumerate(zip(ws, jobs)):
+        g = job.read_tallies()
+        c = g["counters"]
+        n_ion = sum(int(c[16 + i]) for i, p in enumerate(w.processes) if p.kind == W.IONIZATION)
+        assert c[0] == w.n_primaries + n_ion and c[1] == n_ion, f"job {k}"
+        alone, _ = run_gpu(w, [(0, w.n_primaries)], precision="fp32")
+        for key in ["counters", "recomb", "jz", "jr", "spectra"]:
+            np.testing.assert_array_equal(g[key], alone[key], err_msg=f"job {k}: {key}")
+        job.close()
+    batch.close()
