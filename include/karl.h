@@ -48,6 +48,18 @@ enum { KARL_ELASTIC = 0, KARL_EXCITATION = 1, KARL_IONIZATION = 2, KARL_RECOMBIN
 enum { KARL_TARGET_GAS = 0, KARL_TARGET_ION_FIELD = 1 };
 enum { KARL_SOURCE_BETA = 0, KARL_SOURCE_BEAM = 1 };
 enum { KARL_FP64 = 0, KARL_FP32 = 1 };
+/* how karl_transport maps flights onto the device (job descriptor field `mapping`):
+   KARL_MAP_LANE  one particle per lane, one flight segment per step;
+   KARL_MAP_WAVE  one particle per lane, but a particle whose last segment ended on a z-face
+                  (guiding-centre mode) has its flight advanced by the whole wave: lane k takes
+                  segment k with its own free-path draw, up to 64 segments at once;
+   KARL_MAP_AUTO  run the job's first chunk with LANE, measure its flight segments per
+                  interaction, and use WAVE from the next chunk on if that is at least 32 (the
+                  crossover measured on MI355X).
+   The free path is redrawn at every face (Sec. 3.1) from a draw keyed by the step, so segment k
+   needs nothing from segments before it: results do not depend on the mapping.  Straight-line
+   jobs and batched launches use LANE. */
+enum { KARL_MAP_AUTO = 0, KARL_MAP_LANE = 1, KARL_MAP_WAVE = 2 };
 
 /* job flags */
 #define KARL_FLAG_DIGESTS 1u   /* per-primary 64-bit digest of the event sequence          */
@@ -131,6 +143,7 @@ typedef struct {
     int64_t chunk;                /* initial primaries per launch; 0: 65536 */
     void* workspace;              /* device memory, >= karl_workspace_bytes() */
     uint64_t workspace_bytes;
+    int32_t mapping;              /* KARL_MAP_AUTO, KARL_MAP_LANE or KARL_MAP_WAVE */
 } karl_job_desc;
 
 /* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements:
@@ -188,6 +201,14 @@ karl_status karl_reset_tallies(void* job, void* hip_stream);
    secondary generations processed, *max_queue the largest generation. */
 karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches,
                            int64_t* generations, int64_t* max_queue);
+
+/* The mapping karl_transport uses for this job (KARL_MAP_LANE or KARL_MAP_WAVE; KARL_MAP_AUTO
+   while not yet tuned), the segments per interaction that chose it (0 if not tuned), the kernel
+   time per flight segment of the last chunk run with each mapping (0 if none), and the segments
+   advanced by wave-cooperative flights so far.  Any pointer may be NULL. */
+karl_status karl_job_mapping(void* job, int32_t* mapping, double* segments_per_interaction,
+                             double* ms_per_segment_lane, double* ms_per_segment_wave,
+                             int64_t* wave_segments);
 
 /* Release host resources of the job (the caller still owns the workspace). */
 karl_status karl_destroy_job(void* job);

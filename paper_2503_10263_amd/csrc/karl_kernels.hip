@@ -268,6 +268,7 @@ struct Part {
     int64_t n_int;
     bool alive;
     bool start;            // fetched, not yet started
+    bool fly;              // the last segment ended on a z-face (guiding-centre mode)
 };
 
 template <typename Real>
@@ -305,6 +306,20 @@ __device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int id
         case KARL_C_COLL: if (sp) ++lc.coll1; else ++lc.coll0; break;
         case KARL_C_ZCROSS: if (sp) ++lc.zc1; else ++lc.zc0; break;
         default: if (sp) ++lc.rc1; else ++lc.rc0; break;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void count_evn(const Lds<Real>& L, LaneCnt& lc, int idx, int sp, uint32_t n) {
+    if (L.direct) {
+        atomicAdd(&L.cnt[idx + sp], (unsigned long long)n);
+        return;
+    }
+    switch (idx) {
+        case KARL_C_STEP: if (sp) lc.step1 += n; else lc.step0 += n; break;
+        case KARL_C_COLL: if (sp) lc.coll1 += n; else lc.coll0 += n; break;
+        case KARL_C_ZCROSS: if (sp) lc.zc1 += n; else lc.zc0 += n; break;
+        default: if (sp) lc.rc1 += n; else lc.rc0 += n; break;
     }
 }
 
@@ -798,6 +813,7 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     p.e_exc = p.e_bind = p.e_gas = 0.0;
     p.s_path = (Real)0;
     p.alive = true;
+    p.fly = false;
     p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1])) : (Real)0;
     p.dg = mix64(p.lin ^ kDIGEST0);
     atomicAdd(&L.cnt[KARL_C_BIRTH + p.sp], 1ull);
@@ -814,11 +830,26 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     }
 }
 
+// energy bin of a plane spectrum: 0 below the first edge, n_bins+1 at or above the last
+__device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) {
+    const double* ed = J.edges + (size_t)sp * (J.n_bins + 1);
+    if (ee < ed[0]) return 0;
+    if (!(ee < ed[J.n_bins])) return J.n_bins + 1;
+    int lo = 0, hi = J.n_bins;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ed[mid] <= ee) lo = mid;
+        else hi = mid;
+    }
+    return lo + 1;
+}
+
 // ---------------------------------------------------------------- one flight segment
 template <typename Real>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    p.fly = false;
     // batched launches serve the lanes of a wave by (job, species): the species is uniform and
     // the process metadata below become scalar loads
     const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
@@ -997,26 +1028,14 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         ev(p, 3u, (uint32_t)dir, (uint32_t)(p.ir * (J.n_z + 1) + fz), dig);
         const int pl = J.plane_of[fz];
         if (pl >= 0) {
-            const double* ed = J.edges + (size_t)sp * (J.n_bins + 1);
-            const double ee = (double)p.e;
-            int bin;
-            if (ee < ed[0]) bin = 0;
-            else if (!(ee < ed[J.n_bins])) bin = J.n_bins + 1;
-            else {
-                int lo = 0, hi = J.n_bins;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (ed[mid] <= ee) lo = mid;
-                    else hi = mid;
-                }
-                bin = lo + 1;
-            }
+            const int bin = spectrum_bin(J, sp, (double)p.e);
             add_u64(&J.spectra[(((size_t)sp * J.n_planes + (size_t)pl) * 2 + (size_t)dir) * (J.n_bins + 2) + (size_t)bin], 1ull);
             ev(p, 5u, (uint32_t)(pl * 2 + dir), (uint32_t)bin, dig);
         }
         if (fz == 0) kill(J, L, p, KARL_EXIT_LOW);
         else if (fz == J.n_z) kill(J, L, p, KARL_EXIT_HIGH);
         else p.iz = dir ? fz : fz - 1;
+        p.fly = J.gc != 0;
     } else {
         // ---- r-face (straight-line transport) ----
         const int out = (which == 2);
@@ -1034,6 +1053,155 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     }
     p.s += 1u;
     if (p.alive && p.t_alive >= sel2(sp, J.lifetime[0], J.lifetime[1])) kill(J, L, p, KARL_LIFETIME);
+}
+
+
+// ---------------------------------------------------------------- wave-cooperative flight
+// Values of lane j (a wave-uniform index) for every lane.
+__device__ __forceinline__ int bc_i(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
+__device__ __forceinline__ uint32_t bc_u(uint32_t x, int j) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, j);
+}
+__device__ __forceinline__ unsigned long long bc_u64(unsigned long long x, int j) {
+    const uint32_t lo = bc_u((uint32_t)x, j), hi = bc_u((uint32_t)(x >> 32), j);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double bc_r(double x, int j) {
+    return __longlong_as_double((long long)bc_u64((unsigned long long)__double_as_longlong(x), j));
+}
+__device__ __forceinline__ float bc_r(float x, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
+
+// The flight of the particle in lane j, computed by the whole wave (guiding-centre mode, where
+// a flight only meets z-faces).  Lane k takes the k-th flight segment from the particle's
+// position: its cell, its own free-path draw (step ordinal s+k: the draws are keyed by step,
+// so segment k needs nothing from segments before it), the distance to its far face, and
+// whether the draw ends inside the segment.  The particle then crosses every face before the
+// first segment with an interaction, the tube end, or 64 faces, with the tallies of each
+// crossing made by its lane.  Everything a later step reads is accumulated in step order:
+// time alive and path length by a wave-uniform loop over the crossed segments, the event
+// digest likewise.  The interaction itself is left to the next regular step, which draws the
+// same numbers, so results equal those of segment-by-segment transport.
+template <typename Real>
+__device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+                            LaneCnt& lc, int j) {
+    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    const int k = (int)lane_id();
+    const Real z = bc_r(p.z, j), w = bc_r(p.w, j), e = bc_r(p.e, j), vel = bc_r(p.vel, j);
+    const int iz = bc_i(p.iz, j), ir = bc_i(p.ir, j), sp = bc_i(p.sp, j);
+    const uint32_t s = bc_u(p.s, j), pid = bc_u(p.pid, j);
+    const unsigned long long lin = bc_u64(p.lin, j);
+    const int dir = (w > (Real)0) ? 1 : 0;
+    const int izk = dir ? iz + k : iz - k;
+    const bool inside = izk >= 0 && izk < J.n_z;
+    const int izc = inside ? izk : iz;              // lanes past the tube end load valid cells
+    const int fz = dir ? izc + 1 : izc;             // far face of segment k
+    // rates in the segment's cell at the particle's energy (the arithmetic of step())
+    const Real exs = e * (Real)sel2(sp, J.gfrac[0], J.gfrac[1]);
+    const Real xl = klog(exs * (Real)sel2(sp, J.inv_emin[0], J.inv_emin[1])) *
+                    (Real)sel2(sp, J.inv_dlog[0], J.inv_dlog[1]);
+    int kt;
+    Real f;
+    if (!(xl > (Real)0)) {
+        kt = 0;
+        f = (Real)0;
+    } else if (xl >= (Real)(J.n_e - 1)) {
+        kt = J.n_e - 2;
+        f = (Real)1;
+    } else {
+        kt = (int)xl;
+        f = xl - (Real)kt;
+    }
+    const Real n_gas_cell = L.ngas[izc];
+    const Real n_ion_cell = sel2(sp, J.uses_ion_field[0], J.uses_ion_field[1])
+                                ? (Real)J.n_ion[(size_t)ir * J.n_z + (size_t)izc] : (Real)0;
+    const int np = sel2(sp, J.nps[0], J.nps[1]);
+    const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
+    Real sum = (Real)0;
+    for (int q = 0; q < np; ++q) {
+        const int i = pidx[q];
+        Real sig = (Real)0;
+        if (!(exs < L.eth[i])) {
+            const Real* tb = L.xs + (size_t)i * J.n_e;
+            sig = tb[kt] + f * (tb[kt + 1] - tb[kt]);
+        }
+        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+        sum += nt * sig;
+    }
+    const Pair<Real> q0 = draw<Real>(J.seed, pid, lin, s + (uint32_t)k, 0u);
+    const Real eta = q0.d0 + Prec<Real>::eps;
+    const Real dist = (sum > (Real)0) ? -klog(eta) / sum : (Real)INFINITY;
+    const Real zs = (k == 0) ? z : L.zf[dir ? izc : izc + 1];
+    Real sg = (L.zf[fz] - zs) / w;
+    if (sg < (Real)0) sg = (Real)0;
+    const bool coll = inside && (dist < sg);
+    const bool at_end = inside && !coll && (fz == 0 || fz == J.n_z);
+    const unsigned long long cmask = __ballot(coll), emask = __ballot(at_end);
+    const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
+    const int ke = emask ? __ffsll((long long)emask) - 1 : 64;
+    int m = kc;
+    if (ke < kc) m = ke + 1;                       // the tube end comes first
+    if (m == 0) {
+        if (k == j) p.fly = false;
+        return;
+    }
+    if (k == 0 && G.wave_segments) atomicAdd(G.wave_segments, (unsigned long long)m);
+    const Real dt = sg / vel;
+    // time alive and path length in step order; a step whose time reaches the lifetime ends
+    // the flight (the particle is deleted after that crossing)
+    double ta = bc_r(p.t_alive, j);
+    Real path = bc_r(p.s_path, j);
+    const double life = sel2(sp, J.lifetime[0], J.lifetime[1]);
+    bool life_end = false;
+    for (int kk = 0; kk < m; ++kk) {
+        ta += (double)bc_r(dt, kk);
+        path += bc_r(sg, kk);
+        if (kk != ke && ta >= life) {
+            m = kk + 1;
+            life_end = true;
+            break;
+        }
+    }
+    // tallies of the crossed segments, one lane each
+    const int bin = spectrum_bin(J, sp, (double)e);
+    if (k < m) {
+        if (dist != dist || sum != sum) atomicOr(J.status, STATUS_NUMERIC);
+        const double tc = (k == 0) ? bc_r(p.t_cell, j) + (double)dt : (double)dt;
+        if (tc != 0.0) add_f64(&J.dens[((size_t)sp * J.n_r + (size_t)ir) * J.n_z + (size_t)izk], tc);
+        add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)ir) * (J.n_z + 1) + (size_t)fz) * 2 + (size_t)dir], 1ull);
+        const int pl = J.plane_of[fz];
+        if (pl >= 0)
+            add_u64(&J.spectra[(((size_t)sp * J.n_planes + (size_t)pl) * 2 + (size_t)dir) * (J.n_bins + 2) + (size_t)bin], 1ull);
+    }
+    unsigned long long dg = bc_u64(p.dg, j);
+    if (dig)
+        for (int kk = 0; kk < m; ++kk) {
+            const int fk = dir ? iz + kk + 1 : iz - kk;
+            dg = digest_event(dg, s + (uint32_t)kk, 3u, (uint32_t)dir, (uint32_t)(ir * (J.n_z + 1) + fk));
+            const int pl = J.plane_of[fk];
+            if (pl >= 0) dg = digest_event(dg, s + (uint32_t)kk, 5u, (uint32_t)(pl * 2 + dir), (uint32_t)bin);
+        }
+    if (k == j) {
+        const int fl = dir ? iz + m : iz - m + 1;  // the last face crossed
+        p.z = L.zf[fl];
+        p.t_cell = 0.0;
+        p.t_alive = ta;
+        p.s_path = path;
+        p.dg = dg;
+        count_evn(L, lc, KARL_C_STEP, sp, (uint32_t)m);
+        count_evn(L, lc, KARL_C_ZCROSS, sp, (uint32_t)m);
+        if (ke < 64 && m == ke + 1) {
+            p.s = s + (uint32_t)(m - 1);
+            kill(J, L, p, fl == 0 ? KARL_EXIT_LOW : KARL_EXIT_HIGH);
+            p.s += 1u;
+        } else {
+            p.iz = dir ? fl : fl - 1;
+            p.s = s + (uint32_t)m;
+            if (life_end) kill(J, L, p, KARL_LIFETIME);
+        }
+        p.fly = p.alive && m == 64;
+    }
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -1218,8 +1386,9 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 // kBatched = false: one job (jobs[0]); its tables are staged in LDS and its event counters
 // reduced in LDS.  kBatched = true: every lane carries a job index; the lanes of a wave are
 // served job by job (one pass per distinct job, normally one) so that the job's parameters are
-// read with scalar loads.
-template <typename Real, bool kBatched>
+// read with scalar loads.  kCoop (one job, guiding-centre mode): before each step, the flights
+// of particles that just crossed a face are advanced by the whole wave (coop_flight).
+template <typename Real, bool kBatched, bool kCoop = false>
 __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1286,6 +1455,14 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
         if (__ballot(need)) refill<Real, kBatched>(G, p, need, done, wjob);
         if (!__ballot(!done)) break;
         if (!kBatched) {
+            if (kCoop) {
+                unsigned long long cm = __ballot(p.alive && !p.start && p.fly);
+                while (cm) {
+                    const int j = __ffsll((long long)cm) - 1;
+                    cm &= cm - 1ull;
+                    coop_flight(jobs[0], L0, G, p, lc, j);
+                }
+            }
             if (p.alive || p.start) advance(jobs[0], L0, G, p, lc);
         } else {
             bool todo = p.alive || p.start;
@@ -1434,18 +1611,20 @@ size_t lds_bytes(const DevJob& j, int precision) {
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_transport(const DevJob* jobs_dev, const DevJob& job0, bool batched,
-                            const GenArgs& g, int precision, int grid, int block, size_t lds,
-                            hipStream_t s) {
-    (void)job0;
+hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, const GenArgs& g,
+                            int precision, int grid, int block, size_t lds, hipStream_t s) {
     if (precision == KARL_FP32) {
         if (batched)
             hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else if (coop)
+            hipLaunchKernelGGL((transport_kernel<float, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         else
             hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
     } else {
         if (batched)
             hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else if (coop)
+            hipLaunchKernelGGL((transport_kernel<double, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         else
             hipLaunchKernelGGL((transport_kernel<double, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
     }
@@ -1488,14 +1667,19 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int precision, bool batched, int block, size_t lds, int* blocks_per_cu) {
+hipError_t transport_occupancy(int precision, bool batched, bool coop, int block, size_t lds,
+                               int* blocks_per_cu) {
     if (precision == KARL_FP32) {
         if (batched)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
+        if (coop)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, true>, block, lds);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false>, block, lds);
     }
     if (batched)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
+    if (coop)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, true>, block, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false>, block, lds);
 }
 

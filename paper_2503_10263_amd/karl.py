@@ -21,6 +21,8 @@ NLEDGER = 24
 NHIST = 4
 NREASON = 8
 FP64, FP32 = 0, 1
+MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
+MAPPINGS = {"auto": MAP_AUTO, "lane": MAP_LANE, "wave": MAP_WAVE}
 FLAG_DIGESTS, FLAG_HISTORY = 1, 2
 # counter indices (KARL_C_* of include/karl.h); pairs are [electron, ion]
 C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 2, 4, 6, 8
@@ -32,7 +34,8 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
-                "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_destroy_job",
+                "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_job_mapping",
+                "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
                 "karl_batch_stats", "karl_destroy_batch",
                 "karl_server_workspace_bytes", "karl_create_server", "karl_server_submit",
@@ -72,7 +75,8 @@ class JobDesc(C.Structure):
                 ("reserved0", C.c_int32), ("planes", C.POINTER(C.c_int32)),
                 ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
                 ("queue_capacity", C.c_int64), ("chunk", C.c_int64),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
+                ("mapping", C.c_int32)]
 
 
 class ServerDesc(C.Structure):
@@ -117,6 +121,9 @@ def lib():
         L.karl_reset_tallies.argtypes = [C.c_void_p, C.c_void_p]
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.karl_job_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64)]
         L.karl_destroy_job.argtypes = [C.c_void_p]
         L.karl_batch_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_uint64)]
         L.karl_create_batch.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_uint64,
@@ -162,7 +169,7 @@ class Descriptor:
     """karl_job_desc built from a workload; keeps its host arrays alive."""
 
     def __init__(self, w, precision: int = FP64, flags: int = 0, queue_capacity: int = 0,
-                 chunk: int = 0):
+                 chunk: int = 0, mapping: int = MAP_AUTO):
         self.keep = []
         d = JobDesc()
         d.radius, d.length, d.n_r, d.n_z = w.radius, w.length, w.n_r, w.n_z
@@ -207,6 +214,7 @@ class Descriptor:
         d.flags = flags
         d.queue_capacity = queue_capacity
         d.chunk = chunk
+        d.mapping = mapping
         self.d = d
 
     def _hold(self, a, dtype):
@@ -239,13 +247,13 @@ class Job:
     """One transport job on the current HIP device (workspace allocated by torch)."""
 
     def __init__(self, w, precision: str = "fp64", digests: bool = False, history: bool = False,
-                 queue_capacity: int = 0, chunk: int = 0, device=None):
+                 queue_capacity: int = 0, chunk: int = 0, device=None, mapping: str = "auto"):
         import torch
         self.w = w
         self.precision = FP32 if precision == "fp32" else FP64
         flags = (FLAG_DIGESTS if digests else 0) | (FLAG_HISTORY if history else 0)
         self.digests, self.history = digests, history
-        self.desc = Descriptor(w, self.precision, flags, queue_capacity, chunk)
+        self.desc = Descriptor(w, self.precision, flags, queue_capacity, chunk, MAPPINGS[mapping])
         self.nbytes = self.desc.workspace_bytes()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -284,6 +292,16 @@ class Job:
         check(lib().karl_job_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
         return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
                 "max_queue": q.value}
+
+    def mapping(self) -> Dict[str, float]:
+        """Mapping in use ("auto" until tuned), the segments per interaction that chose it, kernel
+        ms per segment of each mapping, segments advanced by wave-cooperative flights."""
+        m, r, a, b, n = C.c_int32(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        check(lib().karl_job_mapping(self.h, C.byref(m), C.byref(r), C.byref(a), C.byref(b),
+                                     C.byref(n)))
+        name = {v: k for k, v in MAPPINGS.items()}[m.value]
+        return {"mapping": name, "segments_per_interaction": r.value, "ms_per_segment_lane": a.value,
+                "ms_per_segment_wave": b.value, "wave_segments": n.value}
 
     def close(self):
         if getattr(self, "h", None):
