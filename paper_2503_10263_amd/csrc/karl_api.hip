@@ -230,6 +230,7 @@ struct Launcher {
     size_t lds = 0;
     int max_blocks = 0;
     int max_blocks_coop = 0;                // single-job launches with wave-cooperative flights
+    int max_blocks_drain = 0;               // single-job deferred-queue launches
     bool coop = false;                      // launch the wave-cooperative kernel
     unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -262,14 +263,17 @@ struct Launcher {
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, dev));
         int per_cu = 0;
-        HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, kBlock, lds, &per_cu));
+        HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, false, kBlock, lds, &per_cu));
         if (per_cu < 1) per_cu = 1;
         max_blocks = per_cu * prop.multiProcessorCount;
-        max_blocks_coop = max_blocks;
+        max_blocks_coop = max_blocks_drain = max_blocks;
         if (!is_batched) {
-            HIP_CHECK(karl::transport_occupancy(prec, false, true, kBlock, lds, &per_cu));
+            HIP_CHECK(karl::transport_occupancy(prec, false, true, false, kBlock, lds, &per_cu));
             if (per_cu < 1) per_cu = 1;
             max_blocks_coop = per_cu * prop.multiProcessorCount;
+            HIP_CHECK(karl::transport_occupancy(prec, false, false, true, kBlock, lds, &per_cu));
+            if (per_cu < 1) per_cu = 1;
+            max_blocks_drain = per_cu * prop.multiProcessorCount;
         }
         HIP_CHECK(hipHostMalloc((void**)&host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
         HIP_CHECK(hipEventCreate(&ev0));
@@ -311,10 +315,12 @@ struct Launcher {
         unsigned long long* qcount = ctl + 1;
         unsigned long long* dcount = ctl + 3;
         HIP_CHECK(karl::launch_fill_u64(dcount, 2, 0ull, s));
+        bool drain = false;
         for (;;) {
             if (items == 0) {
                 if (ndef == 0) break;
                 // the generations are exhausted: drain the deferred queue in one launch
+                drain = true;
                 in = &dq[di];
                 items = ndef;
                 mode = 1;
@@ -354,13 +360,14 @@ struct Launcher {
                 HIP_CHECK(karl::launch_fill_u64(job_fetch, (size_t)n_jobs, 0ull, s));
                 HIP_CHECK(karl::launch_fill_u64(job_waves, (size_t)n_jobs, 0ull, s));
             }
-            const bool use_coop = coop && !batched;
-            const int64_t cap_blocks = use_coop ? max_blocks_coop : max_blocks;
+            const bool use_drain = drain && !batched;
+            const bool use_coop = coop && !batched && !use_drain;
+            const int64_t cap_blocks = use_drain ? max_blocks_drain : use_coop ? max_blocks_coop : max_blocks;
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > cap_blocks) blocks = cap_blocks;
             HIP_CHECK(hipEventRecord(ev0, s));
-            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, g, precision, (int)blocks,
-                                             kBlock, lds, s));
+            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, g, precision,
+                                             (int)blocks, kBlock, lds, s));
             HIP_CHECK(hipEventRecord(ev1, s));
             HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, s));

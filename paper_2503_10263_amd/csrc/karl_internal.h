@@ -111,8 +111,9 @@ struct GenArgs {
 enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 
 size_t lds_bytes(const DevJob& j, int precision);
-hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, const GenArgs& g,
-                            int precision, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain,
+                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            hipStream_t s);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
 // Regroup n queue entries by job: count per job, exclusive scan into first/count, scatter.
@@ -121,8 +122,8 @@ hipError_t launch_sort_by_job(const QueueSoA& in, const QueueSoA& out, int64_t n
                               unsigned long long* cursor, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
                            hipStream_t s);
-hipError_t transport_occupancy(int precision, bool batched, bool coop, int block, size_t lds,
-                               int* blocks_per_cu);
+hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, int block,
+                               size_t lds, int* blocks_per_cu);
 size_t batched_lds_bytes();
 
 }  // namespace karl

@@ -845,7 +845,9 @@ __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) 
 }
 
 // ---------------------------------------------------------------- one flight segment
-template <typename Real>
+// kDrain: the launch that runs the deferred queue, whose species have no ionization process
+// (the job setup defers exactly those); the ionization branch is left out of that kernel.
+template <typename Real, bool kDrain = false>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
@@ -998,7 +1000,14 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                 break;
             }
             case KARL_IONIZATION:
-                k_ionization(J, L, G, p, pi, xc, yc, lc);
+                if constexpr (kDrain) {
+                    // cannot happen for a deferred species; flag it rather than go on silently
+                    atomicOr(J.status, STATUS_NUMERIC);
+                    kill(J, L, p, KARL_LIFETIME);
+                    killed = true;
+                } else {
+                    k_ionization(J, L, G, p, pi, xc, yc, lc);
+                }
                 break;
             default:
                 add_u64(&J.recomb[(size_t)p.ir * J.n_z + (size_t)p.iz], 1ull);
@@ -1362,12 +1371,12 @@ __device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool nee
 }
 
 // One unit of work for a lane: start its fetched particle, or move it by one flight segment.
-template <typename Real>
+template <typename Real, bool kDrain = false>
 __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, const GenArgs& G,
                                         Part<Real>& p, LaneCnt& lc) {
     if (p.start) {
         p.start = false;
-        if (G.mode == 0) {
+        if (!kDrain && G.mode == 0) {
             birth(J, L, p.pid, p, lc);
             if (L.direct) atomicAdd(&L.led[KARL_L_E_PRIMARY], (double)p.e);
             else lc.e_prim += (double)p.e;
@@ -1375,7 +1384,7 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
         }
         start_particle(J, L, p, lc);
     } else {
-        step(J, L, G, p, lc);
+        step<Real, kDrain>(J, L, G, p, lc);
     }
 }
 
@@ -1387,8 +1396,10 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 // reduced in LDS.  kBatched = true: every lane carries a job index; the lanes of a wave are
 // served job by job (one pass per distinct job, normally one) so that the job's parameters are
 // read with scalar loads.  kCoop (one job, guiding-centre mode): before each step, the flights
-// of particles that just crossed a face are advanced by the whole wave (coop_flight).
-template <typename Real, bool kBatched, bool kCoop = false>
+// of particles that just crossed a face are advanced by the whole wave (coop_flight).  kDrain
+// (one job): the deferred-queue launch, without the birth and ionization code, which leaves
+// the kernel half the registers and twice the waves per SIMD.
+template <typename Real, bool kBatched, bool kCoop = false, bool kDrain = false>
 __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1463,7 +1474,7 @@ __global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
                     coop_flight(jobs[0], L0, G, p, lc, j);
                 }
             }
-            if (p.alive || p.start) advance(jobs[0], L0, G, p, lc);
+            if (p.alive || p.start) advance<Real, kDrain>(jobs[0], L0, G, p, lc);
         } else {
             bool todo = p.alive || p.start;
             const int key = 2 * p.job + (p.start ? 0 : p.sp);
@@ -1611,8 +1622,16 @@ size_t lds_bytes(const DevJob& j, int precision) {
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, const GenArgs& g,
-                            int precision, int grid, int block, size_t lds, hipStream_t s) {
+hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain,
+                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            hipStream_t s) {
+    if (drain && !batched) {
+        if (precision == KARL_FP32)
+            hipLaunchKernelGGL((transport_kernel<float, false, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<double, false, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        return hipGetLastError();
+    }
     if (precision == KARL_FP32) {
         if (batched)
             hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
@@ -1667,8 +1686,13 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int precision, bool batched, bool coop, int block, size_t lds,
-                               int* blocks_per_cu) {
+hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, int block,
+                               size_t lds, int* blocks_per_cu) {
+    if (drain && !batched) {
+        if (precision == KARL_FP32)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, true>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, true>, block, lds);
+    }
     if (precision == KARL_FP32) {
         if (batched)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
