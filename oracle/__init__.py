@@ -55,13 +55,14 @@ class _Process(C.Structure):
 class _Desc(C.Structure):
     _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
                 ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
-                ("n_ion", C.POINTER(C.c_double)), ("t_gas", C.c_double), ("m_gas", C.c_double),
+                ("n_ion", C.POINTER(C.c_double)), ("n_elec", C.POINTER(C.c_double)),
+                ("t_gas", C.c_double), ("m_gas", C.c_double),
                 ("bz", C.c_double), ("sp", _Species * 2), ("n_proc", C.c_int32),
                 ("n_e", C.c_int32), ("proc", _Process * MAX_PROC), ("source", C.c_int32),
                 ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
                 ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
                 ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
-                ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
+                ("beam_energy_1", C.c_double), ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
                 ("pad2", C.c_int32), ("planes", C.POINTER(C.c_int32)),
                 ("n_primaries", C.c_int64)]
 
@@ -138,6 +139,10 @@ class Desc:
             n_ion = np.ascontiguousarray(w.n_ion, dtype=np.float64)
             self.keep.append(n_ion)
             d.n_ion = _dptr(n_ion)
+        if getattr(w, "n_elec", None) is not None:
+            n_elec = np.ascontiguousarray(w.n_elec, dtype=np.float64)
+            self.keep.append(n_elec)
+            d.n_elec = _dptr(n_elec)
         d.t_gas = w.t_gas
         d.m_gas = w.m_gas
         d.bz = w.bz
@@ -173,6 +178,7 @@ class Desc:
         d.beta_z = w.beta_z
         d.beta_fmax = w.beta_fmax
         d.beam_energy = w.beam_energy
+        d.beam_energy_1 = getattr(w, "beam_energy_1", 0.0)
         for k in range(3):
             d.beam_pos[k] = w.beam_pos[k]
             d.beam_dir[k] = w.beam_dir[k]
@@ -192,7 +198,7 @@ def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.
         "counters": np.zeros(NCOUNTERS, np.int64),
         "ledger": np.zeros(NLEDGER, np.float64),
         "density_time": np.zeros((2, w.n_r, w.n_z), np.float64),
-        "recomb": np.zeros((w.n_r, w.n_z), np.int64),
+        "recomb": np.zeros((2, w.n_r, w.n_z), np.int64),
         "jz": np.zeros((2, w.n_r, w.n_z + 1, 2), np.int64),
         "jr": np.zeros((2, w.n_r + 1, w.n_z, 2), np.int64),
         "spectra": np.zeros((2, len(w.planes), 2, nb + 2), np.int64),

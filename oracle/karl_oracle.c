@@ -700,8 +700,13 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
         for (int j = 0; j < np; ++j) {
             const ko_process* pr = &d->proc[pidx[j]];
             double nt;
-            if (pr->target == KO_TARGET_GAS) nt = d->n_gas[p->iz];
-            else nt = d->n_ion ? d->n_ion[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
+            if (pr->target == KO_TARGET_GAS) {
+                nt = d->n_gas[p->iz];
+            } else {
+                /* the density field of the other species (Sec. 2.2) */
+                const double* f = (p->sp == 0) ? d->n_ion : d->n_elec;
+                nt = f ? f[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
+            }
             rate[j] = nt * p->sig[j];
             sum += rate[j];
         }
@@ -807,8 +812,9 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
                 p->e_bind += pr->e_th;
                 p->e_gas += out.gas;
                 for (int j = 0; j < out.n; ++j) push(c, &out.s[j]);
-            } else { /* recombination */
-                T->recomb[(size_t)p->ir * d->n_z + (size_t)p->iz] += 1;
+            } else { /* recombination: one deletion logged in the partner's field (Sec. 3.3) */
+                const int partner = 1 - p->sp;
+                T->recomb[((size_t)partner * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz] += 1;
                 kill(c, p, KO_RECOMBINED);
                 killed = 1;
             }
@@ -867,11 +873,15 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
 static void birth(ctx_t* c, uint32_t pid, seed_t* b, int64_t* tries) {
     const ko_desc* d = c->d;
     b->lineage = 0;
-    if (d->source == KO_SOURCE_BEAM) {
+    if (d->source == KO_SOURCE_BEAM || d->source == KO_SOURCE_PAIR) {
         b->sp = d->beam_species;
+        b->e = d->beam_energy;
+        if (d->source == KO_SOURCE_PAIR) {
+            b->sp = (int)(pid & 1u);
+            b->e = b->sp ? d->beam_energy_1 : d->beam_energy;
+        }
         b->x = d->beam_pos[0]; b->y = d->beam_pos[1]; b->z = d->beam_pos[2];
         b->u = d->beam_dir[0]; b->v = d->beam_dir[1]; b->w = d->beam_dir[2];
-        b->e = d->beam_energy;
         b->ir = count_faces_le(c->rf, d->n_r, sqrt(b->x * b->x + b->y * b->y));
         b->iz = count_faces_le(c->zf, d->n_z, b->z);
         return;
@@ -967,7 +977,7 @@ int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activ
             for (int iz = 0; iz < nz; ++iz) {
                 size_t k = ((size_t)s * nr + ir) * nz + iz;
                 double n = t->density_time[k] / (t_sim * vol);
-                if (s == 1) n -= (double)t->recomb[(size_t)ir * nz + iz] / vol;
+                n -= (double)t->recomb[k] / vol;
                 density[k] = n;
             }
             for (int f = 0; f <= nz; ++f) {

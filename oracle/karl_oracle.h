@@ -23,8 +23,12 @@ extern "C" {
 #define KO_MAX_PROC 16
 
 enum { KO_ELASTIC = 0, KO_EXCITATION = 1, KO_IONIZATION = 2, KO_RECOMBINATION = 3 };
-enum { KO_TARGET_GAS = 0, KO_TARGET_ION = 1 };
-enum { KO_SOURCE_BETA = 0, KO_SOURCE_BEAM = 1 };
+/* KO_TARGET_FIELD: the density field of the other species (electrons meet the ion field, ions
+   the electron field), Sec. 2.2 "Density fields" */
+enum { KO_TARGET_GAS = 0, KO_TARGET_FIELD = 1 };
+/* KO_SOURCE_PAIR: both species from the beam position and direction, even primary ids electrons
+   at beam_energy, odd ids ions at beam_energy_1 */
+enum { KO_SOURCE_BETA = 0, KO_SOURCE_BEAM = 1, KO_SOURCE_PAIR = 2 };
 enum { KO_EXIT_LOW = 0, KO_EXIT_HIGH, KO_WALL, KO_CUTOFF, KO_RECOMBINED, KO_CAP,
        KO_LIFETIME, KO_UNTRACKED, KO_NREASON };
 
@@ -68,7 +72,7 @@ typedef struct {
 typedef struct {
     int32_t kind;         /* KO_ELASTIC ... */
     int32_t species;      /* projectile slot: 0 electron, 1 ion */
-    int32_t target;       /* KO_TARGET_GAS or KO_TARGET_ION */
+    int32_t target;       /* KO_TARGET_GAS or KO_TARGET_FIELD */
     int32_t pad;
     double e_th;          /* excitation energy or binding energy (eV); 0 otherwise */
     const double* xs;     /* [n_e] cross section (m^2) at the species' nodes */
@@ -78,7 +82,8 @@ typedef struct {
     double radius, length;       /* m */
     int32_t n_r, n_z;            /* grid (>= 1 each) */
     const double* n_gas;         /* [n_z] gas density per z-cell (m^-3) */
-    const double* n_ion;         /* [n_r*n_z] ion target field (m^-3) or NULL */
+    const double* n_ion;         /* [n_r*n_z] ion density field, target of electrons (m^-3) or NULL = 0 */
+    const double* n_elec;        /* [n_r*n_z] electron density field, target of ions, or NULL = 0 */
     double t_gas;                /* K */
     double m_gas;                /* kg */
     double bz;                   /* T; 0: straight lines */
@@ -88,6 +93,7 @@ typedef struct {
     int32_t source, beam_species;
     double beta_e0, beta_z, beta_fmax;
     double beam_energy, beam_pos[3], beam_dir[3];
+    double beam_energy_1;        /* ion energy of KO_SOURCE_PAIR (eV) */
     uint32_t seed;
     int32_t n_bins;
     int32_t n_planes, pad2;
@@ -99,7 +105,7 @@ typedef struct {
     int64_t* counters;     /* [KO_NCOUNTERS] */
     double* ledger;        /* [KO_NLEDGER] */
     double* density_time;  /* [2][n_r][n_z] seconds */
-    int64_t* recomb;       /* [n_r][n_z] */
+    int64_t* recomb;       /* [2][n_r][n_z] recombinations logged in the field of each species */
     int64_t* jz;           /* [2][n_r][n_z+1][2] */
     int64_t* jr;           /* [2][n_r+1][n_z][2] */
     int64_t* spectra;      /* [2][n_planes][2][n_bins+2] */
@@ -111,7 +117,7 @@ typedef struct {
 int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t);
 
 /* Densities per species and segment, eq. (3) with t_sim = n_prim/activity, eq. (4), minus the
-   recombinations per volume for the ion species; currents (N+ - N-)/(A t_sim) through the
+   recombinations logged in that species' field per volume; currents (N+ - N-)/(A t_sim) through the
    z-faces of each ring ([2][n_r][n_z+1]) and the r-faces of each z-segment ([2][n_r+1][n_z]). */
 int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activity,
               double* density, double* jz_cur, double* jr_cur);

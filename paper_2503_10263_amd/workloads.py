@@ -46,11 +46,13 @@ KIND_NAMES = {ELASTIC: "elastic", EXCITATION: "excitation",
 
 # target of a process: the background gas or the frozen ion-density field
 TARGET_GAS = 0
-TARGET_ION_FIELD = 1
+TARGET_FIELD = 1            # the density field of the other species (Sec. 2.2)
+TARGET_ION_FIELD = TARGET_FIELD
 
 # primary source
 SOURCE_BETA = 0
 SOURCE_BEAM = 1
+SOURCE_PAIR = 2             # beam of both species: even ids electrons, odd ids ions
 
 # species slots
 ELECTRON = 0
@@ -90,7 +92,7 @@ class Process:
     """One interaction channel (Sec. "Interactions")."""
     kind: int
     species: int                # projectile species slot
-    target: int                 # TARGET_GAS or TARGET_ION_FIELD
+    target: int                 # TARGET_GAS or TARGET_FIELD
     e_th: float                 # eV: excitation energy / binding energy; 0 otherwise
     xs: np.ndarray              # [n_e] cross section in m^2 at the species' nodes
     name: str = ""
@@ -105,7 +107,7 @@ class Workload:
     n_r: int
     n_z: int
     n_gas: np.ndarray           # [n_z] m^-3, cell-averaged
-    n_ion: Optional[np.ndarray] # [n_r*n_z] m^-3 or None
+    n_ion: Optional[np.ndarray] # [n_r*n_z] m^-3 ion field (target of electrons) or None
     t_gas: float                # K
     m_gas: float                # kg
     bz: float                   # T; 0 selects straight-line transport
@@ -123,6 +125,8 @@ class Workload:
     seed: int = 1
     planes: List[int] = field(default_factory=list)   # z-face indices
     n_primaries: int = 0
+    n_elec: Optional[np.ndarray] = None   # [n_r*n_z] m^-3 electron field (target of ions)
+    beam_energy_1: float = 0.0            # eV: ion energy of SOURCE_PAIR
 
     @property
     def n_bins(self) -> int:
@@ -335,6 +339,29 @@ def beam_problem(energy: float, processes: List[Process], n_gas: np.ndarray, len
         beam_species=beam_species, beam_energy=energy, beam_pos=tuple(beam_pos),
         beam_dir=tuple(beam_dir), seed=seed, planes=[0, n_z] if planes is None else planes,
         n_primaries=n_primaries)
+
+
+def recombination_pair(sigma_e: float, sigma_i: float, n_primaries: int = 20000, n_z: int = 40,
+                       length: float = 1.0, radius: float = 0.05, e_electron: float = 2.0,
+                       seed: int = 11, n_elec: Optional[np.ndarray] = None,
+                       n_ion: Optional[np.ndarray] = None) -> Workload:
+    """Electrons and H2+ ions injected together on the axis at z = 0 along +z with equal speeds
+    (ion energy = electron energy x M/m), no gas: the only process of each species is
+    recombination with the density field of the other (constant cross sections sigma_e,
+    sigma_i).  The coupled steady state of Sec. 4 "Recombination" (both partners variable)."""
+    e_ion = e_electron * M_H2P / M_E
+    species = [electron(e_cut=0.0, emin=1.0e-3, emax=2.0e4, edges=np.linspace(0.0, 10.0, 11)),
+               Species("H2+", M_H2P, QE, True, 0.0, 1_000_000, math.inf, 1.0e-3, 2.0e4,
+                       np.linspace(0.0, 1.0e4, 11))]
+    procs = [Process(RECOMBINATION, ELECTRON, TARGET_FIELD, 0.0, np.full(64, sigma_e), "e recombination"),
+             Process(RECOMBINATION, ION, TARGET_FIELD, 0.0, np.full(64, sigma_i), "ion recombination")]
+    return Workload(
+        name="recombination pair", radius=radius, length=length, n_r=1, n_z=n_z,
+        n_gas=np.zeros(n_z), n_ion=n_ion, t_gas=0.0, m_gas=M_H2, bz=0.0, species=species,
+        processes=procs, n_e=64, source=SOURCE_PAIR, beam_species=ELECTRON,
+        beam_energy=e_electron, beam_energy_1=e_ion, beam_pos=(0.0, 0.0, 0.0),
+        beam_dir=(0.0, 0.0, 1.0), seed=seed, planes=[0, n_z], n_primaries=n_primaries,
+        n_elec=n_elec)
 
 
 def with_primaries(w: Workload, n: int) -> Workload:

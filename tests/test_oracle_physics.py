@@ -50,7 +50,7 @@ def test_attenuation_exponential_law(oracle_lib):
     z = (trans - N * p) / math.sqrt(N * p * (1 - p))
     assert abs(z) < 4.0
     # absorption positions: counts per cell against the exponential law
-    counts = t["recomb"][0]
+    counts = t["recomb"][1, 0]      # electron recombinations are logged in the ion field
     zf = np.linspace(0.0, L, n_z + 1)
     prob = np.exp(-mu * zf[:-1]) - np.exp(-mu * zf[1:])
     exp_counts = N * prob

@@ -113,8 +113,9 @@ def _check_conservation(oracle_lib, w, n):
     total_out = L[oracle_lib.L_E_DEATH:oracle_lib.L_E_DEATH + 16].sum() + \
         L[oracle_lib.L_E_EXC] + L[oracle_lib.L_E_BIND] + L[oracle_lib.L_E_GAS]
     assert abs(total_out / L[oracle_lib.L_E_PRIMARY] - 1.0) < 1e-12
-    # recombination deletions equal the recombination tally
-    assert deaths[0, W.REASONS.index("recombined")] == t["recomb"].sum()
+    # recombination deletions equal the deletions logged in the partner's field
+    assert deaths[0, W.REASONS.index("recombined")] == t["recomb"][1].sum()
+    assert deaths[1, W.REASONS.index("recombined")] == t["recomb"][0].sum()
     return t
 
 
