@@ -45,8 +45,13 @@ typedef int32_t karl_status;
 #define KARL_MAX_PROC 16
 
 enum { KARL_ELASTIC = 0, KARL_EXCITATION = 1, KARL_IONIZATION = 2, KARL_RECOMBINATION = 3 };
-enum { KARL_TARGET_GAS = 0, KARL_TARGET_ION_FIELD = 1 };
-enum { KARL_SOURCE_BETA = 0, KARL_SOURCE_BEAM = 1 };
+/* target of a process: the gas, or the density field of the other species (electrons meet
+   the ion field, ions the electron field; Sec. 2.2 "Density fields"); TARGET_ION_FIELD is the
+   older name of the electrons' case */
+enum { KARL_TARGET_GAS = 0, KARL_TARGET_FIELD = 1, KARL_TARGET_ION_FIELD = 1 };
+/* KARL_SOURCE_PAIR: both species from the beam position and direction, even primary ids
+   electrons at beam_energy, odd ids ions at beam_energy_1 */
+enum { KARL_SOURCE_BETA = 0, KARL_SOURCE_BEAM = 1, KARL_SOURCE_PAIR = 2 };
 enum { KARL_FP64 = 0, KARL_FP32 = 1 };
 /* how karl_transport maps flights onto the device (job descriptor field `mapping`):
    KARL_MAP_LANE  one particle per lane, one flight segment per step;
@@ -109,7 +114,7 @@ typedef struct {
 typedef struct {
     int32_t kind;           /* KARL_ELASTIC ... KARL_RECOMBINATION */
     int32_t species;        /* projectile: 0 electron slot, 1 ion slot */
-    int32_t target;         /* KARL_TARGET_GAS or KARL_TARGET_ION_FIELD */
+    int32_t target;         /* KARL_TARGET_GAS or KARL_TARGET_FIELD */
     int32_t reserved0;
     double e_th;            /* eV: excitation energy or ionization binding energy; 0 else */
     const double* xs;       /* [n_e] cross section (m^2) at the projectile species' nodes */
@@ -119,7 +124,8 @@ typedef struct {
     double radius, length;        /* cylinder r <= radius, 0 <= z <= length (m) */
     int32_t n_r, n_z;             /* segments of the density/current grid (>= 1) */
     const double* n_gas;          /* [n_z] gas density per z-segment (m^-3) */
-    const double* n_ion;          /* [n_r*n_z] ion-density target field (m^-3) or NULL */
+    const double* n_ion;          /* [n_r*n_z] ion density field, target of electrons (m^-3); NULL: 0 */
+    const double* n_elec;         /* [n_r*n_z] electron density field, target of ions; NULL: 0 */
     double t_gas;                 /* gas temperature (K); 0: target at rest */
     double m_gas;                 /* gas molecule mass (kg) */
     double bz;                    /* axial field (T); 0 selects straight-line transport */
@@ -127,10 +133,11 @@ typedef struct {
     int32_t n_proc;               /* <= KARL_MAX_PROC */
     int32_t n_e;                  /* cross-section nodes per table, 2..1024 */
     karl_process_desc proc[KARL_MAX_PROC];
-    int32_t source;               /* KARL_SOURCE_BETA or KARL_SOURCE_BEAM */
+    int32_t source;               /* KARL_SOURCE_BETA, KARL_SOURCE_BEAM or KARL_SOURCE_PAIR */
     int32_t beam_species;
     double beta_e0, beta_z, beta_fmax;  /* endpoint (eV), daughter charge, shape bound */
     double beam_energy, beam_pos[3], beam_dir[3];
+    double beam_energy_1;         /* ion energy of KARL_SOURCE_PAIR (eV) */
     uint32_t seed;
     int32_t n_bins;               /* spectrum bins per species (edges hold n_bins+1) */
     int32_t n_planes;             /* spectrum planes, each a z-face index 0..n_z */
@@ -148,14 +155,15 @@ typedef struct {
 
 /* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements:
    counters KARL_NCOUNTERS; ledger KARL_NLEDGER; density_time 2*n_r*n_z;
-   recomb n_r*n_z; jz 2*n_r*(n_z+1)*2; jr 2*(n_r+1)*n_z*2; spectra 2*n_planes*2*(n_bins+2);
+   recomb 2*n_r*n_z; jz 2*n_r*(n_z+1)*2; jr 2*(n_r+1)*n_z*2; spectra 2*n_planes*2*(n_bins+2);
    digests n_primaries (needs KARL_FLAG_DIGESTS); hist n_primaries*KARL_NHIST
    (needs KARL_FLAG_HISTORY).  Index order is row-major in the order written. */
 typedef struct {
     int64_t* counters;
     double* ledger;
     double* density_time;   /* [species][r][z] seconds spent per segment (eq. 3 numerator) */
-    int64_t* recomb;        /* [r][z] recombinations N_gamma (eq. 3) */
+    int64_t* recomb;        /* [species][r][z] recombinations logged in that species' field:
+                               N_gamma of eq. 3 (made by the other species) */
     int64_t* jz;            /* [species][r][z-face][dir] crossings, dir 1 = +z (Sec. 2.3) */
     int64_t* jr;            /* [species][r-face][z][dir] crossings, dir 1 = outward */
     int64_t* spectra;       /* [species][plane][dir][bin] with under/overflow bins 0, n_bins+1 */
@@ -185,13 +193,21 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream);
 /* Normalised fields (S12 readout) from the tallies of all primaries transported since creation
    or the last reset, N_prim: the simulated time is t_sim = N_prim / activity (eq. 4, activity
    in decays per second); density[species][r][z] = (time spent in the segment)/(t_sim V) minus,
-   for the ion species, the recombinations in the segment per volume (eq. 3); jz_current
+   the recombinations logged in that species' field in the segment per volume (eq. 3); jz_current
    [species][r][z-face] and jr_current[species][r-face][z] = (N+ - N-)/(A t_sim) through the
    face (current collection, Sec. 2.3), in particles per m^2 per s; A of r-face 0 is zero and
    its current is reported as 0.  Sizes 2*n_r*n_z, 2*n_r*(n_z+1), 2*(n_r+1)*n_z doubles; NULL
    pointers are skipped.  KARL_ESTATE if nothing was transported. */
 karl_status karl_read_fields(void* job, double activity, double* density, double* jz_current,
                              double* jr_current, void* hip_stream);
+
+/* Self-consistent target fields (Sec. 2.2 "Density fields", Sec. 3.6 cycles): set the density
+   field of each species, which processes of the other species with KARL_TARGET_FIELD see, to
+   that species' density from the tallies of all primaries transported so far, eq. (3) with
+   t_sim = N_prim / activity (eq. 4), negative values set to zero.  Calling it after every
+   cycle of primaries makes the later cycles interact with the particles of the earlier ones.
+   No effect on a job without field targets; KARL_ESTATE if nothing was transported. */
+karl_status karl_update_target_fields(void* job, double activity, void* hip_stream);
 
 /* Zero the tallies and the count of transported primaries. */
 karl_status karl_reset_tallies(void* job, void* hip_stream);

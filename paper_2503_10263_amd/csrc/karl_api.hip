@@ -46,7 +46,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte offsets of every region of a job's workspace.
 struct Layout {
-    size_t devjob, xs, n_gas, zf, rf, zcdf, n_ion, edges, plane_of;
+    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of;
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
     size_t snapshot, control, fields, queues, queue_entries;
@@ -54,6 +54,13 @@ struct Layout {
 };
 
 size_t real_size(const karl_job_desc* d) { return d->precision == KARL_FP32 ? 4 : 8; }
+
+// some process targets a species' density field (then both fields get device storage)
+bool uses_fields(const karl_job_desc* d) {
+    for (int i = 0; i < d->n_proc && i < KARL_MAX_PROC; ++i)
+        if (d->proc[i].target == KARL_TARGET_FIELD) return true;
+    return false;
+}
 
 Layout make_layout(const karl_job_desc* d) {
     Layout L{};
@@ -71,7 +78,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.zf = take(rs * (nz + 1));
     L.rf = take(rs * (nr + 1));
     L.zcdf = take(rs * (nz + 1));
-    L.n_ion = take(d->n_ion ? 8 * nr * nz : 0);
+    L.tfield = take(uses_fields(d) ? 8 * 2 * nr * nz : 0);
     L.edges = take(8 * 2 * ((size_t)d->n_bins + 1));
     L.plane_of = take(4 * (nz + 1));
     // tallies: one contiguous block so that a snapshot is one copy
@@ -85,7 +92,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.t_counters = tk(8 * KARL_NCOUNTERS);
     L.t_ledger = tk(8 * KARL_NLEDGER);
     L.t_dens = tk(8 * 2 * nr * nz);
-    L.t_recomb = tk(8 * nr * nz);
+    L.t_recomb = tk(8 * 2 * nr * nz);
     L.t_jz = tk(8 * 2 * nr * (nz + 1) * 2);
     L.t_jr = tk(8 * 2 * (nr + 1) * nz * 2);
     L.t_spectra = tk(8 * 2 * (size_t)d->n_planes * 2 * ((size_t)d->n_bins + 2));
@@ -123,10 +130,13 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     for (int k = 0; k < d->n_z; ++k)
         if (!std::isfinite(d->n_gas[k]) || d->n_gas[k] < 0.0)
             return fail(KARL_EINVAL, "n_gas[%d] must be finite and >= 0", k);
-    if (d->n_ion)
-        for (int k = 0; k < d->n_r * d->n_z; ++k)
-            if (!std::isfinite(d->n_ion[k]) || d->n_ion[k] < 0.0)
-                return fail(KARL_EINVAL, "n_ion[%d] must be finite and >= 0", k);
+    for (int f = 0; f < 2; ++f) {
+        const double* fld = f ? d->n_elec : d->n_ion;
+        if (fld)
+            for (int k = 0; k < d->n_r * d->n_z; ++k)
+                if (!std::isfinite(fld[k]) || fld[k] < 0.0)
+                    return fail(KARL_EINVAL, "%s[%d] must be finite and >= 0", f ? "n_elec" : "n_ion", k);
+    }
     if (!std::isfinite(d->t_gas) || d->t_gas < 0.0) return fail(KARL_EINVAL, "t_gas must be >= 0");
     if (!finite_pos(d->m_gas)) return fail(KARL_EINVAL, "m_gas must be positive");
     if (!std::isfinite(d->bz)) return fail(KARL_EINVAL, "bz must be finite");
@@ -149,7 +159,7 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
         if (p.kind < KARL_ELASTIC || p.kind > KARL_RECOMBINATION)
             return fail(KARL_EINVAL, "process %d: unknown kind %d", i, p.kind);
         if (p.species < 0 || p.species > 1) return fail(KARL_EINVAL, "process %d: species", i);
-        if (p.target != KARL_TARGET_GAS && p.target != KARL_TARGET_ION_FIELD)
+        if (p.target != KARL_TARGET_GAS && p.target != KARL_TARGET_FIELD)
             return fail(KARL_EINVAL, "process %d: target", i);
         if (!p.xs) return fail(KARL_EINVAL, "process %d: table missing", i);
         if (!std::isfinite(p.e_th) || p.e_th < 0.0) return fail(KARL_EINVAL, "process %d: e_th", i);
@@ -162,10 +172,12 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     if (d->source == KARL_SOURCE_BETA) {
         if (!finite_pos(d->beta_e0) || !finite_pos(d->beta_fmax) || !std::isfinite(d->beta_z))
             return fail(KARL_EINVAL, "beta source needs e0 > 0 and f_max > 0");
-    } else if (d->source == KARL_SOURCE_BEAM) {
+    } else if (d->source == KARL_SOURCE_BEAM || d->source == KARL_SOURCE_PAIR) {
         if (d->beam_species < 0 || d->beam_species > 1 || !std::isfinite(d->beam_energy) ||
             d->beam_energy < 0.0)
             return fail(KARL_EINVAL, "beam needs a species slot and an energy >= 0");
+        if (d->source == KARL_SOURCE_PAIR && (!std::isfinite(d->beam_energy_1) || d->beam_energy_1 < 0.0))
+            return fail(KARL_EINVAL, "a pair beam needs an ion energy >= 0");
         const double n = std::sqrt(d->beam_dir[0] * d->beam_dir[0] + d->beam_dir[1] * d->beam_dir[1] +
                                    d->beam_dir[2] * d->beam_dir[2]);
         if (!(std::fabs(n - 1.0) < 1e-9)) return fail(KARL_EINVAL, "beam direction must be a unit vector");
@@ -646,8 +658,15 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     TRY(upload_real(*j, L.zf, zf));
     TRY(upload_real(*j, L.rf, rf));
     TRY(upload_real(*j, L.zcdf, zcdf));
-    if (d->n_ion)
-        TRY_HIP(hipMemcpy(j->ws + L.n_ion, d->n_ion, sizeof(double) * (size_t)nr * nz, hipMemcpyHostToDevice));
+    if (uses_fields(d)) {
+        // field[0] electrons (target of ions), field[1] ions (target of electrons); absent: 0
+        TRY_HIP(karl::launch_fill_u64((unsigned long long*)(j->ws + L.tfield), (size_t)2 * nr * nz, 0ull, nullptr));
+        if (d->n_elec)
+            TRY_HIP(hipMemcpy(j->ws + L.tfield, d->n_elec, sizeof(double) * (size_t)nr * nz, hipMemcpyHostToDevice));
+        if (d->n_ion)
+            TRY_HIP(hipMemcpy(j->ws + L.tfield + 8 * (size_t)nr * nz, d->n_ion, sizeof(double) * (size_t)nr * nz,
+                              hipMemcpyHostToDevice));
+    }
     TRY_HIP(hipMemcpy(j->ws + L.edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
     TRY_HIP(hipMemcpy(j->ws + L.plane_of, plane_of.data(), sizeof(int32_t) * plane_of.size(), hipMemcpyHostToDevice));
 
@@ -666,7 +685,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.beam_species = d->beam_species;
     J.flags = (int32_t)d->flags;
     J.seed = d->seed;
-    J.n_ion_present = d->n_ion ? 1 : 0;
+    J.reserved0 = 0;
     for (int s = 0; s < 2; ++s) {
         const karl_species_desc& sp = d->species[s];
         J.tracked[s] = sp.tracked ? 1 : 0;
@@ -687,7 +706,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.e_from_v2[s] = 0.5 * sp.mass / kQE;
         J.v2_from_e[s] = 2.0 * kQE / sp.mass;
         J.nps[s] = 0;
-        J.uses_ion_field[s] = 0;
+        J.uses_field[s] = 0;
         J.defer[s] = 0;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
@@ -699,7 +718,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     for (int i = 0; i < d->n_proc; ++i) {
         const int s = d->proc[i].species;
         J.pidx[s][J.nps[s]++] = i;
-        if (d->proc[i].target == KARL_TARGET_ION_FIELD && d->n_ion) J.uses_ion_field[s] = 1;
+        if (d->proc[i].target == KARL_TARGET_FIELD) J.uses_field[s] = 1;
     }
     // A species without ionization never produces secondaries: its particles can wait in the
     // deferred queue and run together in one launch after the other generations.
@@ -715,6 +734,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.beta_z = d->beta_z;
     J.beta_fmax = d->beta_fmax;
     J.beam_e = d->beam_energy;
+    J.beam_e1 = d->beam_energy_1;
     for (int k = 0; k < 3; ++k) {
         J.beam_pos[k] = d->beam_pos[k];
         J.beam_dir[k] = d->beam_dir[k];
@@ -727,7 +747,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.zf = w + L.zf;
     J.rf = w + L.rf;
     J.zcdf = w + L.zcdf;
-    J.n_ion = d->n_ion ? (const double*)(w + L.n_ion) : nullptr;
+    J.field[0] = uses_fields(d) ? (double*)(w + L.tfield) : nullptr;
+    J.field[1] = uses_fields(d) ? (double*)(w + L.tfield + 8 * (size_t)nr * nz) : nullptr;
     J.edges = (const double*)(w + L.edges);
     J.plane_of = (const int32_t*)(w + L.plane_of);
     char* t = w + L.tallies;
@@ -791,7 +812,7 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     if ((st = get(out->counters, J.counters, 8 * KARL_NCOUNTERS)) != KARL_OK) return st;
     if ((st = get(out->ledger, J.ledger, 8 * KARL_NLEDGER)) != KARL_OK) return st;
     if ((st = get(out->density_time, J.dens, 8 * 2 * nr * nz)) != KARL_OK) return st;
-    if ((st = get(out->recomb, J.recomb, 8 * nr * nz)) != KARL_OK) return st;
+    if ((st = get(out->recomb, J.recomb, 8 * 2 * nr * nz)) != KARL_OK) return st;
     if ((st = get(out->jz, J.jz, 8 * 2 * nr * (nz + 1) * 2)) != KARL_OK) return st;
     if ((st = get(out->jr, J.jr, 8 * 2 * (nr + 1) * nz * 2)) != KARL_OK) return st;
     if ((st = get(out->spectra, J.spectra, 8 * 2 * (size_t)j->n_planes * 2 * ((size_t)j->n_bins + 2))) != KARL_OK)
@@ -829,6 +850,20 @@ karl_status karl_read_fields(void* job, double activity, double* density, double
     if (density) HIP_CHECK(hipMemcpy(density, f, 8 * n_dens, hipMemcpyDeviceToHost));
     if (jz_current) HIP_CHECK(hipMemcpy(jz_current, f + n_dens, 8 * n_jz, hipMemcpyDeviceToHost));
     if (jr_current) HIP_CHECK(hipMemcpy(jr_current, f + n_dens + n_jz, 8 * n_jr, hipMemcpyDeviceToHost));
+    return KARL_OK;
+}
+
+karl_status karl_update_target_fields(void* job, double activity, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_EINVAL, "job is NULL");
+    if (!(activity > 0.0) || !std::isfinite(activity))
+        return fail(KARL_EINVAL, "activity must be positive and finite");
+    if (j->n_transported <= 0) return fail(KARL_ESTATE, "no primaries transported since the last reset");
+    if (!j->dj.field[0]) return KARL_OK;   // no process targets a field
+    HIP_CHECK(hipSetDevice(j->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(karl::launch_target_fields(j->dj, (double)j->n_transported / activity, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     return KARL_OK;
 }
 

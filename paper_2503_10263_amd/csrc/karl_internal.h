@@ -30,9 +30,9 @@ struct DevJob {
     int32_t n_r, n_z, n_e, n_proc, n_bins, n_planes;
     int32_t gc, source, beam_species, flags;
     uint32_t seed;
-    int32_t beam_ir, beam_iz, n_ion_present;
+    int32_t beam_ir, beam_iz, reserved0;
     int32_t nps[2];
-    int32_t uses_ion_field[2];   // a process of the species targets the ion field (and n_ion exists)
+    int32_t uses_field[2];       // a process of the species targets the other species' field
     int32_t defer[2];            // products of this species go to the deferred queue
     int32_t tracked[2];
     int64_t cap[2];
@@ -49,7 +49,7 @@ struct DevJob {
     double sigma_v;        // sqrt(k T / m_gas)
     double m_gas;
     double beta_e0, beta_z, beta_fmax;
-    double beam_e, beam_pos[3], beam_dir[3];
+    double beam_e, beam_e1, beam_pos[3], beam_dir[3];
     int32_t pidx[2][KARL_MAX_PROC];   // global process index of the j-th process of a species
     int32_t kind[KARL_MAX_PROC];
     int32_t target[KARL_MAX_PROC];
@@ -61,7 +61,7 @@ struct DevJob {
     const void* zf;        // [n_z+1] z faces
     const void* rf;        // [n_r+1] r faces
     const void* zcdf;      // [n_z+1] cumulative gas weights
-    const double* n_ion;   // [n_r*n_z]
+    double* field[2];      // [n_r*n_z] density field of each species (m^-3), or NULL
     const double* edges;   // [2][n_bins+1]
     const int32_t* plane_of;   // [n_z+1] plane index or -1
     // tallies
@@ -114,6 +114,7 @@ size_t lds_bytes(const DevJob& j, int precision);
 hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain,
                             const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s);
+hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
 // Regroup n queue entries by job: count per job, exclusive scan into first/count, scatter.

@@ -732,15 +732,19 @@ __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Re
                       LaneCnt& lc) {
     p.lin = 0ull;
     p.pid = pid;
-    if (J.source == KARL_SOURCE_BEAM) {
+    if (J.source == KARL_SOURCE_BEAM || J.source == KARL_SOURCE_PAIR) {
         p.sp = J.beam_species;
+        p.e = (Real)J.beam_e;
+        if (J.source == KARL_SOURCE_PAIR) {
+            p.sp = (int32_t)(pid & 1u);
+            p.e = (Real)(p.sp ? J.beam_e1 : J.beam_e);
+        }
         p.x = (Real)J.beam_pos[0];
         p.y = (Real)J.beam_pos[1];
         p.z = (Real)J.beam_pos[2];
         p.u = (Real)J.beam_dir[0];
         p.v = (Real)J.beam_dir[1];
         p.w = (Real)J.beam_dir[2];
-        p.e = (Real)J.beam_e;
         p.ir = J.beam_ir;
         p.iz = J.beam_iz;
         return;
@@ -872,8 +876,10 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         f = xl - (Real)k;
     }
     const Real n_gas_cell = L.ngas[p.iz];
-    const Real n_ion_cell = sel2(sp, J.uses_ion_field[0], J.uses_ion_field[1])
-                                ? (Real)J.n_ion[(size_t)p.ir * J.n_z + (size_t)p.iz] : (Real)0;
+    // density field of the other species (Sec. 2.2), for processes that target it
+    const Real n_fld_cell = sel2(sp, J.uses_field[0], J.uses_field[1])
+                                ? (Real)(sp ? J.field[0] : J.field[1])[(size_t)p.ir * J.n_z + (size_t)p.iz]
+                                : (Real)0;
     const int np = sel2(sp, J.nps[0], J.nps[1]);
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
@@ -884,7 +890,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             const Real* tb = L.xs + (size_t)i * J.n_e;
             sig = tb[k] + f * (tb[k + 1] - tb[k]);
         }
-        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
         sum += nt * sig;
     }
     const Pair<Real> q0 = draw<Real>(J.seed, p.pid, p.lin, p.s, 0u);
@@ -961,7 +967,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                 const Real* tb = L.xs + (size_t)i * J.n_e;
                 sig = tb[k] + f * (tb[k + 1] - tb[k]);
             }
-            const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+            const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
             const Real rate = nt * sig;
             run += rate;
             if (rate > (Real)0) last = j;
@@ -1010,7 +1016,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                 }
                 break;
             default:
-                add_u64(&J.recomb[(size_t)p.ir * J.n_z + (size_t)p.iz], 1ull);
+                // one deletion logged in the partner's field (Sec. 3.3 "Recombination")
+                add_u64(&J.recomb[((size_t)(1 - sp) * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], 1ull);
                 kill(J, L, p, KARL_RECOMBINED);
                 killed = true;
                 break;
@@ -1123,8 +1130,9 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
         f = xl - (Real)kt;
     }
     const Real n_gas_cell = L.ngas[izc];
-    const Real n_ion_cell = sel2(sp, J.uses_ion_field[0], J.uses_ion_field[1])
-                                ? (Real)J.n_ion[(size_t)ir * J.n_z + (size_t)izc] : (Real)0;
+    const Real n_fld_cell = sel2(sp, J.uses_field[0], J.uses_field[1])
+                                ? (Real)(sp ? J.field[0] : J.field[1])[(size_t)ir * J.n_z + (size_t)izc]
+                                : (Real)0;
     const int np = sel2(sp, J.nps[0], J.nps[1]);
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
@@ -1135,7 +1143,7 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
             const Real* tb = L.xs + (size_t)i * J.n_e;
             sig = tb[kt] + f * (tb[kt + 1] - tb[kt]);
         }
-        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_ion_cell;
+        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
         sum += nt * sig;
     }
     const Pair<Real> q0 = draw<Real>(J.seed, pid, lin, s + (uint32_t)k, 0u);
@@ -1546,8 +1554,10 @@ __global__ void fields_kernel(const DevJob J, double t_sim, double* density, dou
             const double r1 = J.radius * (double)(ir + 1) / (double)nr;
             const double ring = kPI * (r1 * r1 - r0 * r0);
             const double vol = ring * dz;
+            (void)s;
+            (void)iz;
             double n = J.dens[t] / (t_sim * vol);
-            if (s == 1) n -= (double)J.recomb[(size_t)ir * nz + iz] / vol;
+            n -= (double)J.recomb[t] / vol;
             density[t] = n;
         } else if (t < n_dens + n_jz) {
             const size_t k = t - n_dens;
@@ -1565,6 +1575,25 @@ __global__ void fields_kernel(const DevJob J, double t_sim, double* density, dou
             const double net = (double)((long long)J.jr[2 * k + 1] - (long long)J.jr[2 * k]);
             jr_cur[k] = (area > 0.0) ? net / (area * t_sim) : 0.0;
         }
+    }
+}
+
+// Target fields for the next cycle (Sec. 2.2, Sec. 3.6): the density of each species from the
+// tallies so far, eq. (3) with t_sim = N_prim / activity (eq. 4), negative values set to zero.
+__global__ void target_fields_kernel(const DevJob J, double t_sim) {
+    const int nr = J.n_r, nz = J.n_z;
+    const double dz = J.length / (double)nz;
+    const size_t n = (size_t)2 * nr * nz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(t / ((size_t)nr * nz));
+        const size_t cell = t % ((size_t)nr * nz);
+        const int ir = (int)(cell / nz);
+        const double r0 = J.radius * (double)ir / (double)nr;
+        const double r1 = J.radius * (double)(ir + 1) / (double)nr;
+        const double vol = kPI * (r1 * r1 - r0 * r0) * dz;
+        double d = J.dens[t] / (t_sim * vol);
+        d -= (double)J.recomb[t] / vol;
+        if (J.field[s]) J.field[s][cell] = d > 0.0 ? d : 0.0;
     }
 }
 
@@ -1661,6 +1690,14 @@ hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double*
     size_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fields_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, t_sim, density, jz, jr);
+    return hipGetLastError();
+}
+
+hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s) {
+    const size_t total = (size_t)2 * j.n_r * j.n_z;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(target_fields_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, t_sim);
     return hipGetLastError();
 }
 

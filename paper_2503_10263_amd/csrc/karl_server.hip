@@ -48,7 +48,7 @@ constexpr int kFloorWindow = 8;
 // A job descriptor together with copies of every host array it points to.
 struct OwnedDesc {
     karl_job_desc d{};
-    std::vector<double> n_gas, n_ion, edges[2], xs[KARL_MAX_PROC];
+    std::vector<double> n_gas, n_ion, n_elec, edges[2], xs[KARL_MAX_PROC];
     std::vector<int32_t> planes;
 
     void copy_from(const karl_job_desc& s) {
@@ -58,6 +58,10 @@ struct OwnedDesc {
         if (s.n_ion) {
             n_ion.assign(s.n_ion, s.n_ion + (size_t)s.n_r * s.n_z);
             d.n_ion = n_ion.data();
+        }
+        if (s.n_elec) {
+            n_elec.assign(s.n_elec, s.n_elec + (size_t)s.n_r * s.n_z);
+            d.n_elec = n_elec.data();
         }
         for (int k = 0; k < 2; ++k) {
             edges[k].assign(s.species[k].edges, s.species[k].edges + s.n_bins + 1);

@@ -34,7 +34,8 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
-                "karl_read_fields", "karl_reset_tallies", "karl_job_stats", "karl_job_mapping",
+                "karl_read_fields", "karl_update_target_fields", "karl_reset_tallies",
+                "karl_job_stats", "karl_job_mapping",
                 "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
                 "karl_batch_stats", "karl_destroy_batch",
@@ -65,12 +66,14 @@ class ProcessDesc(C.Structure):
 class JobDesc(C.Structure):
     _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
                 ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
-                ("n_ion", C.POINTER(C.c_double)), ("t_gas", C.c_double), ("m_gas", C.c_double),
+                ("n_ion", C.POINTER(C.c_double)), ("n_elec", C.POINTER(C.c_double)),
+                ("t_gas", C.c_double), ("m_gas", C.c_double),
                 ("bz", C.c_double), ("species", SpeciesDesc * 2), ("n_proc", C.c_int32),
                 ("n_e", C.c_int32), ("proc", ProcessDesc * MAX_PROC), ("source", C.c_int32),
                 ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
                 ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
                 ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
+                ("beam_energy_1", C.c_double),
                 ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
                 ("reserved0", C.c_int32), ("planes", C.POINTER(C.c_int32)),
                 ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
@@ -118,6 +121,7 @@ def lib():
         L.karl_read_tallies.argtypes = [C.c_void_p, C.POINTER(Tallies), C.c_void_p]
         L.karl_read_fields.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
+        L.karl_update_target_fields.argtypes = [C.c_void_p, C.c_double, C.c_void_p]
         L.karl_reset_tallies.argtypes = [C.c_void_p, C.c_void_p]
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -176,6 +180,8 @@ class Descriptor:
         d.n_gas = _dptr(self._hold(w.n_gas, np.float64))
         if w.n_ion is not None:
             d.n_ion = _dptr(self._hold(w.n_ion, np.float64))
+        if getattr(w, "n_elec", None) is not None:
+            d.n_elec = _dptr(self._hold(w.n_elec, np.float64))
         d.t_gas, d.m_gas, d.bz = w.t_gas, w.m_gas, w.bz
         nb = len(w.species[0].edges) - 1
         for s in range(2):
@@ -201,6 +207,7 @@ class Descriptor:
         d.source, d.beam_species = w.source, w.beam_species
         d.beta_e0, d.beta_z, d.beta_fmax = w.beta_e0, w.beta_z, w.beta_fmax
         d.beam_energy = w.beam_energy
+        d.beam_energy_1 = getattr(w, "beam_energy_1", 0.0)
         for k in range(3):
             d.beam_pos[k] = w.beam_pos[k]
             d.beam_dir[k] = w.beam_dir[k]
@@ -232,7 +239,7 @@ def tally_shapes(w, digests: bool, history: bool) -> Dict[str, tuple]:
     nb = len(w.species[0].edges) - 1
     s = {
         "counters": ((NCOUNTERS,), np.int64), "ledger": ((NLEDGER,), np.float64),
-        "density_time": ((2, w.n_r, w.n_z), np.float64), "recomb": ((w.n_r, w.n_z), np.int64),
+        "density_time": ((2, w.n_r, w.n_z), np.float64), "recomb": ((2, w.n_r, w.n_z), np.int64),
         "jz": ((2, w.n_r, w.n_z + 1, 2), np.int64), "jr": ((2, w.n_r + 1, w.n_z, 2), np.int64),
         "spectra": ((2, len(w.planes), 2, nb + 2), np.int64),
     }
@@ -283,6 +290,10 @@ class Job:
     def read_fields(self, activity: float, stream=None) -> Dict[str, np.ndarray]:
         """Densities (m^-3) and currents (m^-2 s^-1) normalised with t_sim = N_prim/activity."""
         return _read_fields(self.h, self.w, activity, stream)
+
+    def update_target_fields(self, activity: float, stream=None):
+        """Set each species' target field to its density from the tallies so far (eq. 3-4)."""
+        check(lib().karl_update_target_fields(self.h, float(activity), self._stream(stream)))
 
     def reset(self, stream=None):
         check(lib().karl_reset_tallies(self.h, self._stream(stream)))
