@@ -49,7 +49,10 @@ class _Species(C.Structure):
 
 class _Process(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
-                ("pad", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double))]
+                ("pad", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
+                ("ang_bins", C.c_int32), ("ang_nodes", C.c_int32), ("e_iso", C.c_double),
+                ("ang_edges", C.POINTER(C.c_double)), ("ang_theta", C.POINTER(C.c_double)),
+                ("ang_pdf", C.POINTER(C.c_double))]
 
 
 class _Desc(C.Structure):
@@ -109,6 +112,8 @@ def lib():
                                        C.c_uint32, C.c_double, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]
         L.ko_debug_collide.restype = C.c_int
+        L.ko_debug_angle.argtypes = [C.POINTER(_Desc), C.c_int, C.c_double, C.c_double]
+        L.ko_debug_angle.restype = C.c_double
         L.ko_debug_helix.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_double, C.c_double,
                                      C.POINTER(C.c_double)]
@@ -172,6 +177,18 @@ class Desc:
             d.proc[i].target = p.target
             d.proc[i].e_th = p.e_th
             d.proc[i].xs = _dptr(xs)
+            ang = getattr(p, "angular", None)
+            if ang is not None:
+                edges = np.ascontiguousarray(ang.edges, dtype=np.float64)
+                theta = np.ascontiguousarray(ang.theta, dtype=np.float64)
+                pdf = np.ascontiguousarray(ang.pdf, dtype=np.float64)
+                self.keep += [edges, theta, pdf]
+                d.proc[i].ang_bins = len(edges) - 1
+                d.proc[i].ang_nodes = len(theta)
+                d.proc[i].e_iso = ang.e_iso
+                d.proc[i].ang_edges = _dptr(edges)
+                d.proc[i].ang_theta = _dptr(theta)
+                d.proc[i].ang_pdf = _dptr(pdf)
         d.source = w.source
         d.beam_species = w.beam_species
         d.beta_e0 = w.beta_e0
@@ -281,6 +298,12 @@ def collide(w, proc: int, pid: int, lineage: int, s: int, e: float, direction) -
     rc = lib().ko_debug_collide(C.byref(D.d), proc, pid, lineage, s, e, _dptr(dr), _dptr(out))
     assert rc == 0
     return out
+
+
+def angle(w, proc: int, e_cm: float, u: float) -> float:
+    """Polar centre-of-mass scattering angle of elastic process `proc` (rad)."""
+    D = Desc(w)
+    return float(lib().ko_debug_angle(C.byref(D.d), int(proc), float(e_cm), float(u)))
 
 
 def helix(charge, mass, bz, pos, direction, speed, path) -> np.ndarray:

@@ -515,7 +515,44 @@ static void set_velocity(part_t* p, double e_from_v2, const double vv[3]) {
     }
 }
 
-static void k_elastic(ctx_t* c, part_t* p, double* gas_out) {
+/* Polar angle from the piecewise linear density of one energy bin (Sec. 3.3): the interval is the
+   one where the running area (trapezoids, left to right) first exceeds u times the total, and
+   inside it the linear density is integrated exactly: f0 x + (s/2) x^2 = r, solved as
+   x = 2 r / (f0 + sqrt(f0^2 + 2 s r)). */
+static double table_angle(const ko_process* pr, int b, double u) {
+    const int n = pr->ang_nodes;
+    const double* th = pr->ang_theta;
+    const double* f = pr->ang_pdf + (size_t)b * n;
+    double total = 0.0;
+    for (int k = 0; k + 1 < n; ++k) total += 0.5 * (f[k] + f[k + 1]) * (th[k + 1] - th[k]);
+    double a = u * total;
+    double run = 0.0;
+    int k = 0;
+    for (; k + 1 < n - 1; ++k) {
+        double next = run + 0.5 * (f[k] + f[k + 1]) * (th[k + 1] - th[k]);
+        if (a < next) break;
+        run = next;
+    }
+    double h = th[k + 1] - th[k];
+    double r = a - run;
+    double s = (f[k + 1] - f[k]) / h;
+    double den = f[k] + sqrt(f[k] * f[k] + 2.0 * s * r);
+    double x = (r > 0.0 && den > 0.0) ? 2.0 * r / den : 0.0;
+    if (x > h) x = h;
+    return th[k] + x;
+}
+
+/* cosine of the centre-of-mass scattering angle for impact energy ecm and uniform u */
+static double scatter_mu(const ko_process* pr, double ecm, double u) {
+    if (pr->ang_bins <= 0 || ecm < pr->e_iso) return 2.0 * u - 1.0;
+    int b = 0;
+    while (b < pr->ang_bins - 1 && ecm >= pr->ang_edges[b + 1]) ++b;
+    double sn, cs;
+    ko_sincos(table_angle(pr, b, u), &sn, &cs);
+    return cs;
+}
+
+static void k_elastic(ctx_t* c, part_t* p, int pi, double* gas_out) {
     const ko_desc* d = c->d;
     const int s = p->sp;
     double v[3] = {p->vel * p->u, p->vel * p->v, p->vel * p->w};
@@ -534,7 +571,9 @@ static void k_elastic(ctx_t* c, part_t* p, double* gas_out) {
     double mf = c->mfrac[s], gf = c->gfrac[s];
     double cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     pair_t q = draw(d->seed, p->pid, p->lineage, p->s, 1);
-    double mu = 2.0 * q.d0 - 1.0;
+    /* impact energy in the centre-of-mass frame selects the angle distribution */
+    double ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * c->e_from_v2[s] * gf;
+    double mu = scatter_mu(&d->proc[pi], ecm, q.d0);
     double phi = TWO_PI * q.d1;
     double gn[3];
     rotate(gh[0], gh[1], gh[2], mu, phi, gn);
@@ -800,7 +839,7 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
             int killed = 0;
             if (pr->kind == KO_ELASTIC) {
                 double gas;
-                k_elastic(c, p, &gas);
+                k_elastic(c, p, pi, &gas);
                 p->e_gas += gas;
             } else if (pr->kind == KO_EXCITATION) {
                 p->e = p->e - pr->e_th;
@@ -1035,7 +1074,7 @@ int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, 
     for (int k = 0; k < 16; ++k) out[k] = 0.0;
     const ko_process* pr = &d->proc[proc];
     if (pr->kind == KO_ELASTIC) {
-        k_elastic(&c, &P, &out[14]);
+        k_elastic(&c, &P, proc, &out[14]);
     } else if (pr->kind == KO_EXCITATION) {
         P.e = P.e - pr->e_th;
     } else if (pr->kind == KO_IONIZATION) {
@@ -1052,6 +1091,12 @@ int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, 
     out[0] = P.e; out[1] = P.u; out[2] = P.v; out[3] = P.w; out[4] = P.alive;
     ctx_free(&c);
     return 0;
+}
+
+double ko_debug_angle(const ko_desc* d, int proc, double e_cm, double u) {
+    if (proc < 0 || proc >= d->n_proc) return -1.0;
+    double mu = scatter_mu(&d->proc[proc], e_cm, u);
+    return acos(mu);
 }
 
 void ko_debug_helix(double charge, double mass, double bz, const double pos[3],

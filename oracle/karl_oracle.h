@@ -76,6 +76,15 @@ typedef struct {
     int32_t pad;
     double e_th;          /* excitation energy or binding energy (eV); 0 otherwise */
     const double* xs;     /* [n_e] cross section (m^2) at the species' nodes */
+    /* elastic scattering angle (Sec. 3.3 "Elastic scattering"): isotropic in the centre-of-mass
+       frame when ang_bins == 0 or the impact energy in that frame is below e_iso; otherwise a
+       piecewise linear density over the polar angle, one per impact-energy bin */
+    int32_t ang_bins;     /* energy bins of the table (0: isotropic) */
+    int32_t ang_nodes;    /* angle nodes per bin (>= 2) */
+    double e_iso;         /* eV: isotropic below this centre-of-mass energy */
+    const double* ang_edges;  /* [ang_bins+1] bin edges in centre-of-mass energy (eV) */
+    const double* ang_theta;  /* [ang_nodes] increasing polar angles (rad) within [0, pi] */
+    const double* ang_pdf;    /* [ang_bins][ang_nodes] density values >= 0 at the nodes */
 } ko_process;
 
 typedef struct {
@@ -133,6 +142,9 @@ uint64_t ko_mix64(uint64_t z);
 double ko_log(double x);
 void ko_sincos(double x, double* s, double* c);
 double ko_beta_shape(double e, double e0, double z);
+/* polar scattering angle (rad) of elastic process `proc` at centre-of-mass energy e_cm for the
+   uniform number u in [0,1) (the table path; isotropic processes return acos(2u-1)) */
+double ko_debug_angle(const ko_desc* d, int proc, double e_cm, double u);
 /* birth state of primary pid: x,y,z,u,v,w,E,tries */
 int ko_birth(const ko_desc* d, int64_t pid, double out[8]);
 /* kinematics of process `proc` for one particle at the origin:

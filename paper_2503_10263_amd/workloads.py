@@ -88,6 +88,17 @@ class Species:
 
 
 @dataclass
+class AngularTable:
+    """Scattering-angle distribution of an elastic process (Sec. 3.3 "Elastic scattering"):
+    isotropic in the centre-of-mass frame below e_iso, above it a piecewise linear density
+    over the polar angle per bin of centre-of-mass impact energy."""
+    edges: np.ndarray           # [n_bins+1] eV
+    theta: np.ndarray           # [n_nodes] rad, increasing within [0, pi]
+    pdf: np.ndarray             # [n_bins][n_nodes] >= 0
+    e_iso: float = 0.0          # eV
+
+
+@dataclass
 class Process:
     """One interaction channel (Sec. "Interactions")."""
     kind: int
@@ -96,6 +107,7 @@ class Process:
     e_th: float                 # eV: excitation energy / binding energy; 0 otherwise
     xs: np.ndarray              # [n_e] cross section in m^2 at the species' nodes
     name: str = ""
+    angular: Optional[AngularTable] = None   # elastic only; None: isotropic
 
 
 @dataclass
@@ -362,6 +374,22 @@ def recombination_pair(sigma_e: float, sigma_i: float, n_primaries: int = 20000,
         beam_energy=e_electron, beam_energy_1=e_ion, beam_pos=(0.0, 0.0, 0.0),
         beam_dir=(0.0, 0.0, 1.0), seed=seed, planes=[0, n_z], n_primaries=n_primaries,
         n_elec=n_elec)
+
+
+def screened_table(e_iso: float = 100.0, n_bins: int = 6, n_nodes: int = 64,
+                   emin: float = 100.0, emax: float = 2.0e4) -> AngularTable:
+    """A composite elastic distribution like the paper's electron case: isotropic below e_iso,
+    above it a forward-peaked screened-Rutherford shape p(theta) ~ sin(theta) / (1 + 2 eta -
+    cos(theta))^2 with screening eta = 3.4 eV / E (stronger forward peak at higher energy),
+    tabulated at the centre of each log-spaced energy bin on nodes denser near 0."""
+    edges = np.geomspace(emin, emax, n_bins + 1)
+    theta = np.pi * np.linspace(0.0, 1.0, n_nodes) ** 2
+    pdf = np.zeros((n_bins, n_nodes))
+    for b in range(n_bins):
+        e = math.sqrt(edges[b] * edges[b + 1])
+        eta = 3.4 / e
+        pdf[b] = np.sin(theta) / (1.0 + 2.0 * eta - np.cos(theta)) ** 2
+    return AngularTable(edges=edges, theta=theta, pdf=pdf, e_iso=e_iso)
 
 
 def with_primaries(w: Workload, n: int) -> Workload:
