@@ -118,6 +118,17 @@ typedef struct {
     int32_t reserved0;
     double e_th;            /* eV: excitation energy or ionization binding energy; 0 else */
     const double* xs;       /* [n_e] cross section (m^2) at the projectile species' nodes */
+    /* elastic scattering angle (Sec. 3.3 "Elastic scattering"): isotropic in the centre-of-mass
+       frame when ang_bins == 0 or the centre-of-mass impact energy is below e_iso (a composite
+       distribution); otherwise drawn from the piecewise linear density over the polar angle of
+       the impact-energy bin (below the first edge: the first bin, from the last edge on: the
+       last).  Elastic processes only. */
+    int32_t ang_bins;       /* energy bins, 0..1024 */
+    int32_t ang_nodes;      /* angle nodes per bin, 2..4096 */
+    double e_iso;           /* eV */
+    const double* ang_edges;  /* [ang_bins+1] increasing centre-of-mass energies (eV) */
+    const double* ang_theta;  /* [ang_nodes] increasing polar angles in [0, pi] (rad) */
+    const double* ang_pdf;    /* [ang_bins][ang_nodes] densities >= 0, positive area per bin */
 } karl_process_desc;
 
 typedef struct {

@@ -32,6 +32,7 @@ karl_status fail(karl_status code, const char* fmt, ...) {
     } while (0)
 
 constexpr double kKB = 1.380649e-23;
+constexpr double kPI_HOST = 3.14159265358979323846;
 constexpr double kQE = 1.602176634e-19;
 constexpr size_t kAlign = 256;
 constexpr int kBlock = 256;
@@ -46,7 +47,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte offsets of every region of a job's workspace.
 struct Layout {
-    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of;
+    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of, angles;
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
     size_t snapshot, control, fields, queues, queue_entries;
@@ -54,6 +55,19 @@ struct Layout {
 };
 
 size_t real_size(const karl_job_desc* d) { return d->precision == KARL_FP32 ? 4 : 8; }
+
+// doubles of a process' angle table on the device: edges, theta, cdf and pdf
+size_t angle_block(const karl_process_desc& p) {
+    if (p.ang_bins <= 0) return 0;
+    const size_t nb = (size_t)p.ang_bins, n = (size_t)p.ang_nodes;
+    return (nb + 1) + n + 2 * nb * n;
+}
+
+size_t angle_doubles(const karl_job_desc* d) {
+    size_t n = 0;
+    for (int i = 0; i < d->n_proc && i < KARL_MAX_PROC; ++i) n += angle_block(d->proc[i]);
+    return n;
+}
 
 // some process targets a species' density field (then both fields get device storage)
 bool uses_fields(const karl_job_desc* d) {
@@ -81,6 +95,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.tfield = take(uses_fields(d) ? 8 * 2 * nr * nz : 0);
     L.edges = take(8 * 2 * ((size_t)d->n_bins + 1));
     L.plane_of = take(4 * (nz + 1));
+    L.angles = take(8 * angle_doubles(d));
     // tallies: one contiguous block so that a snapshot is one copy
     size_t t = 0;
     auto tk = [&](size_t bytes) {
@@ -168,6 +183,28 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
         for (int k = 0; k < d->n_e; ++k)
             if (!std::isfinite(p.xs[k]) || p.xs[k] < 0.0)
                 return fail(KARL_EINVAL, "process %d: cross section %d must be finite and >= 0", i, k);
+        if (p.ang_bins != 0) {
+            if (p.kind != KARL_ELASTIC) return fail(KARL_EINVAL, "process %d: angle table on a non-elastic process", i);
+            if (p.ang_bins < 0 || p.ang_bins > 1024 || p.ang_nodes < 2 || p.ang_nodes > 4096)
+                return fail(KARL_EINVAL, "process %d: angle table needs 1..1024 bins and 2..4096 nodes", i);
+            if (!p.ang_edges || !p.ang_theta || !p.ang_pdf) return fail(KARL_EINVAL, "process %d: angle table missing", i);
+            if (!std::isfinite(p.e_iso) || p.e_iso < 0.0) return fail(KARL_EINVAL, "process %d: e_iso", i);
+            for (int b = 0; b < p.ang_bins; ++b)
+                if (!(p.ang_edges[b] < p.ang_edges[b + 1])) return fail(KARL_EINVAL, "process %d: angle edges must increase", i);
+            if (!(p.ang_theta[0] >= 0.0) || !(p.ang_theta[p.ang_nodes - 1] <= kPI_HOST))
+                return fail(KARL_EINVAL, "process %d: angle nodes must lie in [0, pi]", i);
+            for (int k = 0; k + 1 < p.ang_nodes; ++k)
+                if (!(p.ang_theta[k] < p.ang_theta[k + 1])) return fail(KARL_EINVAL, "process %d: angle nodes must increase", i);
+            for (int b = 0; b < p.ang_bins; ++b) {
+                bool any = false;   // some positive density: the bin has a positive area
+                for (int k = 0; k < p.ang_nodes; ++k) {
+                    const double f = p.ang_pdf[(size_t)b * p.ang_nodes + k];
+                    if (!std::isfinite(f) || f < 0.0) return fail(KARL_EINVAL, "process %d: angle density must be finite and >= 0", i);
+                    any = any || f > 0.0;
+                }
+                if (!any) return fail(KARL_EINVAL, "process %d: angle bin %d has no area", i, b);
+            }
+        }
     }
     if (d->source == KARL_SOURCE_BETA) {
         if (!finite_pos(d->beta_e0) || !finite_pos(d->beta_fmax) || !std::isfinite(d->beta_z))
@@ -669,6 +706,34 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     }
     TRY_HIP(hipMemcpy(j->ws + L.edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
     TRY_HIP(hipMemcpy(j->ws + L.plane_of, plane_of.data(), sizeof(int32_t) * plane_of.size(), hipMemcpyHostToDevice));
+    // angle tables with the cumulative areas of the piecewise linear densities (trapezoids,
+    // left to right)
+    size_t ang_off = 0;
+    std::vector<size_t> ang_at(d->n_proc, 0);
+    if (angle_doubles(d) > 0) {
+        std::vector<double> tab(angle_doubles(d));
+        for (int i = 0; i < d->n_proc; ++i) {
+            const karl_process_desc& p = d->proc[i];
+            ang_at[i] = ang_off;
+            if (p.ang_bins <= 0) continue;
+            const int nb = p.ang_bins, n = p.ang_nodes;
+            double* e = tab.data() + ang_off;
+            double* th = e + nb + 1;
+            double* cdf = th + n;
+            double* pdf = cdf + (size_t)nb * n;
+            for (int b = 0; b <= nb; ++b) e[b] = p.ang_edges[b];
+            for (int k = 0; k < n; ++k) th[k] = p.ang_theta[k];
+            for (int b = 0; b < nb; ++b) {
+                const double* f = p.ang_pdf + (size_t)b * n;
+                double* c = cdf + (size_t)b * n;
+                c[0] = 0.0;
+                for (int k = 0; k + 1 < n; ++k) c[k + 1] = c[k] + 0.5 * (f[k] + f[k + 1]) * (th[k + 1] - th[k]);
+                for (int k = 0; k < n; ++k) pdf[(size_t)b * n + k] = f[k];
+            }
+            ang_off += angle_block(p);
+        }
+        TRY_HIP(hipMemcpy(j->ws + L.angles, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+    }
 
     // ---- device job
     karl::DevJob& J = j->dj;
@@ -710,6 +775,11 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.defer[s] = 0;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
+        const bool has_ang = i < d->n_proc && d->proc[i].ang_bins > 0;
+        J.ang[i] = has_ang ? (const double*)(j->ws + L.angles) + ang_at[i] : nullptr;
+        J.ang_nb[i] = has_ang ? d->proc[i].ang_bins : 0;
+        J.ang_n[i] = has_ang ? d->proc[i].ang_nodes : 0;
+        J.e_iso[i] = has_ang ? d->proc[i].e_iso : 0.0;
         J.kind[i] = i < d->n_proc ? d->proc[i].kind : 0;
         J.target[i] = i < d->n_proc ? d->proc[i].target : 0;
         J.e_th[i] = i < d->n_proc ? d->proc[i].e_th : 0.0;

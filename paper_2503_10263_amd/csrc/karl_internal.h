@@ -55,6 +55,10 @@ struct DevJob {
     int32_t target[KARL_MAX_PROC];
     double e_th[KARL_MAX_PROC];
     float e_th_f[KARL_MAX_PROC];
+    // elastic angle tables: per process edges [nb+1], theta [n], cdf [nb][n], pdf [nb][n]
+    const double* ang[KARL_MAX_PROC];
+    int32_t ang_nb[KARL_MAX_PROC], ang_n[KARL_MAX_PROC];
+    double e_iso[KARL_MAX_PROC];
     // device tables (Real = double or float according to the precision)
     const void* xs;        // [n_proc][n_e]
     const void* n_gas;     // [n_z]

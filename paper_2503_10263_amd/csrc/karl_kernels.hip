@@ -488,8 +488,42 @@ __device__ __forceinline__ void set_velocity(Part<Real>& p, Real e_from_v2, cons
     }
 }
 
+// Cosine of the centre-of-mass scattering angle (Sec. 3.3 "Elastic scattering"): isotropic
+// without a table or below the composite threshold, else from the piecewise linear density of
+// the impact-energy bin: the interval is the last whose cumulative area is <= u times the
+// total, and inside it f0 x + (s/2) x^2 = r is solved as x = 2 r / (f0 + sqrt(f0^2 + 2 s r)).
+// The table arithmetic is FP64 in both precisions.
 template <typename Real>
-__device__ void k_elastic(const DevJob& J, Part<Real>& p) {
+__device__ Real scatter_mu(const DevJob& J, int pi, Real ecm, Real u) {
+    const int nb = J.ang_nb[pi];
+    if (nb <= 0 || ecm < (Real)J.e_iso[pi]) return (Real)2 * u - (Real)1;
+    const int n = J.ang_n[pi];
+    const double* e = J.ang[pi];
+    const double* th = e + nb + 1;
+    int b = 0;
+    while (b < nb - 1 && (double)ecm >= e[b + 1]) ++b;
+    const double* c = th + n + (size_t)b * n;
+    const double* f = th + n + (size_t)nb * n + (size_t)b * n;
+    const double a = (double)u * c[n - 1];
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (c[mid] <= a) lo = mid;
+        else hi = mid - 1;
+    }
+    const double h = th[lo + 1] - th[lo];
+    const double r = a - c[lo];
+    const double s = (f[lo + 1] - f[lo]) / h;
+    const double den = f[lo] + ksqrt(f[lo] * f[lo] + 2.0 * s * r);
+    double x = (r > 0.0 && den > 0.0) ? 2.0 * r / den : 0.0;
+    if (x > h) x = h;
+    double sn, cs;
+    ksincos(th[lo] + x, &sn, &cs);
+    return (Real)cs;
+}
+
+template <typename Real>
+__device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
     const int s = p.sp;
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     Real V[3];
@@ -508,7 +542,9 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p) {
     const Real gf = (Real)sel2(s, J.gfrac[0], J.gfrac[1]);
     const Real cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
-    const Real mu = (Real)2 * q.d0 - (Real)1;
+    // the impact energy in the centre-of-mass frame selects the angle distribution
+    const Real ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * (Real)sel2(s, J.e_from_v2[0], J.e_from_v2[1]) * gf;
+    const Real mu = scatter_mu(J, pi, ecm, q.d0);
     const Real phi = (Real)kTWO_PI * q.d1;
     Real gn[3];
     rotate(gh[0], gh[1], gh[2], mu, phi, gn);
@@ -996,7 +1032,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         bool killed = false;
         switch (L.kind[pi]) {
             case KARL_ELASTIC:
-                k_elastic(J, p);
+                k_elastic(J, p, pi);
                 break;
             case KARL_EXCITATION: {
                 const Real ex = L.eth[pi];
@@ -1408,7 +1444,7 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 // (one job): the deferred-queue launch, without the birth and ionization code, which leaves
 // the kernel half the registers and twice the waves per SIMD.
 template <typename Real, bool kBatched, bool kCoop = false, bool kDrain = false>
-__global__ __launch_bounds__(kBlock, KARL_WAVES_PER_SIMD) void transport_kernel(
+__global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x;

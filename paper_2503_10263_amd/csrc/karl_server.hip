@@ -49,6 +49,7 @@ constexpr int kFloorWindow = 8;
 struct OwnedDesc {
     karl_job_desc d{};
     std::vector<double> n_gas, n_ion, n_elec, edges[2], xs[KARL_MAX_PROC];
+    std::vector<double> ang_edges[KARL_MAX_PROC], ang_theta[KARL_MAX_PROC], ang_pdf[KARL_MAX_PROC];
     std::vector<int32_t> planes;
 
     void copy_from(const karl_job_desc& s) {
@@ -70,6 +71,15 @@ struct OwnedDesc {
         for (int i = 0; i < s.n_proc; ++i) {
             xs[i].assign(s.proc[i].xs, s.proc[i].xs + s.n_e);
             d.proc[i].xs = xs[i].data();
+            const karl_process_desc& p = s.proc[i];
+            if (p.ang_bins > 0) {
+                ang_edges[i].assign(p.ang_edges, p.ang_edges + p.ang_bins + 1);
+                ang_theta[i].assign(p.ang_theta, p.ang_theta + p.ang_nodes);
+                ang_pdf[i].assign(p.ang_pdf, p.ang_pdf + (size_t)p.ang_bins * p.ang_nodes);
+                d.proc[i].ang_edges = ang_edges[i].data();
+                d.proc[i].ang_theta = ang_theta[i].data();
+                d.proc[i].ang_pdf = ang_pdf[i].data();
+            }
         }
         if (s.n_planes > 0) {
             planes.assign(s.planes, s.planes + s.n_planes);

@@ -60,7 +60,10 @@ class SpeciesDesc(C.Structure):
 
 class ProcessDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
-                ("reserved0", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double))]
+                ("reserved0", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
+                ("ang_bins", C.c_int32), ("ang_nodes", C.c_int32), ("e_iso", C.c_double),
+                ("ang_edges", C.POINTER(C.c_double)), ("ang_theta", C.POINTER(C.c_double)),
+                ("ang_pdf", C.POINTER(C.c_double))]
 
 
 class JobDesc(C.Structure):
@@ -204,6 +207,13 @@ class Descriptor:
             if len(xs) != w.n_e:
                 raise ValueError(f"process {i}: table has {len(xs)} nodes, expected {w.n_e}")
             dp.xs = _dptr(xs)
+            ang = getattr(p, "angular", None)
+            if ang is not None:
+                edges = self._hold(ang.edges, np.float64)
+                theta = self._hold(ang.theta, np.float64)
+                pdf = self._hold(ang.pdf, np.float64)
+                dp.ang_bins, dp.ang_nodes, dp.e_iso = len(edges) - 1, len(theta), ang.e_iso
+                dp.ang_edges, dp.ang_theta, dp.ang_pdf = _dptr(edges), _dptr(theta), _dptr(pdf)
         d.source, d.beam_species = w.source, w.beam_species
         d.beta_e0, d.beta_z, d.beta_fmax = w.beta_e0, w.beta_z, w.beta_fmax
         d.beam_energy = w.beam_energy

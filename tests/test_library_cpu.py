@@ -95,3 +95,17 @@ def test_null_job_is_an_error_not_a_crash(karl):
     lib = karl.lib()
     assert lib.karl_transport(None, 0, 1, None) == karl.ESTATE
     assert lib.karl_destroy_job(None) == karl.EINVAL
+
+
+def test_invalid_angle_tables_are_rejected(karl):
+    w = W.cfg_tiny(n_primaries=10)
+    w.processes[0].angular = W.screened_table()
+    w.processes[0].angular.pdf[2][:] = 0.0                # a bin without area
+    with pytest.raises(karl.KarlError) as ei:
+        karl.Descriptor(w, queue_capacity=1024).workspace_bytes()
+    assert ei.value.code == karl.EINVAL
+    w = W.cfg_tiny(n_primaries=10)
+    w.processes[2].angular = W.screened_table()           # the excitation process
+    with pytest.raises(karl.KarlError) as ei:
+        karl.Descriptor(w, queue_capacity=1024).workspace_bytes()
+    assert ei.value.code == karl.EINVAL
