@@ -44,7 +44,7 @@ class _Species(C.Structure):
     _fields_ = [("mass", C.c_double), ("charge", C.c_double), ("e_cut", C.c_double),
                 ("lifetime", C.c_double), ("cap", C.c_int64), ("tracked", C.c_int32),
                 ("pad", C.c_int32), ("xs_emin", C.c_double), ("xs_emax", C.c_double),
-                ("edges", C.POINTER(C.c_double))]
+                ("edges", C.POINTER(C.c_double)), ("dens_edges", C.POINTER(C.c_double))]
 
 
 class _Process(C.Structure):
@@ -67,7 +67,7 @@ class _Desc(C.Structure):
                 ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
                 ("beam_energy_1", C.c_double), ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
                 ("pad2", C.c_int32), ("planes", C.POINTER(C.c_int32)),
-                ("n_primaries", C.c_int64)]
+                ("n_primaries", C.c_int64), ("n_dens_bins", C.c_int32), ("pad3", C.c_int32)]
 
 
 class _Tallies(C.Structure):
@@ -75,7 +75,7 @@ class _Tallies(C.Structure):
                 ("density_time", C.POINTER(C.c_double)), ("recomb", C.POINTER(C.c_int64)),
                 ("jz", C.POINTER(C.c_int64)), ("jr", C.POINTER(C.c_int64)),
                 ("spectra", C.POINTER(C.c_int64)), ("digests", C.POINTER(C.c_uint64)),
-                ("hist", C.POINTER(C.c_double))]
+                ("hist", C.POINTER(C.c_double)), ("density_time_e", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -166,6 +166,13 @@ class Desc:
             d.sp[s].xs_emin = sp.xs_emin
             d.sp[s].xs_emax = sp.xs_emax
             d.sp[s].edges = _dptr(edges)
+            if getattr(w, "dens_edges", None) is not None:
+                de = np.ascontiguousarray(w.dens_edges[s], dtype=np.float64)
+                if len(de) != len(w.dens_edges[0]):
+                    raise ValueError("both species need the same number of density energy bins")
+                self.keep.append(de)
+                d.sp[s].dens_edges = _dptr(de)
+                d.n_dens_bins = len(de) - 1
         d.n_proc = len(w.processes)
         d.n_e = w.n_e
         for i, p in enumerate(w.processes):
@@ -224,6 +231,9 @@ def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.
         t["digests"] = np.zeros(w.n_primaries, np.uint64)
     if hist:
         t["hist"] = np.zeros((w.n_primaries, NHIST), np.float64)
+    if getattr(w, "dens_edges", None) is not None:
+        nd = len(w.dens_edges[0]) - 1
+        t["density_time_e"] = np.zeros((2, w.n_r, w.n_z, nd + 2), np.float64)
     return t
 
 
@@ -246,6 +256,8 @@ def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, digests: bool = Fa
         T.digests = t["digests"].ctypes.data_as(C.POINTER(C.c_uint64))
     if "hist" in t:
         T.hist = _dptr(t["hist"])
+    if "density_time_e" in t:
+        T.density_time_e = _dptr(t["density_time_e"])
     rc = lib().ko_run(C.byref(D.d), pid_begin, pid_end, C.byref(T))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (rc={rc})")
@@ -261,6 +273,8 @@ def _tallies_struct(t):
     T.jz = t["jz"].ctypes.data_as(C.POINTER(C.c_int64))
     T.jr = t["jr"].ctypes.data_as(C.POINTER(C.c_int64))
     T.spectra = t["spectra"].ctypes.data_as(C.POINTER(C.c_int64))
+    if "density_time_e" in t:
+        T.density_time_e = _dptr(t["density_time_e"])
     return T
 
 

@@ -259,6 +259,7 @@ typedef struct {
     int32_t pidx[2][KO_MAX_PROC];
     /* compensated accumulators */
     double* dens_s; double* dens_c;
+    double* dense_s; double* dense_c;   /* energy-resolved times (or NULL) */
     double led_s[KO_NLEDGER], led_c[KO_NLEDGER];
     /* particle stack */
     seed_t* stack; int64_t n_stack, cap_stack;
@@ -299,6 +300,11 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
     size_t nd = (size_t)2 * d->n_r * d->n_z;
     c->dens_s = (double*)calloc(nd, sizeof(double));
     c->dens_c = (double*)calloc(nd, sizeof(double));
+    if (t && t->density_time_e && d->n_dens_bins > 0) {
+        size_t ne = nd * (size_t)(d->n_dens_bins + 2);
+        c->dense_s = (double*)calloc(ne, sizeof(double));
+        c->dense_c = (double*)calloc(ne, sizeof(double));
+    }
     for (int k = 0; k <= d->n_z; ++k) c->zf[k] = d->length * (double)k / (double)d->n_z;
     for (int k = 0; k <= d->n_r; ++k) c->rf[k] = d->radius * (double)k / (double)d->n_r;
     c->zcdf[0] = 0.0;
@@ -333,6 +339,7 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
 static void ctx_free(ctx_t* c) {
     free(c->zf); free(c->rf); free(c->zcdf); free(c->plane_of);
     free(c->dens_s); free(c->dens_c); free(c->stack);
+    free(c->dense_s); free(c->dense_c);
 }
 
 static void ledger_add(ctx_t* c, int i, double x) { nadd(&c->led_s[i], &c->led_c[i], x); }
@@ -796,6 +803,14 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
         double dt = l / p->vel;
         p->t_cell += dt;
         p->t_alive += dt;
+        if (c->dense_s) {
+            /* energy-resolved density field (Sec. 3.4): the segment's time in the bin of the
+               energy the particle flies with */
+            int eb = find_bin(S->dens_edges, d->n_dens_bins, p->e);
+            size_t k = ((((size_t)p->sp * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz) *
+                        (size_t)(d->n_dens_bins + 2)) + (size_t)eb;
+            nadd(&c->dense_s[k], &c->dense_c[k], dt);
+        }
         if (c->gc) {
             p->z += l * p->w;
             p->s_path += l;
@@ -992,6 +1007,10 @@ int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t) 
     }
     size_t nd = (size_t)2 * d->n_r * d->n_z;
     for (size_t k = 0; k < nd; ++k) t->density_time[k] += c.dens_s[k] + c.dens_c[k];
+    if (c.dense_s) {
+        size_t ne = nd * (size_t)(d->n_dens_bins + 2);
+        for (size_t k = 0; k < ne; ++k) t->density_time_e[k] += c.dense_s[k] + c.dense_c[k];
+    }
     for (int k = 0; k < KO_NLEDGER; ++k) t->ledger[k] += c.led_s[k] + c.led_c[k];
     ctx_free(&c);
     return 0;

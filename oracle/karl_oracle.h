@@ -67,6 +67,7 @@ typedef struct {
     double xs_emin;       /* eV: first table node */
     double xs_emax;       /* eV: last table node */
     const double* edges;  /* [n_bins+1] spectrum bin edges (eV), increasing */
+    const double* dens_edges;  /* [n_dens_bins+1] energy bins of the density field (eV) or NULL */
 } ko_species;
 
 typedef struct {
@@ -108,6 +109,8 @@ typedef struct {
     int32_t n_planes, pad2;
     const int32_t* planes;       /* [n_planes] z-face indices */
     int64_t n_primaries;
+    int32_t n_dens_bins;         /* energy bins of the density field (Sec. 3.4); 0: none */
+    int32_t pad3;
 } ko_desc;
 
 typedef struct {
@@ -120,6 +123,9 @@ typedef struct {
     int64_t* spectra;      /* [2][n_planes][2][n_bins+2] */
     uint64_t* digests;     /* [n_primaries] or NULL */
     double* hist;          /* [n_primaries][KO_NHIST] or NULL */
+    /* [2][n_r][n_z][n_dens_bins+2] time per segment and energy bin (bin 0 below the first
+       edge, n_dens_bins+1 at or above the last), or NULL */
+    double* density_time_e;
 } ko_tallies;
 
 /* Transport primaries pid_begin..pid_end-1 and add their contributions to t. */

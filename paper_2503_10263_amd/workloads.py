@@ -138,6 +138,7 @@ class Workload:
     planes: List[int] = field(default_factory=list)   # z-face indices
     n_primaries: int = 0
     n_elec: Optional[np.ndarray] = None   # [n_r*n_z] m^-3 electron field (target of ions)
+    dens_edges: Optional[tuple] = None    # (electron, ion) energy-bin edges of the density field
     beam_energy_1: float = 0.0            # eV: ion energy of SOURCE_PAIR
 
     @property
