@@ -109,6 +109,8 @@ typedef struct {
     double xs_emin;         /* eV; energy of the first cross-section node */
     double xs_emax;         /* eV; energy of the last node; nodes are log-spaced */
     const double* edges;    /* [n_bins+1] increasing spectrum bin edges (eV) */
+    const double* dens_edges;  /* [n_dens_bins+1] increasing energy-bin edges of the
+                                  energy-resolved density field (eV); NULL without it */
 } karl_species_desc;
 
 typedef struct {
@@ -162,6 +164,8 @@ typedef struct {
     void* workspace;              /* device memory, >= karl_workspace_bytes() */
     uint64_t workspace_bytes;
     int32_t mapping;              /* KARL_MAP_AUTO, KARL_MAP_LANE or KARL_MAP_WAVE */
+    int32_t n_dens_bins;          /* energy bins of the energy-resolved density field (Sec. 3.4:
+                                     times per segment with an energy axis), 0..4096; 0: none */
 } karl_job_desc;
 
 /* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements:
@@ -180,6 +184,9 @@ typedef struct {
     int64_t* spectra;       /* [species][plane][dir][bin] with under/overflow bins 0, n_bins+1 */
     uint64_t* digests;
     double* hist;
+    double* density_time_e; /* [species][r][z][n_dens_bins+2] seconds per energy bin: each
+                               flight segment's time in the bin of the particle's energy (bin 0
+                               below the first edge, n_dens_bins+1 at or above the last) */
 } karl_tallies;
 
 /* Device bytes a job needs (tables, tallies and their snapshot, two secondary queues). */

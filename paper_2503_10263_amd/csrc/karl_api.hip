@@ -47,9 +47,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte offsets of every region of a job's workspace.
 struct Layout {
-    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of, angles;
+    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of, angles, dens_edges;
     size_t tallies, tally_bytes;
-    size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist;
+    size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist, t_dense;
     size_t snapshot, control, fields, queues, queue_entries;
     size_t total;
 };
@@ -96,6 +96,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.edges = take(8 * 2 * ((size_t)d->n_bins + 1));
     L.plane_of = take(4 * (nz + 1));
     L.angles = take(8 * angle_doubles(d));
+    L.dens_edges = take(d->n_dens_bins > 0 ? 8 * 2 * ((size_t)d->n_dens_bins + 1) : 0);
     // tallies: one contiguous block so that a snapshot is one copy
     size_t t = 0;
     auto tk = [&](size_t bytes) {
@@ -113,6 +114,7 @@ Layout make_layout(const karl_job_desc* d) {
     L.t_spectra = tk(8 * 2 * (size_t)d->n_planes * 2 * ((size_t)d->n_bins + 2));
     L.t_digests = tk((d->flags & KARL_FLAG_DIGESTS) ? 8 * np : 0);
     L.t_hist = tk((d->flags & KARL_FLAG_HISTORY) ? 8 * KARL_NHIST * np : 0);
+    L.t_dense = tk(d->n_dens_bins > 0 ? 8 * 2 * nr * nz * ((size_t)d->n_dens_bins + 2) : 0);
     L.tally_bytes = t;
     L.tallies = take(t);
     L.snapshot = take(t);
@@ -224,6 +226,15 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     } else {
         return fail(KARL_EINVAL, "unknown source %d", d->source);
     }
+    if (d->n_dens_bins < 0 || d->n_dens_bins > 4096)
+        return fail(KARL_EINVAL, "n_dens_bins must be in 0..4096");
+    if (d->n_dens_bins > 0)
+        for (int s = 0; s < 2; ++s) {
+            const double* e = d->species[s].dens_edges;
+            if (!e) return fail(KARL_EINVAL, "species %d: density energy edges missing", s);
+            for (int b = 0; b < d->n_dens_bins; ++b)
+                if (!(e[b] < e[b + 1])) return fail(KARL_EINVAL, "species %d: density energy edges must increase", s);
+        }
     if (d->n_primaries < 0 || d->n_primaries > (int64_t)0xFFFFFFFFLL)
         return fail(KARL_EINVAL, "n_primaries must be in 0..2^32-1");
     if (d->precision != KARL_FP64 && d->precision != KARL_FP32)
@@ -281,6 +292,7 @@ struct Launcher {
     int max_blocks_coop = 0;                // single-job launches with wave-cooperative flights
     int max_blocks_drain = 0;               // single-job deferred-queue launches
     bool coop = false;                      // launch the wave-cooperative kernel
+    bool dense = false;                     // the job has an energy-resolved density tally
     unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
@@ -415,7 +427,7 @@ struct Launcher {
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > cap_blocks) blocks = cap_blocks;
             HIP_CHECK(hipEventRecord(ev0, s));
-            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, g, precision,
+            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, dense, g, precision,
                                              (int)blocks, kBlock, lds, s));
             HIP_CHECK(hipEventRecord(ev1, s));
             HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
@@ -706,6 +718,13 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     }
     TRY_HIP(hipMemcpy(j->ws + L.edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
     TRY_HIP(hipMemcpy(j->ws + L.plane_of, plane_of.data(), sizeof(int32_t) * plane_of.size(), hipMemcpyHostToDevice));
+    if (d->n_dens_bins > 0) {
+        std::vector<double> de(2 * ((size_t)d->n_dens_bins + 1));
+        for (int s = 0; s < 2; ++s)
+            std::memcpy(&de[(size_t)s * (d->n_dens_bins + 1)], d->species[s].dens_edges,
+                        sizeof(double) * ((size_t)d->n_dens_bins + 1));
+        TRY_HIP(hipMemcpy(j->ws + L.dens_edges, de.data(), sizeof(double) * de.size(), hipMemcpyHostToDevice));
+    }
     // angle tables with the cumulative areas of the piecewise linear densities (trapezoids,
     // left to right)
     size_t ang_off = 0;
@@ -831,6 +850,9 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.spectra = (unsigned long long*)(t + L.t_spectra);
     J.digests = (d->flags & KARL_FLAG_DIGESTS) ? (unsigned long long*)(t + L.t_digests) : nullptr;
     J.hist = (d->flags & KARL_FLAG_HISTORY) ? (double*)(t + L.t_hist) : nullptr;
+    J.n_dens_bins = d->n_dens_bins;
+    J.dens_edges = d->n_dens_bins > 0 ? (const double*)(w + L.dens_edges) : nullptr;
+    J.dense = d->n_dens_bins > 0 ? (double*)(t + L.t_dense) : nullptr;
     unsigned long long* ctl = (unsigned long long*)(w + L.control);
     j->status = (unsigned int*)(ctl + 5);     // the job's own sticky status (NaN met)
     J.status = j->status;
@@ -842,6 +864,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     TRY_HIP(hipMemcpy(w + L.devjob, &J, sizeof(J), hipMemcpyHostToDevice));
     j->lds = lds;
     j->run.ctl = ctl;
+    j->run.dense = d->n_dens_bins > 0;
     j->run.jobs_dev = (karl::DevJob*)(w + L.devjob);
     TRY_HIP(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
     TRY_HIP(karl::launch_fill_u64((unsigned long long*)t, L.tally_bytes / 8, 0ull, nullptr));
@@ -890,6 +913,11 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     if (out->digests) {
         if (!J.digests) return fail(KARL_EINVAL, "digests requested but KARL_FLAG_DIGESTS not set");
         if ((st = get(out->digests, J.digests, 8 * (size_t)j->n_primaries)) != KARL_OK) return st;
+    }
+    if (out->density_time_e) {
+        if (!J.dense) return fail(KARL_EINVAL, "energy-resolved density requested but n_dens_bins is 0");
+        if ((st = get(out->density_time_e, J.dense, 8 * 2 * nr * nz * ((size_t)J.n_dens_bins + 2))) != KARL_OK)
+            return st;
     }
     if (out->hist) {
         if (!J.hist) return fail(KARL_EINVAL, "history ledger requested but KARL_FLAG_HISTORY not set");

@@ -68,6 +68,8 @@ struct DevJob {
     double* field[2];      // [n_r*n_z] density field of each species (m^-3), or NULL
     const double* edges;   // [2][n_bins+1]
     const int32_t* plane_of;   // [n_z+1] plane index or -1
+    const double* dens_edges;  // [2][n_dens_bins+1] or NULL
+    int32_t n_dens_bins, reserved1;
     // tallies
     unsigned long long* counters;
     double* ledger;
@@ -78,6 +80,7 @@ struct DevJob {
     unsigned long long* spectra;
     unsigned long long* digests;
     double* hist;
+    double* dense;         // [2][n_r][n_z][n_dens_bins+2] or NULL
     unsigned int* status;
 };
 
@@ -115,7 +118,7 @@ struct GenArgs {
 enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 
 size_t lds_bytes(const DevJob& j, int precision);
-hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain,
+hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain, bool dense,
                             const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s);
 hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s);

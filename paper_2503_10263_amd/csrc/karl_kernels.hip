@@ -870,6 +870,28 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     }
 }
 
+// energy-resolved density field (Sec. 3.4): a flight segment's time in the bin of the energy
+// the particle flies with (bin 0 below the first edge, n_dens_bins+1 at or above the last)
+__device__ __forceinline__ void add_dense(const DevJob& J, int sp, int ir, int iz, double e, double dt) {
+    const int nb = J.n_dens_bins;
+    const double* ed = J.dens_edges + (size_t)sp * (nb + 1);
+    int bin;
+    if (e < ed[0]) {
+        bin = 0;
+    } else if (!(e < ed[nb])) {
+        bin = nb + 1;
+    } else {
+        int lo = 0, hi = nb;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ed[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        bin = lo + 1;
+    }
+    add_f64(&J.dense[(((size_t)sp * J.n_r + (size_t)ir) * J.n_z + (size_t)iz) * (size_t)(nb + 2) + (size_t)bin], dt);
+}
+
 // energy bin of a plane spectrum: 0 below the first edge, n_bins+1 at or above the last
 __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) {
     const double* ed = J.edges + (size_t)sp * (J.n_bins + 1);
@@ -887,7 +909,8 @@ __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) 
 // ---------------------------------------------------------------- one flight segment
 // kDrain: the launch that runs the deferred queue, whose species have no ionization process
 // (the job setup defers exactly those); the ionization branch is left out of that kernel.
-template <typename Real, bool kDrain = false>
+// kDrain == 1 also leaves out the energy-resolved density tally (jobs without it), 2 keeps it.
+template <typename Real, int kDrain = 0>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
@@ -981,6 +1004,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     const Real dt = l / p.vel;
     p.t_cell += (double)dt;
     p.t_alive += (double)dt;
+    if (kDrain != 1 && J.dense) add_dense(J, sp, p.ir, p.iz, (double)p.e, (double)dt);
     if (J.gc) {
         p.z += l * p.w;
         p.s_path += l;
@@ -1222,6 +1246,7 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
         if (dist != dist || sum != sum) atomicOr(J.status, STATUS_NUMERIC);
         const double tc = (k == 0) ? bc_r(p.t_cell, j) + (double)dt : (double)dt;
         if (tc != 0.0) add_f64(&J.dens[((size_t)sp * J.n_r + (size_t)ir) * J.n_z + (size_t)izk], tc);
+        if (J.dense) add_dense(J, sp, ir, izk, (double)e, (double)dt);
         add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)ir) * (J.n_z + 1) + (size_t)fz) * 2 + (size_t)dir], 1ull);
         const int pl = J.plane_of[fz];
         if (pl >= 0)
@@ -1415,7 +1440,7 @@ __device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool nee
 }
 
 // One unit of work for a lane: start its fetched particle, or move it by one flight segment.
-template <typename Real, bool kDrain = false>
+template <typename Real, int kDrain = 0>
 __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, const GenArgs& G,
                                         Part<Real>& p, LaneCnt& lc) {
     if (p.start) {
@@ -1442,8 +1467,9 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 // read with scalar loads.  kCoop (one job, guiding-centre mode): before each step, the flights
 // of particles that just crossed a face are advanced by the whole wave (coop_flight).  kDrain
 // (one job): the deferred-queue launch, without the birth and ionization code, which leaves
-// the kernel half the registers and twice the waves per SIMD.
-template <typename Real, bool kBatched, bool kCoop = false, bool kDrain = false>
+// the kernel half the registers and twice the waves per SIMD (1: without, 2: with the
+// energy-resolved density tally).
+template <typename Real, bool kBatched, bool kCoop = false, int kDrain = 0>
 __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1687,14 +1713,21 @@ size_t lds_bytes(const DevJob& j, int precision) {
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain,
+hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain, bool dense,
                             const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s) {
     if (drain && !batched) {
-        if (precision == KARL_FP32)
-            hipLaunchKernelGGL((transport_kernel<float, false, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        else
-            hipLaunchKernelGGL((transport_kernel<double, false, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        if (precision == KARL_FP32) {
+            if (dense)
+                hipLaunchKernelGGL((transport_kernel<float, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+            else
+                hipLaunchKernelGGL((transport_kernel<float, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        } else {
+            if (dense)
+                hipLaunchKernelGGL((transport_kernel<double, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+            else
+                hipLaunchKernelGGL((transport_kernel<double, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        }
         return hipGetLastError();
     }
     if (precision == KARL_FP32) {
@@ -1763,8 +1796,8 @@ hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drai
                                size_t lds, int* blocks_per_cu) {
     if (drain && !batched) {
         if (precision == KARL_FP32)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, true>, block, lds);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, true>, block, lds);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 1>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 1>, block, lds);
     }
     if (precision == KARL_FP32) {
         if (batched)

@@ -48,7 +48,7 @@ constexpr int kFloorWindow = 8;
 // A job descriptor together with copies of every host array it points to.
 struct OwnedDesc {
     karl_job_desc d{};
-    std::vector<double> n_gas, n_ion, n_elec, edges[2], xs[KARL_MAX_PROC];
+    std::vector<double> n_gas, n_ion, n_elec, edges[2], dens_edges[2], xs[KARL_MAX_PROC];
     std::vector<double> ang_edges[KARL_MAX_PROC], ang_theta[KARL_MAX_PROC], ang_pdf[KARL_MAX_PROC];
     std::vector<int32_t> planes;
 
@@ -67,6 +67,10 @@ struct OwnedDesc {
         for (int k = 0; k < 2; ++k) {
             edges[k].assign(s.species[k].edges, s.species[k].edges + s.n_bins + 1);
             d.species[k].edges = edges[k].data();
+            if (s.n_dens_bins > 0 && s.species[k].dens_edges) {
+                dens_edges[k].assign(s.species[k].dens_edges, s.species[k].dens_edges + s.n_dens_bins + 1);
+                d.species[k].dens_edges = dens_edges[k].data();
+            }
         }
         for (int i = 0; i < s.n_proc; ++i) {
             xs[i].assign(s.proc[i].xs, s.proc[i].xs + s.n_e);

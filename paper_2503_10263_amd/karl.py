@@ -55,7 +55,7 @@ class SpeciesDesc(C.Structure):
     _fields_ = [("mass", C.c_double), ("charge", C.c_double), ("e_cut", C.c_double),
                 ("lifetime", C.c_double), ("cap", C.c_int64), ("tracked", C.c_int32),
                 ("reserved0", C.c_int32), ("xs_emin", C.c_double), ("xs_emax", C.c_double),
-                ("edges", C.POINTER(C.c_double))]
+                ("edges", C.POINTER(C.c_double)), ("dens_edges", C.POINTER(C.c_double))]
 
 
 class ProcessDesc(C.Structure):
@@ -82,7 +82,7 @@ class JobDesc(C.Structure):
                 ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
                 ("queue_capacity", C.c_int64), ("chunk", C.c_int64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
-                ("mapping", C.c_int32)]
+                ("mapping", C.c_int32), ("n_dens_bins", C.c_int32)]
 
 
 class ServerDesc(C.Structure):
@@ -104,7 +104,7 @@ class Tallies(C.Structure):
                 ("density_time", C.POINTER(C.c_double)), ("recomb", C.POINTER(C.c_int64)),
                 ("jz", C.POINTER(C.c_int64)), ("jr", C.POINTER(C.c_int64)),
                 ("spectra", C.POINTER(C.c_int64)), ("digests", C.POINTER(C.c_uint64)),
-                ("hist", C.POINTER(C.c_double))]
+                ("hist", C.POINTER(C.c_double)), ("density_time_e", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -198,6 +198,12 @@ class Descriptor:
             if len(edges) != nb + 1:
                 raise ValueError("both species need the same number of spectrum bins")
             ds.edges = _dptr(edges)
+            if getattr(w, "dens_edges", None) is not None:
+                de = self._hold(w.dens_edges[s], np.float64)
+                if len(de) != len(w.dens_edges[0]):
+                    raise ValueError("both species need the same number of density energy bins")
+                ds.dens_edges = _dptr(de)
+                d.n_dens_bins = len(de) - 1
         d.n_proc = len(w.processes)
         d.n_e = w.n_e
         for i, p in enumerate(w.processes):
@@ -253,6 +259,8 @@ def tally_shapes(w, digests: bool, history: bool) -> Dict[str, tuple]:
         "jz": ((2, w.n_r, w.n_z + 1, 2), np.int64), "jr": ((2, w.n_r + 1, w.n_z, 2), np.int64),
         "spectra": ((2, len(w.planes), 2, nb + 2), np.int64),
     }
+    if getattr(w, "dens_edges", None) is not None:
+        s["density_time_e"] = ((2, w.n_r, w.n_z, len(w.dens_edges[0]) + 1), np.float64)
     if digests:
         s["digests"] = ((w.n_primaries,), np.uint64)
     if history:
