@@ -19,16 +19,17 @@ LIB_PATH = os.path.join(HERE, "liboracle_karl.so")
 SRC = os.path.join(HERE, "karl_oracle.c")
 
 MAX_PROC = 16
-NCOUNTERS = 48
-NLEDGER = 24
+MAX_SPECIES = 4
+NCOUNTERS = 80
+NLEDGER = 48
 NHIST = 4
-NREASON = 8
+NREASON = 9
 
 # counter / ledger offsets (mirror of karl_oracle.h)
-C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 2, 4, 6, 8
-C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES = 10, 11, 12
-C_PROC, C_DEATH = 16, 32
-L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 17, 18, 19, 20
+C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 4, 8, 12, 16
+C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES = 20, 21, 22
+C_PROC, C_DEATH = 24, 40
+L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 37, 38, 39, 40
 
 
 def build(force: bool = True) -> str:
@@ -49,7 +50,8 @@ class _Species(C.Structure):
 
 class _Process(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
-                ("pad", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
+                ("product", C.c_int32), ("partner", C.c_int32), ("density_power", C.c_int32),
+                ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
                 ("ang_bins", C.c_int32), ("ang_nodes", C.c_int32), ("e_iso", C.c_double),
                 ("ang_edges", C.POINTER(C.c_double)), ("ang_theta", C.POINTER(C.c_double)),
                 ("ang_pdf", C.POINTER(C.c_double))]
@@ -58,9 +60,10 @@ class _Process(C.Structure):
 class _Desc(C.Structure):
     _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
                 ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
-                ("n_ion", C.POINTER(C.c_double)), ("n_elec", C.POINTER(C.c_double)),
+                ("n_field", C.POINTER(C.c_double) * MAX_SPECIES),
                 ("t_gas", C.c_double), ("m_gas", C.c_double),
-                ("bz", C.c_double), ("sp", _Species * 2), ("n_proc", C.c_int32),
+                ("bz", C.c_double), ("sp", _Species * MAX_SPECIES), ("n_species", C.c_int32),
+                ("n_proc", C.c_int32),
                 ("n_e", C.c_int32), ("proc", _Process * MAX_PROC), ("source", C.c_int32),
                 ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
                 ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
@@ -140,19 +143,21 @@ class Desc:
         n_gas = np.ascontiguousarray(w.n_gas, dtype=np.float64)
         self.keep.append(n_gas)
         d.n_gas = _dptr(n_gas)
-        if w.n_ion is not None:
-            n_ion = np.ascontiguousarray(w.n_ion, dtype=np.float64)
-            self.keep.append(n_ion)
-            d.n_ion = _dptr(n_ion)
-        if getattr(w, "n_elec", None) is not None:
-            n_elec = np.ascontiguousarray(w.n_elec, dtype=np.float64)
-            self.keep.append(n_elec)
-            d.n_elec = _dptr(n_elec)
+        # density fields: slot 0 electrons (n_elec), slot 1 ions (n_ion), further slots from
+        # the workload's extra_fields mapping
+        flds = {0: getattr(w, "n_elec", None), 1: w.n_ion}
+        flds.update(getattr(w, "extra_fields", None) or {})
+        for s, f in flds.items():
+            if f is not None:
+                a = np.ascontiguousarray(f, dtype=np.float64)
+                self.keep.append(a)
+                d.n_field[s] = _dptr(a)
         d.t_gas = w.t_gas
         d.m_gas = w.m_gas
         d.bz = w.bz
         nb = len(w.species[0].edges) - 1
-        for s in range(2):
+        d.n_species = len(w.species)
+        for s in range(len(w.species)):
             sp = w.species[s]
             edges = np.ascontiguousarray(sp.edges, dtype=np.float64)
             assert len(edges) == nb + 1, "both species need the same number of bins"
@@ -169,7 +174,7 @@ class Desc:
             if getattr(w, "dens_edges", None) is not None:
                 de = np.ascontiguousarray(w.dens_edges[s], dtype=np.float64)
                 if len(de) != len(w.dens_edges[0]):
-                    raise ValueError("both species need the same number of density energy bins")
+                    raise ValueError("every species needs the same number of density energy bins")
                 self.keep.append(de)
                 d.sp[s].dens_edges = _dptr(de)
                 d.n_dens_bins = len(de) - 1
@@ -182,6 +187,10 @@ class Desc:
             d.proc[i].kind = p.kind
             d.proc[i].species = p.species
             d.proc[i].target = p.target
+            d.proc[i].product = getattr(p, "product", 1)
+            partner = getattr(p, "partner", None)
+            d.proc[i].partner = (1 - p.species) if partner is None else partner
+            d.proc[i].density_power = getattr(p, "density_power", 1)
             d.proc[i].e_th = p.e_th
             d.proc[i].xs = _dptr(xs)
             ang = getattr(p, "angular", None)
@@ -218,14 +227,15 @@ class Desc:
 
 def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.ndarray]:
     nb = len(w.species[0].edges) - 1
+    ns = len(w.species)
     t = {
         "counters": np.zeros(NCOUNTERS, np.int64),
         "ledger": np.zeros(NLEDGER, np.float64),
-        "density_time": np.zeros((2, w.n_r, w.n_z), np.float64),
-        "recomb": np.zeros((2, w.n_r, w.n_z), np.int64),
-        "jz": np.zeros((2, w.n_r, w.n_z + 1, 2), np.int64),
-        "jr": np.zeros((2, w.n_r + 1, w.n_z, 2), np.int64),
-        "spectra": np.zeros((2, len(w.planes), 2, nb + 2), np.int64),
+        "density_time": np.zeros((ns, w.n_r, w.n_z), np.float64),
+        "recomb": np.zeros((ns, w.n_r, w.n_z), np.int64),
+        "jz": np.zeros((ns, w.n_r, w.n_z + 1, 2), np.int64),
+        "jr": np.zeros((ns, w.n_r + 1, w.n_z, 2), np.int64),
+        "spectra": np.zeros((ns, len(w.planes), 2, nb + 2), np.int64),
     }
     if digests:
         t["digests"] = np.zeros(w.n_primaries, np.uint64)
@@ -233,7 +243,7 @@ def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.
         t["hist"] = np.zeros((w.n_primaries, NHIST), np.float64)
     if getattr(w, "dens_edges", None) is not None:
         nd = len(w.dens_edges[0]) - 1
-        t["density_time_e"] = np.zeros((2, w.n_r, w.n_z, nd + 2), np.float64)
+        t["density_time_e"] = np.zeros((ns, w.n_r, w.n_z, nd + 2), np.float64)
     return t
 
 
@@ -281,9 +291,10 @@ def _tallies_struct(t):
 def fields(w, t, n_prim: float, activity: float):
     """Normalised densities and currents from oracle tallies `t` (eqs. 3-5)."""
     D = Desc(w)
-    dens = np.zeros((2, w.n_r, w.n_z))
-    jz = np.zeros((2, w.n_r, w.n_z + 1))
-    jr = np.zeros((2, w.n_r + 1, w.n_z))
+    ns = len(w.species)
+    dens = np.zeros((ns, w.n_r, w.n_z))
+    jz = np.zeros((ns, w.n_r, w.n_z + 1))
+    jr = np.zeros((ns, w.n_r + 1, w.n_z))
     T = _tallies_struct(t)
     rc = lib().ko_fields(C.byref(D.d), C.byref(T), n_prim, activity, _dptr(dens), _dptr(jz), _dptr(jr))
     if rc != 0:

@@ -21,8 +21,13 @@
  *   - interactions (Sec. 3.3): elastic scattering with a thermal target and a CM-frame
  *     rotation; excitation E' = E - E_x without deflection; ionization with target
  *     redraw, secondary energy from the Kim-Rudd BEB distribution, E_e = E_i - E_ion -
- *     E_i^new, phi_e = phi_i - pi, ion given the target velocity; recombination logs one
- *     deletion in the target field and removes the particle.
+ *     E_i^new, phi_e = phi_i - pi, ion (of the process's product species: the molecular
+ *     ion, or the atomic ion of dissociative ionization) given the target velocity;
+ *     recombination logs one deletion in the partner's field and removes the particle;
+ *     charge exchange gives the projectile the velocity of a target particle; clustering
+ *     replaces the projectile by a particle of the product species that moves along the
+ *     target particle's velocity with that particle's momentum.  Three-body clustering
+ *     goes with the square of the gas density.
  *   - current collection N+ / N- through faces (Sec. 2.3), spectra at planes.
  *   - injector with the allowed beta spectrum drawn by rejection (Sec. 3.5; Sec. 3.8 "Velocity distribution").
  */
@@ -245,18 +250,20 @@ typedef struct {
     double* rf;          /* [n_r+1] r faces */
     double* zcdf;        /* [n_z+1] cumulative gas weights */
     int32_t* plane_of;   /* [n_z+1] plane index or -1 */
-    double inv_dlog[2];
-    double omega[2];     /* q B / m */
+    int n_species;
+    double inv_dlog[KO_MAX_SPECIES];
+    double omega[KO_MAX_SPECIES];     /* q B / m */
     /* per-species constants of the kinematics, evaluated once */
-    double mfrac[2];     /* m / (m + M) */
-    double gfrac[2];     /* M / (m + M): also E_xs / E (centre-of-mass energy factor) */
-    double inv_emin[2];  /* 1 / first table energy */
-    double inv_om[2];    /* 1 / omega (0 without field) */
-    double e_from_v2[2]; /* E(eV) = v^2 * e_from_v2 = v^2 m / (2 e) */
-    double v2_from_e[2]; /* v^2 = E(eV) * v2_from_e = E 2 e / m */
+    double mfrac[KO_MAX_SPECIES];     /* m / (m + M) */
+    double gfrac[KO_MAX_SPECIES];     /* M / (m + M): also E_xs / E (centre-of-mass energy factor) */
+    double inv_emin[KO_MAX_SPECIES];  /* 1 / first table energy */
+    double inv_om[KO_MAX_SPECIES];    /* 1 / omega (0 without field) */
+    double e_from_v2[KO_MAX_SPECIES]; /* E(eV) = v^2 * e_from_v2 = v^2 m / (2 e) */
+    double v2_from_e[KO_MAX_SPECIES]; /* v^2 = E(eV) * v2_from_e = E 2 e / m */
     double sigma_v;      /* thermal target speed scale sqrt(kT/M) */
-    int32_t nps[2];
-    int32_t pidx[2][KO_MAX_PROC];
+    double conv[KO_MAX_PROC];         /* clustering: M / m_product (momentum of the target) */
+    int32_t nps[KO_MAX_SPECIES];
+    int32_t pidx[KO_MAX_SPECIES][KO_MAX_PROC];
     /* compensated accumulators */
     double* dens_s; double* dens_c;
     double* dense_s; double* dense_c;   /* energy-resolved times (or NULL) */
@@ -293,11 +300,13 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
     if (d->n_r < 1 || d->n_z < 1 || d->n_e < 2 || d->n_proc < 0 || d->n_proc > KO_MAX_PROC)
         return -1;
     if (!(d->radius > 0.0) || !(d->length > 0.0) || d->n_bins < 1) return -1;
+    c->n_species = d->n_species ? d->n_species : 2;
+    if (c->n_species < 2 || c->n_species > KO_MAX_SPECIES) return -1;
     c->zf = (double*)malloc(sizeof(double) * (size_t)(d->n_z + 1));
     c->rf = (double*)malloc(sizeof(double) * (size_t)(d->n_r + 1));
     c->zcdf = (double*)malloc(sizeof(double) * (size_t)(d->n_z + 1));
     c->plane_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(d->n_z + 1));
-    size_t nd = (size_t)2 * d->n_r * d->n_z;
+    size_t nd = (size_t)c->n_species * d->n_r * d->n_z;
     c->dens_s = (double*)calloc(nd, sizeof(double));
     c->dens_c = (double*)calloc(nd, sizeof(double));
     if (t && t->density_time_e && d->n_dens_bins > 0) {
@@ -315,7 +324,7 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
         if (f < 0 || f > d->n_z) return -1;
         if (c->plane_of[f] < 0) c->plane_of[f] = p;
     }
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < c->n_species; ++s) {
         c->inv_dlog[s] = (double)(d->n_e - 1) / log(d->sp[s].xs_emax / d->sp[s].xs_emin);
         c->omega[s] = d->sp[s].charge * d->bz / d->sp[s].mass;
         double mt = d->sp[s].mass + d->m_gas;
@@ -328,10 +337,23 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
     }
     c->sigma_v = sqrt(KB * d->t_gas / d->m_gas);
     for (int i = 0; i < d->n_proc; ++i) {
-        int s = d->proc[i].species;
-        if (s < 0 || s > 1) return -1;
+        const ko_process* pr = &d->proc[i];
+        int s = pr->species;
+        if (s < 0 || s >= c->n_species) return -1;
+        if (pr->kind < KO_ELASTIC || pr->kind > KO_CLUSTERING) return -1;
+        if (pr->kind == KO_IONIZATION && (pr->product < 1 || pr->product >= c->n_species)) return -1;
+        if (pr->kind == KO_CLUSTERING &&
+            (pr->product < 0 || pr->product >= c->n_species || pr->product == s)) return -1;
+        if (pr->target == KO_TARGET_FIELD && (pr->partner < 0 || pr->partner >= c->n_species))
+            return -1;
+        if (pr->target != KO_TARGET_GAS && pr->target != KO_TARGET_FIELD) return -1;
+        if (pr->density_power < 0 || pr->density_power > 2) return -1;
+        if (pr->density_power == 2 && pr->target != KO_TARGET_GAS) return -1;
+        if (pr->kind == KO_CLUSTERING) c->conv[i] = d->m_gas / d->sp[pr->product].mass;
         c->pidx[s][c->nps[s]++] = i;
     }
+    if (d->source == KO_SOURCE_BEAM && (d->beam_species < 0 || d->beam_species >= c->n_species))
+        return -1;
     c->gc = (d->bz != 0.0);
     return 0;
 }
@@ -682,7 +704,8 @@ static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, prod
     double vf[3] = {V[0] + sf * df[0], V[1] + sf * df[1], V[2] + sf * df[2]};
     double vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
     double es = (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) * ef2;
-    double eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * c->e_from_v2[1];
+    const int qi = d->proc[pi].product;   /* the ion species made */
+    double eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * c->e_from_v2[qi];
     double e0 = p->e;
     set_velocity(p, ef2, vf);
     out->gas = e0 - (p->e + es + eion + B);
@@ -701,8 +724,38 @@ static void k_ionization(ctx_t* c, part_t* p, int pi, double xc, double yc, prod
     double Vm = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
     if (Vm > 0.0) { double iv = 1.0 / Vm; si->u = V[0] * iv; si->v = V[1] * iv; si->w = V[2] * iv; }
     else { si->u = 0.0; si->v = 0.0; si->w = 1.0; }
-    si->e = eion; si->sp = 1; si->ir = p->ir; si->iz = p->iz;
+    si->e = eion; si->sp = qi; si->ir = p->ir; si->iz = p->iz;
     si->lineage = child_lineage(p->lineage, p->s, 1);
+}
+
+/* Clustering (Sec. 3.3 "Clustering"): a target particle's velocity is drawn as for elastic
+   scattering; the product moves along it with the target particle's momentum, |v'| = (M/m')|V|.
+   The product is a new particle at the collision point; its energy comes from the gas. */
+static void k_clustering(ctx_t* c, part_t* p, int pi, double xc, double yc, seed_t* out,
+                         double* gas) {
+    const int q = c->d->proc[pi].product;
+    double V[3];
+    thermal(c, p, 2, 3, V);
+    const double sc = c->conv[pi];
+    double vn[3] = {sc * V[0], sc * V[1], sc * V[2]};
+    double vm = sqrt(vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
+    out->x = xc; out->y = yc; out->z = p->z;
+    if (vm > 0.0) { double iv = 1.0 / vm; out->u = vn[0] * iv; out->v = vn[1] * iv; out->w = vn[2] * iv; }
+    else { out->u = 0.0; out->v = 0.0; out->w = 1.0; }
+    out->e = (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]) * c->e_from_v2[q];
+    out->sp = q; out->ir = p->ir; out->iz = p->iz;
+    out->lineage = child_lineage(p->lineage, p->s, 0);
+    *gas = -out->e;
+}
+
+/* Charge exchange (Sec. 3.3 "Charge exchange"): the projectile continues with the velocity of a
+   target particle, drawn as for elastic scattering. */
+static void k_charge_exchange(ctx_t* c, part_t* p, double* gas) {
+    double V[3];
+    thermal(c, p, 2, 3, V);
+    double e0 = p->e;
+    set_velocity(p, c->e_from_v2[p->sp], V);
+    *gas = e0 - p->e;
 }
 
 /* ------------------------------------------------------------------ */
@@ -745,15 +798,16 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
         double sum = 0.0;
         for (int j = 0; j < np; ++j) {
             const ko_process* pr = &d->proc[pidx[j]];
-            double nt;
             if (pr->target == KO_TARGET_GAS) {
-                nt = d->n_gas[p->iz];
+                double n = d->n_gas[p->iz];
+                /* three-body clustering: rate k n^2, written as n (n sigma) with sigma = k/v */
+                rate[j] = (pr->density_power == 2) ? n * (n * p->sig[j]) : n * p->sig[j];
             } else {
-                /* the density field of the other species (Sec. 2.2) */
-                const double* f = (p->sp == 0) ? d->n_ion : d->n_elec;
-                nt = f ? f[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
+                /* the density field of the partner species (Sec. 2.2) */
+                const double* f = d->n_field[pr->partner];
+                double nt = f ? f[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
+                rate[j] = nt * p->sig[j];
             }
-            rate[j] = nt * p->sig[j];
             sum += rate[j];
         }
         pair_t q0 = draw(d->seed, p->pid, p->lineage, p->s, 0);
@@ -866,9 +920,20 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
                 p->e_bind += pr->e_th;
                 p->e_gas += out.gas;
                 for (int j = 0; j < out.n; ++j) push(c, &out.s[j]);
+            } else if (pr->kind == KO_CHARGE_EXCHANGE) {
+                double gas;
+                k_charge_exchange(c, p, &gas);
+                p->e_gas += gas;
+            } else if (pr->kind == KO_CLUSTERING) {
+                seed_t prod;
+                double gas;
+                k_clustering(c, p, pi, xc, yc, &prod, &gas);
+                p->e_gas += gas;
+                kill(c, p, KO_CONVERTED);
+                push(c, &prod);
+                killed = 1;
             } else { /* recombination: one deletion logged in the partner's field (Sec. 3.3) */
-                const int partner = 1 - p->sp;
-                T->recomb[((size_t)partner * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz] += 1;
+                T->recomb[((size_t)pr->partner * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz] += 1;
                 kill(c, p, KO_RECOMBINED);
                 killed = 1;
             }
@@ -1005,7 +1070,7 @@ int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t) 
             transport(&c, &s, (uint32_t)pid);
         }
     }
-    size_t nd = (size_t)2 * d->n_r * d->n_z;
+    size_t nd = (size_t)c.n_species * d->n_r * d->n_z;
     for (size_t k = 0; k < nd; ++k) t->density_time[k] += c.dens_s[k] + c.dens_c[k];
     if (c.dense_s) {
         size_t ne = nd * (size_t)(d->n_dens_bins + 2);
@@ -1026,7 +1091,9 @@ int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activ
     const int nr = d->n_r, nz = d->n_z;
     const double t_sim = n_prim / activity;
     const double dz = d->length / (double)nz;
-    for (int s = 0; s < 2; ++s) {
+    const int ns = d->n_species ? d->n_species : 2;
+    if (ns < 2 || ns > KO_MAX_SPECIES) return -1;
+    for (int s = 0; s < ns; ++s) {
         for (int ir = 0; ir < nr; ++ir) {
             double r0 = d->radius * (double)ir / (double)nr;
             double r1 = d->radius * (double)(ir + 1) / (double)nr;
@@ -1104,6 +1171,14 @@ int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, 
         out[10] = pr2.s[1].e; out[11] = pr2.s[1].u; out[12] = pr2.s[1].v; out[13] = pr2.s[1].w;
         out[14] = pr2.gas;
         out[15] = pr2.w;
+    } else if (pr->kind == KO_CHARGE_EXCHANGE) {
+        k_charge_exchange(&c, &P, &out[14]);
+    } else if (pr->kind == KO_CLUSTERING) {
+        seed_t prod;
+        k_clustering(&c, &P, proc, 0.0, 0.0, &prod, &out[14]);
+        P.alive = 0;
+        out[5] = 1;
+        out[10] = prod.e; out[11] = prod.u; out[12] = prod.v; out[13] = prod.w;
     } else {
         P.alive = 0;
     }

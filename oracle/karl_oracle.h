@@ -21,38 +21,47 @@ extern "C" {
 #endif
 
 #define KO_MAX_PROC 16
+#define KO_MAX_SPECIES 4
 
-enum { KO_ELASTIC = 0, KO_EXCITATION = 1, KO_IONIZATION = 2, KO_RECOMBINATION = 3 };
-/* KO_TARGET_FIELD: the density field of the other species (electrons meet the ion field, ions
-   the electron field), Sec. 2.2 "Density fields" */
+/* interaction classes of Sec. 3.3: elastic scattering, excitation, ionization (with or without
+   dissociation of the target: the ion species made is the process's `product`), recombination,
+   charge exchange (the projectile takes the velocity of a target particle) and clustering (the
+   projectile becomes the `product` species) */
+enum { KO_ELASTIC = 0, KO_EXCITATION = 1, KO_IONIZATION = 2, KO_RECOMBINATION = 3,
+       KO_CHARGE_EXCHANGE = 4, KO_CLUSTERING = 5 };
+/* KO_TARGET_FIELD: the density field of the process's `partner` species, Sec. 2.2 "Density
+   fields" */
 enum { KO_TARGET_GAS = 0, KO_TARGET_FIELD = 1 };
 /* KO_SOURCE_PAIR: both species from the beam position and direction, even primary ids electrons
    at beam_energy, odd ids ions at beam_energy_1 */
 enum { KO_SOURCE_BETA = 0, KO_SOURCE_BEAM = 1, KO_SOURCE_PAIR = 2 };
+/* KO_CONVERTED: the projectile of a clustering reaction, replaced by its product */
 enum { KO_EXIT_LOW = 0, KO_EXIT_HIGH, KO_WALL, KO_CUTOFF, KO_RECOMBINED, KO_CAP,
-       KO_LIFETIME, KO_UNTRACKED, KO_NREASON };
+       KO_LIFETIME, KO_UNTRACKED, KO_CONVERTED, KO_NREASON };
 
 /* counters (int64) */
-#define KO_C_BIRTH         0   /* [2] particles born per species                  */
-#define KO_C_STEP          2   /* [2] flight segments per species                 */
-#define KO_C_COLL          4   /* [2] collisions per species                      */
-#define KO_C_ZCROSS        6   /* [2] z-face crossings per species                */
-#define KO_C_RCROSS        8   /* [2] r-face crossings per species (incl. wall)   */
-#define KO_C_TARGET_REDRAW 10  /* ionization target-velocity redraws              */
-#define KO_C_BEB_TRIES     11  /* secondary-energy proposals                      */
-#define KO_C_BETA_TRIES    12  /* beta-energy proposals                           */
-#define KO_C_PROC          16  /* [16] collisions per process                     */
-#define KO_C_DEATH         32  /* [2][8] deletions per species and reason         */
-#define KO_NCOUNTERS       48
+#define KO_C_BIRTH         0   /* [4] particles born per species                  */
+#define KO_C_STEP          4   /* [4] flight segments per species                 */
+#define KO_C_COLL          8   /* [4] collisions per species                      */
+#define KO_C_ZCROSS        12  /* [4] z-face crossings per species                */
+#define KO_C_RCROSS        16  /* [4] r-face crossings per species (incl. wall)   */
+#define KO_C_TARGET_REDRAW 20  /* ionization target-velocity redraws              */
+#define KO_C_BEB_TRIES     21  /* secondary-energy proposals                      */
+#define KO_C_BETA_TRIES    22  /* beta-energy proposals                           */
+#define KO_C_PROC          24  /* [16] collisions per process                     */
+#define KO_C_DEATH         40  /* [4][9] deletions per species and reason         */
+#define KO_NCOUNTERS       80
 
 /* energy / time ledger (double) */
 #define KO_L_E_PRIMARY     0   /* birth energy of primaries (eV)                  */
-#define KO_L_E_DEATH       1   /* [2][8] energy at deletion per species/reason    */
-#define KO_L_E_EXC         17  /* excitation losses                               */
-#define KO_L_E_BIND        18  /* ionization binding energies                     */
-#define KO_L_E_GAS         19  /* energy given to the gas (elastic + ionization)  */
-#define KO_L_T_ALIVE       20  /* [2] summed particle lifetimes (s)               */
-#define KO_NLEDGER         24
+#define KO_L_E_DEATH       1   /* [4][9] energy at deletion per species/reason    */
+#define KO_L_E_EXC         37  /* excitation losses                               */
+#define KO_L_E_BIND        38  /* ionization binding energies                     */
+#define KO_L_E_GAS         39  /* energy exchanged with the gas: elastic recoil, the ionization
+                                  frame, charge exchange, and minus the energy of clustering and
+                                  ionization products, whose velocity is a target particle's */
+#define KO_L_T_ALIVE       40  /* [4] summed particle lifetimes (s)               */
+#define KO_NLEDGER         48
 
 #define KO_NHIST           4   /* per history: E_in, E_accounted, n_born, n_dead  */
 
@@ -71,10 +80,15 @@ typedef struct {
 } ko_species;
 
 typedef struct {
-    int32_t kind;         /* KO_ELASTIC ... */
-    int32_t species;      /* projectile slot: 0 electron, 1 ion */
+    int32_t kind;         /* KO_ELASTIC ... KO_CLUSTERING */
+    int32_t species;      /* projectile slot 0..n_species-1 (slot 0: electrons) */
     int32_t target;       /* KO_TARGET_GAS or KO_TARGET_FIELD */
-    int32_t pad;
+    int32_t product;      /* ionization: the ion species made (1..n_species-1); clustering: the
+                             species the projectile becomes; ignored otherwise */
+    int32_t partner;      /* KO_TARGET_FIELD: the species whose density field is the target */
+    int32_t density_power;/* gas targets: the collision rate goes as n_gas^density_power (1, or 2
+                             for three-body clustering, whose "cross section" is k/v in m^5);
+                             0 means 1 */
     double e_th;          /* excitation energy or binding energy (eV); 0 otherwise */
     const double* xs;     /* [n_e] cross section (m^2) at the species' nodes */
     /* elastic scattering angle (Sec. 3.3 "Elastic scattering"): isotropic in the centre-of-mass
@@ -92,12 +106,14 @@ typedef struct {
     double radius, length;       /* m */
     int32_t n_r, n_z;            /* grid (>= 1 each) */
     const double* n_gas;         /* [n_z] gas density per z-cell (m^-3) */
-    const double* n_ion;         /* [n_r*n_z] ion density field, target of electrons (m^-3) or NULL = 0 */
-    const double* n_elec;        /* [n_r*n_z] electron density field, target of ions, or NULL = 0 */
+    /* [n_r*n_z] density field of each species (m^-3), the target of processes with that
+       partner; NULL = 0 */
+    const double* n_field[KO_MAX_SPECIES];
     double t_gas;                /* K */
     double m_gas;                /* kg */
     double bz;                   /* T; 0: straight lines */
-    ko_species sp[2];
+    ko_species sp[KO_MAX_SPECIES];
+    int32_t n_species;           /* 2..4; 0 means 2 */
     int32_t n_proc, n_e;
     ko_process proc[KO_MAX_PROC];
     int32_t source, beam_species;
@@ -116,14 +132,15 @@ typedef struct {
 typedef struct {
     int64_t* counters;     /* [KO_NCOUNTERS] */
     double* ledger;        /* [KO_NLEDGER] */
-    double* density_time;  /* [2][n_r][n_z] seconds */
-    int64_t* recomb;       /* [2][n_r][n_z] recombinations logged in the field of each species */
-    int64_t* jz;           /* [2][n_r][n_z+1][2] */
-    int64_t* jr;           /* [2][n_r+1][n_z][2] */
-    int64_t* spectra;      /* [2][n_planes][2][n_bins+2] */
+    /* leading index: species 0..n_species-1 */
+    double* density_time;  /* [S][n_r][n_z] seconds */
+    int64_t* recomb;       /* [S][n_r][n_z] recombinations logged in the field of each species */
+    int64_t* jz;           /* [S][n_r][n_z+1][2] */
+    int64_t* jr;           /* [S][n_r+1][n_z][2] */
+    int64_t* spectra;      /* [S][n_planes][2][n_bins+2] */
     uint64_t* digests;     /* [n_primaries] or NULL */
     double* hist;          /* [n_primaries][KO_NHIST] or NULL */
-    /* [2][n_r][n_z][n_dens_bins+2] time per segment and energy bin (bin 0 below the first
+    /* [S][n_r][n_z][n_dens_bins+2] time per segment and energy bin (bin 0 below the first
        edge, n_dens_bins+1 at or above the last), or NULL */
     double* density_time_e;
 } ko_tallies;
@@ -133,7 +150,7 @@ int ko_run(const ko_desc* d, int64_t pid_begin, int64_t pid_end, ko_tallies* t);
 
 /* Densities per species and segment, eq. (3) with t_sim = n_prim/activity, eq. (4), minus the
    recombinations logged in that species' field per volume; currents (N+ - N-)/(A t_sim) through the
-   z-faces of each ring ([2][n_r][n_z+1]) and the r-faces of each z-segment ([2][n_r+1][n_z]). */
+   z-faces of each ring ([S][n_r][n_z+1]) and the r-faces of each z-segment ([S][n_r+1][n_z]). */
 int ko_fields(const ko_desc* d, const ko_tallies* t, double n_prim, double activity,
               double* density, double* jz_cur, double* jr_cur);
 
@@ -155,8 +172,8 @@ double ko_debug_angle(const ko_desc* d, int proc, double e_cm, double u);
 int ko_birth(const ko_desc* d, int64_t pid, double out[8]);
 /* kinematics of process `proc` for one particle at the origin:
    out[0]=E', out[1..3]=dir', out[4]=alive, out[5]=n_products,
-   out[6]=E_slow, out[7..9]=dir_slow, out[10]=E_ion, out[11..13]=dir_ion,
-   out[14]=energy to gas, out[15]=w (ionization) */
+   out[6]=E_slow, out[7..9]=dir_slow, out[10]=E_ion, out[11..13]=dir_ion (ionization; the
+   clustering product is reported as the ion), out[14]=energy to gas, out[15]=w (ionization) */
 int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, uint32_t s,
                      double e, const double dir[3], double out[16]);
 /* helix: position and direction after path length `path` (guiding-centre formulas) */

@@ -35,18 +35,28 @@ A0 = 5.29177210903e-11          # Bohr radius, m
 RYD_EV = 13.605693122994        # Rydberg energy, eV
 M_H2 = 2.01565006414 * AMU      # two 1H atoms (electron masses included)
 M_H2P = M_H2 - M_E              # H2+ ion
+M_HP = 1.00727646688 * AMU      # proton
+M_H3P = 3.0 * 1.00782503207 * AMU - M_E     # H3+ (binding energies neglected)
+M_T = 3.01604928 * AMU          # tritium atom
+M_T2 = 2.0 * M_T                # T2 molecule (binding energy neglected)
+M_TP = M_T - M_E                # T+
+M_T2P = M_T2 - M_E              # T2+
+M_T3P = 3.0 * M_T - M_E         # T3+
 
 # process kinds
 ELASTIC = 0
 EXCITATION = 1
 IONIZATION = 2
 RECOMBINATION = 3
-KIND_NAMES = {ELASTIC: "elastic", EXCITATION: "excitation",
-              IONIZATION: "ionization", RECOMBINATION: "recombination"}
+CHARGE_EXCHANGE = 4
+CLUSTERING = 5
+KIND_NAMES = {ELASTIC: "elastic", EXCITATION: "excitation", IONIZATION: "ionization",
+              RECOMBINATION: "recombination", CHARGE_EXCHANGE: "charge exchange",
+              CLUSTERING: "clustering"}
 
-# target of a process: the background gas or the frozen ion-density field
+# target of a process: the background gas or a density field (Sec. 2.2)
 TARGET_GAS = 0
-TARGET_FIELD = 1            # the density field of the other species (Sec. 2.2)
+TARGET_FIELD = 1            # the density field of the process's partner species
 TARGET_ION_FIELD = TARGET_FIELD
 
 # primary source
@@ -54,13 +64,15 @@ SOURCE_BETA = 0
 SOURCE_BEAM = 1
 SOURCE_PAIR = 2             # beam of both species: even ids electrons, odd ids ions
 
-# species slots
+# species slots: 0 electrons, 1 the molecular ion; chemistry jobs add slots 2 and 3
 ELECTRON = 0
 ION = 1
+MAX_SPECIES = 4
 
-# deletion reasons (deletion logger, Sec. "Termination")
+# deletion reasons (deletion logger, Sec. "Termination"); "converted": the projectile of a
+# clustering reaction, replaced by its product
 REASONS = ["exit_low", "exit_high", "wall", "cutoff", "recombined", "cap",
-           "lifetime", "untracked"]
+           "lifetime", "untracked", "converted"]
 
 MAX_PROC = 16
 
@@ -108,6 +120,9 @@ class Process:
     xs: np.ndarray              # [n_e] cross section in m^2 at the species' nodes
     name: str = ""
     angular: Optional[AngularTable] = None   # elastic only; None: isotropic
+    product: int = ION          # ionization: ion species made; clustering: species made
+    partner: Optional[int] = None   # TARGET_FIELD: species of the field (None: 1 - species)
+    density_power: int = 1      # gas targets: rate ~ n_gas^density_power (2: three-body)
 
 
 @dataclass
@@ -138,8 +153,9 @@ class Workload:
     planes: List[int] = field(default_factory=list)   # z-face indices
     n_primaries: int = 0
     n_elec: Optional[np.ndarray] = None   # [n_r*n_z] m^-3 electron field (target of ions)
-    dens_edges: Optional[tuple] = None    # (electron, ion) energy-bin edges of the density field
+    dens_edges: Optional[tuple] = None    # per-species energy-bin edges of the density field
     beam_energy_1: float = 0.0            # eV: ion energy of SOURCE_PAIR
+    extra_fields: Optional[dict] = None   # slot (2, 3) -> [n_r*n_z] m^-3 density field
 
     @property
     def n_bins(self) -> int:
@@ -391,6 +407,154 @@ def screened_table(e_iso: float = 100.0, n_bins: int = 6, n_nodes: int = 64,
         eta = 3.4 / e
         pdf[b] = np.sin(theta) / (1.0 + 2.0 * eta - np.cos(theta)) ** 2
     return AngularTable(edges=edges, theta=theta, pdf=pdf, e_iso=e_iso)
+
+
+# ----------------------------------------------------------------------------
+# ion chemistry (Sec. 3.3 "Clustering", "Charge exchange", "Ionization";
+# Sec. 4 "Clustering", "Charge Exchange")
+# ----------------------------------------------------------------------------
+def rate_table(k: float, mass: float, m_gas: float, nodes_xs: np.ndarray) -> np.ndarray:
+    """Cross section k / v of a process known by its rate coefficient k (m^3/s for two-body,
+    m^6/s for three-body reactions, giving m^2 or m^5), at table nodes given as the
+    interpolation energy E_xs = E M/(m+M) of a projectile of `mass` on gas at rest; v is the
+    projectile's speed at E = E_xs (m+M)/M."""
+    e_lab = np.asarray(nodes_xs, np.float64) * (mass + m_gas) / m_gas
+    v = np.sqrt(2.0 * e_lab * QE / mass)
+    return k / v
+
+
+def xs_charge_exchange(e_cm: np.ndarray, a: float = 4.0e-10, b: float = 0.3e-10) -> np.ndarray:
+    """Resonant charge-exchange shape sigma = (a - b ln(E/eV))^2 (m^2), E in eV."""
+    return (a - b * np.log(np.asarray(e_cm, np.float64))) ** 2
+
+
+def ion_species(name: str, mass: float, tracked: bool = True, emin: float = 1.0e-4,
+                emax: float = 1.0e2, n_bins: int = 100, lifetime: float = math.inf) -> Species:
+    return Species(name, mass, QE, tracked, 0.0, 1_000_000, lifetime, emin, emax,
+                   np.linspace(0.0, emax, n_bins + 1))
+
+
+CLUSTERING_CASES = {
+    # name: (projectile slot, density (m^-3), density power, cross section or rate coefficient)
+    "t2p_radiative": (ION, 1.0e18, 1, 1.91e-18),     # T2+ + T2 -> T3+ + T, sigma (m^2)
+    "tp_tertiary": (2, 1.0e22, 2, 2.6e-41),          # T+ + 2 T2 -> T3+ + T2, k_ter (m^6/s)
+    "tp_radiative": (2, 2.0e25, 1, 5.0e-23),         # T+ + T2 -> T3+ + h nu, k_rad (m^3/s)
+}
+
+
+def clustering_beam(case: str, n_primaries: int = 80_000, e_beam: float = 6.8e-3,
+                    length: float = 2.0, n_z: int = 40, bz: float = 2.5, t_gas: float = 80.0,
+                    seed: int = 21) -> Workload:
+    """The clustering test of Sec. 4: an ion beam of 6.8 meV along +z on the axis of a uniform
+    tritium column in a 2.5 T field; the only process of the injected ion is clustering into
+    T3+ (slot 3), with the paper's cross section (T2+) or rate coefficient (T+ radiative and
+    three-body, 80 K values).  Species: e- (0), T2+ (1), T+ (2), T3+ (3, no processes).  The
+    injected ion's density decays as exp(-z / lambda) with lambda = 1/(sigma n), v/(k n) or
+    v/(k n^2)."""
+    slot, n, power, coef = CLUSTERING_CASES[case]
+    masses = {ION: M_T2P, 2: M_TP}
+    m = masses[slot]
+    n_e = 64
+    gf = M_T2 / (m + M_T2)
+    e_xs = e_beam * gf
+    # table nodes from the beam's interpolation energy upwards: the beam sits on node 0
+    ions = []
+    for name, mass in (("T2+", M_T2P), ("T+", M_TP), ("T3+", M_T3P)):
+        ions.append(ion_species(name, mass, emin=e_xs if mass == m else 1.0e-4, emax=1.0e2))
+    nodes = log_nodes(e_xs, 1.0e2, n_e)
+    xs = np.full(n_e, coef) if case == "t2p_radiative" else rate_table(coef, m, M_T2, nodes)
+    proc = [Process(CLUSTERING, slot, TARGET_GAS, 0.0, xs, case, product=3, density_power=power)]
+    species = [electron(edges=np.linspace(0.0, 2.0e4, 11)), *ions]
+    for sp in ions:
+        sp.edges = np.linspace(0.0, 1.0, 11)
+    return Workload(
+        name=f"clustering {case}", radius=0.05, length=length, n_r=1, n_z=n_z,
+        n_gas=np.full(n_z, n), n_ion=None, t_gas=t_gas, m_gas=M_T2, bz=bz, species=species,
+        processes=proc, n_e=n_e, source=SOURCE_BEAM, beam_species=slot, beam_energy=e_beam,
+        beam_pos=(0.0, 0.0, 0.0), beam_dir=(0.0, 0.0, 1.0), seed=seed, planes=[0, n_z],
+        n_primaries=n_primaries)
+
+
+def charge_exchange_box(n_primaries: int = 2000, e_beam: float = 10.0, n: float = 1.224e19,
+                        t_gas: float = 80.0, lifetime: float = 0.5, n_bins: int = 40,
+                        seed: int = 23) -> Workload:
+    """The charge-exchange test of Sec. 4 in an unbounded form: T2+ ions of 10 eV start in a T2
+    gas of 1.224e19 m^-3 at 80 K whose only ion process is resonant charge exchange; the
+    column (1 km) is far larger than the ions' diffusion length and every ion is deleted
+    after `lifetime`, so the time spent per energy interval (the energy-resolved density
+    field) tends to the Maxwell-Boltzmann energy density of the gas, weighted with the mean
+    time between exchanges, 1/(n sigma(E) v(E))."""
+    n_e = 256
+    emin, emax = 1.0e-5, 1.0e2
+    nodes = log_nodes(emin, emax, n_e)
+    proc = [Process(CHARGE_EXCHANGE, ION, TARGET_GAS, 0.0, xs_charge_exchange(nodes),
+                    "T2+ charge exchange")]
+    ion = ion_species("T2+", M_T2P, emin=emin, emax=emax, n_bins=n_bins, lifetime=lifetime)
+    species = [electron(edges=np.linspace(0.0, 2.0e4, n_bins + 1)), ion]
+    kt = KB * t_gas / QE
+    e_hi = 8.0 * kt * M_T2P / M_T2
+    edges = np.linspace(0.0, e_hi, n_bins + 1)
+    w = Workload(
+        name="charge exchange", radius=1.0e3, length=2.0e3, n_r=1, n_z=1,
+        n_gas=np.array([n]), n_ion=None, t_gas=t_gas, m_gas=M_T2, bz=0.0, species=species,
+        processes=proc, n_e=n_e, source=SOURCE_BEAM, beam_species=ION, beam_energy=e_beam,
+        beam_pos=(0.0, 0.0, 1.0e3), beam_dir=(0.0, 0.0, 1.0), seed=seed, planes=[0, 1],
+        n_primaries=n_primaries)
+    w.dens_edges = (np.linspace(0.0, 2.0e4, n_bins + 1), edges)
+    return w
+
+
+def hydrogen_chemistry(n_primaries: int = 4000, bz: float = 2.5, column_cm2: float = 5.0e15,
+                       n_r: int = 4, n_z: int = 32, seed: int = 31,
+                       boost: float = 1.0e6) -> Workload:
+    """Beta electrons in H2 with the ion chemistry of Sec. 3.3 on the same kernels: electron
+    elastic scattering, excitation, ionization to H2+ (slot 1) and dissociative ionization to
+    H+ (slot 2); H2+ elastic scattering, charge exchange and clustering to H3+ (slot 3); H+
+    elastic scattering with radiative and three-body clustering to H3+; H3+ elastic
+    scattering; H+ recombining on the electron field and electrons on the H3+ field.  The
+    clustering rate coefficients are the paper's 80 K values times `boost` and the
+    recombination cross sections are enlarged likewise, so that a short tube sees all
+    channels."""
+    n_e = 256
+    length = 1.0
+    n = column_cm2 * 1.0e4 / length
+    en = log_nodes(1.0, 2.0e4, n_e)
+    ei = log_nodes(1.0e-4, 1.0e2, n_e)
+    procs = [
+        Process(ELASTIC, ELECTRON, TARGET_GAS, 0.0, xs_elastic_e(en), "e elastic"),
+        Process(IONIZATION, ELECTRON, TARGET_GAS, 15.43, xs_beb(en), "e ionization -> H2+",
+                product=ION),
+        Process(IONIZATION, ELECTRON, TARGET_GAS, 18.08, 0.1 * xs_beb(en, b=18.08, u=18.08),
+                "e dissociative ionization -> H+", product=2),
+        Process(EXCITATION, ELECTRON, TARGET_GAS, 12.6, xs_excitation(en, 12.6, 1.5e-20), "e exc 12.6"),
+        Process(RECOMBINATION, ELECTRON, TARGET_FIELD, 0.0, 1.0e5 * xs_recombination(en),
+                "e + H3+ recombination", partner=3),
+        Process(ELASTIC, ION, TARGET_GAS, 0.0, xs_langevin(ei), "H2+ Langevin elastic"),
+        Process(CHARGE_EXCHANGE, ION, TARGET_GAS, 0.0, xs_charge_exchange(ei), "H2+ charge exchange"),
+        Process(CLUSTERING, ION, TARGET_GAS, 0.0, np.full(n_e, 1.91e-18), "H2+ + H2 -> H3+ + H",
+                product=3),
+        Process(ELASTIC, 2, TARGET_GAS, 0.0, xs_langevin(ei), "H+ Langevin elastic"),
+        Process(CLUSTERING, 2, TARGET_GAS, 0.0, rate_table(5.0e-23 * boost, M_HP, M_H2, ei),
+                "H+ + H2 -> H3+ radiative", product=3),
+        Process(CLUSTERING, 2, TARGET_GAS, 0.0, rate_table(2.6e-41 * boost, M_HP, M_H2, ei),
+                "H+ + 2 H2 -> H3+ three-body", product=3, density_power=2),
+        Process(RECOMBINATION, 2, TARGET_FIELD, 0.0, np.full(n_e, 2.0e-16), "H+ + e recombination",
+                partner=ELECTRON),
+        Process(ELASTIC, 3, TARGET_GAS, 0.0, xs_langevin(ei), "H3+ Langevin elastic"),
+    ]
+    z = (np.arange(n_z) + 0.5) / n_z
+    n_e_field = np.repeat((2.0e15 * (1.0 - 0.5 * z))[None, :], n_r, axis=0).reshape(-1)
+    n_h3_field = np.repeat((1.0e15 * (0.5 + z))[None, :], n_r, axis=0).reshape(-1)
+    species = [electron(),
+               ion_species("H2+", M_H2P, n_bins=200),
+               ion_species("H+", M_HP, n_bins=200),
+               ion_species("H3+", M_H3P, n_bins=200)]
+    species[0].edges = np.linspace(0.0, 2.0e4, 201)
+    return Workload(
+        name="hydrogen chemistry", radius=0.045, length=length, n_r=n_r, n_z=n_z,
+        n_gas=np.full(n_z, n), n_ion=None, t_gas=80.0, m_gas=M_H2, bz=bz, species=species,
+        processes=procs, n_e=n_e, source=SOURCE_BETA, seed=seed, planes=[0, n_z // 2, n_z],
+        n_primaries=n_primaries, n_elec=n_e_field, extra_fields={3: n_h3_field})
 
 
 def with_primaries(w: Workload, n: int) -> Workload:

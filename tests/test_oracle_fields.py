@@ -33,8 +33,8 @@ def test_pair_source_species_by_parity(oracle_lib):
         sp = pid & 1
         assert c[oracle_lib.C_BIRTH + sp] == 1 and c[oracle_lib.C_BIRTH + 1 - sp] == 0
         # with empty fields both exit at the far end with their injection energy
-        assert c[oracle_lib.C_DEATH + sp * 8 + W.REASONS.index("exit_high")] == 1
-        e_exit = t["ledger"][oracle_lib.L_E_DEATH + sp * 8 + W.REASONS.index("exit_high")]
+        assert c[oracle_lib.C_DEATH + sp * oracle_lib.NREASON + W.REASONS.index("exit_high")] == 1
+        e_exit = t["ledger"][oracle_lib.L_E_DEATH + sp * oracle_lib.NREASON + W.REASONS.index("exit_high")]
         assert e_exit == (w.beam_energy_1 if sp else w.beam_energy)
 
 
@@ -45,7 +45,7 @@ def test_ion_recombination_on_fixed_electron_field(oracle_lib):
     t = oracle_lib.run(w)
     N = w.n_primaries // 2                       # odd ids are ions
     mu = n_e * sig
-    trans = t["counters"][oracle_lib.C_DEATH + 8 + W.REASONS.index("exit_high")]
+    trans = t["counters"][oracle_lib.C_DEATH + oracle_lib.NREASON + W.REASONS.index("exit_high")]
     p = math.exp(-mu * L)
     assert abs(trans - N * p) < 4.0 * math.sqrt(N * p * (1 - p))
     counts = t["recomb"][0, 0]                    # ion recombinations, logged in the electron field
@@ -85,4 +85,4 @@ def test_coupled_recombination_slope(oracle_lib):
     # every recombination of one species is a deletion logged in the other's field
     c = t["counters"]
     assert c[oracle_lib.C_DEATH + W.REASONS.index("recombined")] == t["recomb"][1].sum()
-    assert c[oracle_lib.C_DEATH + 8 + W.REASONS.index("recombined")] == t["recomb"][0].sum()
+    assert c[oracle_lib.C_DEATH + oracle_lib.NREASON + W.REASONS.index("recombined")] == t["recomb"][0].sum()

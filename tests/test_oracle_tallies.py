@@ -107,10 +107,11 @@ def _check_conservation(oracle_lib, w, n):
     # each ionization makes one electron and one ion (charge conservation)
     assert c[oracle_lib.C_BIRTH] == n + n_ion_proc
     assert c[oracle_lib.C_BIRTH + 1] == n_ion_proc
-    deaths = c[oracle_lib.C_DEATH:oracle_lib.C_DEATH + 16].reshape(2, 8)
+    nr = oracle_lib.NREASON
+    deaths = c[oracle_lib.C_DEATH:oracle_lib.C_DEATH + 2 * nr].reshape(2, nr)
     assert deaths[0].sum() == c[oracle_lib.C_BIRTH] and deaths[1].sum() == c[oracle_lib.C_BIRTH + 1]
     L = t["ledger"]
-    total_out = L[oracle_lib.L_E_DEATH:oracle_lib.L_E_DEATH + 16].sum() + \
+    total_out = L[oracle_lib.L_E_DEATH:oracle_lib.L_E_DEATH + 2 * nr].sum() + \
         L[oracle_lib.L_E_EXC] + L[oracle_lib.L_E_BIND] + L[oracle_lib.L_E_GAS]
     assert abs(total_out / L[oracle_lib.L_E_PRIMARY] - 1.0) < 1e-12
     # recombination deletions equal the deletions logged in the partner's field
@@ -128,7 +129,7 @@ def test_conservation_full_capped(oracle_lib):
     w.species[W.ION].cap = 2000
     t = _check_conservation(oracle_lib, w, 40)
     c = t["counters"]
-    assert c[oracle_lib.C_DEATH + 8 + W.REASONS.index("cap")] > 0
+    assert c[oracle_lib.C_DEATH + oracle_lib.NREASON + W.REASONS.index("cap")] > 0
 
 
 def test_gas_at_rest_energy_budget(oracle_lib):
