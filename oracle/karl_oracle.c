@@ -344,7 +344,8 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
         if (pr->kind == KO_IONIZATION && (pr->product < 1 || pr->product >= c->n_species)) return -1;
         if (pr->kind == KO_CLUSTERING &&
             (pr->product < 0 || pr->product >= c->n_species || pr->product == s)) return -1;
-        if (pr->target == KO_TARGET_FIELD && (pr->partner < 0 || pr->partner >= c->n_species))
+        if ((pr->target == KO_TARGET_FIELD || pr->kind == KO_RECOMBINATION) &&
+            (pr->partner < 0 || pr->partner >= c->n_species))
             return -1;
         if (pr->target != KO_TARGET_GAS && pr->target != KO_TARGET_FIELD) return -1;
         if (pr->density_power < 0 || pr->density_power > 2) return -1;

@@ -85,7 +85,8 @@ typedef struct {
     int32_t target;       /* KO_TARGET_GAS or KO_TARGET_FIELD */
     int32_t product;      /* ionization: the ion species made (1..n_species-1); clustering: the
                              species the projectile becomes; ignored otherwise */
-    int32_t partner;      /* KO_TARGET_FIELD: the species whose density field is the target */
+    int32_t partner;      /* KO_TARGET_FIELD: the species whose density field is the target;
+                             recombination: the species whose field logs the deletion */
     int32_t density_power;/* gas targets: the collision rate goes as n_gas^density_power (1, or 2
                              for three-body clustering, whose "cross section" is k/v in m^5);
                              0 means 1 */
