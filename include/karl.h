@@ -43,11 +43,17 @@ typedef int32_t karl_status;
 #define KARL_ENUMERIC  (-6)  /* NaN/Inf met in the particle state                     */
 
 #define KARL_MAX_PROC 16
+#define KARL_MAX_SPECIES 4
 
-enum { KARL_ELASTIC = 0, KARL_EXCITATION = 1, KARL_IONIZATION = 2, KARL_RECOMBINATION = 3 };
-/* target of a process: the gas, or the density field of the other species (electrons meet
-   the ion field, ions the electron field; Sec. 2.2 "Density fields"); TARGET_ION_FIELD is the
-   older name of the electrons' case */
+/* interaction classes (Sec. 3.3): elastic scattering, excitation, ionization (the ion made is
+   the process's `product` species: the molecular ion, or the atomic ion of dissociative
+   ionization), recombination, charge exchange (the projectile continues with the velocity of a
+   target particle) and clustering (the projectile is replaced by a particle of the `product`
+   species moving along a target particle's velocity with that particle's momentum) */
+enum { KARL_ELASTIC = 0, KARL_EXCITATION = 1, KARL_IONIZATION = 2, KARL_RECOMBINATION = 3,
+       KARL_CHARGE_EXCHANGE = 4, KARL_CLUSTERING = 5 };
+/* target of a process: the gas, or the density field of the process's `partner` species
+   (Sec. 2.2 "Density fields"); TARGET_ION_FIELD is the older name of the electrons' case */
 enum { KARL_TARGET_GAS = 0, KARL_TARGET_FIELD = 1, KARL_TARGET_ION_FIELD = 1 };
 /* KARL_SOURCE_PAIR: both species from the beam position and direction, even primary ids
    electrons at beam_energy, odd ids ions at beam_energy_1 */
@@ -70,31 +76,35 @@ enum { KARL_MAP_AUTO = 0, KARL_MAP_LANE = 1, KARL_MAP_WAVE = 2 };
 #define KARL_FLAG_DIGESTS 1u   /* per-primary 64-bit digest of the event sequence          */
 #define KARL_FLAG_HISTORY 2u   /* per-primary ledger: E_in, E_accounted, n_born, n_deleted  */
 
-/* deletion reasons (Sec. 3.2, deletion logger) */
+/* deletion reasons (Sec. 3.2, deletion logger); KARL_CONVERTED: the projectile of a clustering
+   reaction, replaced by its product */
 enum { KARL_EXIT_LOW = 0, KARL_EXIT_HIGH, KARL_WALL, KARL_CUTOFF, KARL_RECOMBINED, KARL_CAP,
-       KARL_LIFETIME, KARL_UNTRACKED, KARL_NREASON };
+       KARL_LIFETIME, KARL_UNTRACKED, KARL_CONVERTED, KARL_NREASON };
 
-/* layout of the counters array (int64) */
-#define KARL_C_BIRTH          0  /* [2] particles born per species                      */
-#define KARL_C_STEP           2  /* [2] flight segments per species                     */
-#define KARL_C_COLL           4  /* [2] interactions per species                        */
-#define KARL_C_ZCROSS         6  /* [2] z-face crossings per species                    */
-#define KARL_C_RCROSS         8  /* [2] r-face crossings per species (wall included)    */
-#define KARL_C_TARGET_REDRAW 10  /* ionization target-velocity redraws                  */
-#define KARL_C_BEB_TRIES     11  /* secondary-energy proposals                          */
-#define KARL_C_BETA_TRIES    12  /* beta-energy proposals                               */
-#define KARL_C_PROC          16  /* [16] interactions per process                       */
-#define KARL_C_DEATH         32  /* [2][8] deletions per species and reason             */
-#define KARL_NCOUNTERS       48
+/* layout of the counters array (int64); per-species entries have KARL_MAX_SPECIES slots */
+#define KARL_C_BIRTH          0  /* [4] particles born per species                      */
+#define KARL_C_STEP           4  /* [4] flight segments per species                     */
+#define KARL_C_COLL           8  /* [4] interactions per species                        */
+#define KARL_C_ZCROSS        12  /* [4] z-face crossings per species                    */
+#define KARL_C_RCROSS        16  /* [4] r-face crossings per species (wall included)    */
+#define KARL_C_TARGET_REDRAW 20  /* ionization target-velocity redraws                  */
+#define KARL_C_BEB_TRIES     21  /* secondary-energy proposals                          */
+#define KARL_C_BETA_TRIES    22  /* beta-energy proposals                               */
+#define KARL_C_PROC          24  /* [16] interactions per process                       */
+#define KARL_C_DEATH         40  /* [4][9] deletions per species and reason             */
+#define KARL_NCOUNTERS       80
 
 /* layout of the ledger array (double) */
 #define KARL_L_E_PRIMARY      0  /* summed birth energy of primaries (eV)               */
-#define KARL_L_E_DEATH        1  /* [2][8] energy at deletion per species and reason    */
-#define KARL_L_E_EXC         17  /* excitation energy losses                            */
-#define KARL_L_E_BIND        18  /* ionization binding energies                         */
-#define KARL_L_E_GAS         19  /* energy handed to the gas (elastic, ionization frame) */
-#define KARL_L_T_ALIVE       20  /* [2] summed particle lifetimes (s)                   */
-#define KARL_NLEDGER         24
+#define KARL_L_E_DEATH        1  /* [4][9] energy at deletion per species and reason    */
+#define KARL_L_E_EXC         37  /* excitation energy losses                            */
+#define KARL_L_E_BIND        38  /* ionization binding energies                         */
+#define KARL_L_E_GAS         39  /* energy exchanged with the gas: elastic recoil, the
+                                    ionization frame, charge exchange, and minus the energy of
+                                    ionization and clustering products (a target particle's
+                                    velocity)                                           */
+#define KARL_L_T_ALIVE       40  /* [4] summed particle lifetimes (s)                   */
+#define KARL_NLEDGER         48
 
 #define KARL_NHIST            4  /* per-primary ledger entries                          */
 
@@ -114,10 +124,16 @@ typedef struct {
 } karl_species_desc;
 
 typedef struct {
-    int32_t kind;           /* KARL_ELASTIC ... KARL_RECOMBINATION */
-    int32_t species;        /* projectile: 0 electron slot, 1 ion slot */
+    int32_t kind;           /* KARL_ELASTIC ... KARL_CLUSTERING */
+    int32_t species;        /* projectile slot 0..n_species-1 (slot 0: electrons) */
     int32_t target;         /* KARL_TARGET_GAS or KARL_TARGET_FIELD */
-    int32_t reserved0;
+    int32_t product;        /* ionization: the ion species made (1..n_species-1); clustering:
+                               the species the projectile becomes; ignored otherwise */
+    int32_t partner;        /* KARL_TARGET_FIELD: the species whose density field is the
+                               target (all field processes of one species share one partner);
+                               recombination: the species whose field logs the deletion */
+    int32_t density_power;  /* gas targets: the rate goes as n_gas^density_power, 1 or 2
+                               (three-body clustering: xs holds k/v in m^5); 0 means 1 */
     double e_th;            /* eV: excitation energy or ionization binding energy; 0 else */
     const double* xs;       /* [n_e] cross section (m^2) at the projectile species' nodes */
     /* elastic scattering angle (Sec. 3.3 "Elastic scattering"): isotropic in the centre-of-mass
@@ -137,12 +153,14 @@ typedef struct {
     double radius, length;        /* cylinder r <= radius, 0 <= z <= length (m) */
     int32_t n_r, n_z;             /* segments of the density/current grid (>= 1) */
     const double* n_gas;          /* [n_z] gas density per z-segment (m^-3) */
-    const double* n_ion;          /* [n_r*n_z] ion density field, target of electrons (m^-3); NULL: 0 */
-    const double* n_elec;         /* [n_r*n_z] electron density field, target of ions; NULL: 0 */
+    /* [n_r*n_z] density field of each species (m^-3), seen by field-target processes that
+       name it as partner; NULL: 0 */
+    const double* n_field[KARL_MAX_SPECIES];
     double t_gas;                 /* gas temperature (K); 0: target at rest */
     double m_gas;                 /* gas molecule mass (kg) */
     double bz;                    /* axial field (T); 0 selects straight-line transport */
-    karl_species_desc species[2]; /* slot 0 electrons, slot 1 ions */
+    karl_species_desc species[KARL_MAX_SPECIES]; /* slot 0 electrons, 1.. ions */
+    int32_t n_species;            /* 2..KARL_MAX_SPECIES; 0 means 2 */
     int32_t n_proc;               /* <= KARL_MAX_PROC */
     int32_t n_e;                  /* cross-section nodes per table, 2..1024 */
     karl_process_desc proc[KARL_MAX_PROC];
@@ -168,9 +186,9 @@ typedef struct {
                                      times per segment with an energy axis), 0..4096; 0: none */
 } karl_job_desc;
 
-/* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements:
-   counters KARL_NCOUNTERS; ledger KARL_NLEDGER; density_time 2*n_r*n_z;
-   recomb 2*n_r*n_z; jz 2*n_r*(n_z+1)*2; jr 2*(n_r+1)*n_z*2; spectra 2*n_planes*2*(n_bins+2);
+/* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements, with
+   S = n_species: counters KARL_NCOUNTERS; ledger KARL_NLEDGER; density_time S*n_r*n_z;
+   recomb S*n_r*n_z; jz S*n_r*(n_z+1)*2; jr S*(n_r+1)*n_z*2; spectra S*n_planes*2*(n_bins+2);
    digests n_primaries (needs KARL_FLAG_DIGESTS); hist n_primaries*KARL_NHIST
    (needs KARL_FLAG_HISTORY).  Index order is row-major in the order written. */
 typedef struct {
@@ -178,7 +196,7 @@ typedef struct {
     double* ledger;
     double* density_time;   /* [species][r][z] seconds spent per segment (eq. 3 numerator) */
     int64_t* recomb;        /* [species][r][z] recombinations logged in that species' field:
-                               N_gamma of eq. 3 (made by the other species) */
+                               N_gamma of eq. 3 (made by its partners) */
     int64_t* jz;            /* [species][r][z-face][dir] crossings, dir 1 = +z (Sec. 2.3) */
     int64_t* jr;            /* [species][r-face][z][dir] crossings, dir 1 = outward */
     int64_t* spectra;       /* [species][plane][dir][bin] with under/overflow bins 0, n_bins+1 */
@@ -214,14 +232,14 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream);
    the recombinations logged in that species' field in the segment per volume (eq. 3); jz_current
    [species][r][z-face] and jr_current[species][r-face][z] = (N+ - N-)/(A t_sim) through the
    face (current collection, Sec. 2.3), in particles per m^2 per s; A of r-face 0 is zero and
-   its current is reported as 0.  Sizes 2*n_r*n_z, 2*n_r*(n_z+1), 2*(n_r+1)*n_z doubles; NULL
-   pointers are skipped.  KARL_ESTATE if nothing was transported. */
+   its current is reported as 0.  Sizes S*n_r*n_z, S*n_r*(n_z+1), S*(n_r+1)*n_z doubles (S =
+   n_species); NULL pointers are skipped.  KARL_ESTATE if nothing was transported. */
 karl_status karl_read_fields(void* job, double activity, double* density, double* jz_current,
                              double* jr_current, void* hip_stream);
 
 /* Self-consistent target fields (Sec. 2.2 "Density fields", Sec. 3.6 cycles): set the density
-   field of each species, which processes of the other species with KARL_TARGET_FIELD see, to
-   that species' density from the tallies of all primaries transported so far, eq. (3) with
+   field of each species that a KARL_TARGET_FIELD process names as partner to that species'
+   density from the tallies of all primaries transported so far, eq. (3) with
    t_sim = N_prim / activity (eq. 4), negative values set to zero.  Calling it after every
    cycle of primaries makes the later cycles interact with the particles of the earlier ones.
    No effect on a job without field targets; KARL_ESTATE if nothing was transported. */

@@ -69,7 +69,9 @@ size_t angle_doubles(const karl_job_desc* d) {
     return n;
 }
 
-// some process targets a species' density field (then both fields get device storage)
+int species_count(const karl_job_desc* d) { return d->n_species ? d->n_species : 2; }
+
+// some process targets a species' density field (then every species' field gets device storage)
 bool uses_fields(const karl_job_desc* d) {
     for (int i = 0; i < d->n_proc && i < KARL_MAX_PROC; ++i)
         if (d->proc[i].target == KARL_TARGET_FIELD) return true;
@@ -80,6 +82,7 @@ Layout make_layout(const karl_job_desc* d) {
     Layout L{};
     const size_t rs = real_size(d);
     const size_t nr = (size_t)d->n_r, nz = (size_t)d->n_z;
+    const size_t ns = (size_t)species_count(d);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -92,11 +95,11 @@ Layout make_layout(const karl_job_desc* d) {
     L.zf = take(rs * (nz + 1));
     L.rf = take(rs * (nr + 1));
     L.zcdf = take(rs * (nz + 1));
-    L.tfield = take(uses_fields(d) ? 8 * 2 * nr * nz : 0);
-    L.edges = take(8 * 2 * ((size_t)d->n_bins + 1));
+    L.tfield = take(uses_fields(d) ? 8 * ns * nr * nz : 0);
+    L.edges = take(8 * ns * ((size_t)d->n_bins + 1));
     L.plane_of = take(4 * (nz + 1));
     L.angles = take(8 * angle_doubles(d));
-    L.dens_edges = take(d->n_dens_bins > 0 ? 8 * 2 * ((size_t)d->n_dens_bins + 1) : 0);
+    L.dens_edges = take(d->n_dens_bins > 0 ? 8 * ns * ((size_t)d->n_dens_bins + 1) : 0);
     // tallies: one contiguous block so that a snapshot is one copy
     size_t t = 0;
     auto tk = [&](size_t bytes) {
@@ -107,19 +110,19 @@ Layout make_layout(const karl_job_desc* d) {
     const size_t np = (size_t)d->n_primaries;
     L.t_counters = tk(8 * KARL_NCOUNTERS);
     L.t_ledger = tk(8 * KARL_NLEDGER);
-    L.t_dens = tk(8 * 2 * nr * nz);
-    L.t_recomb = tk(8 * 2 * nr * nz);
-    L.t_jz = tk(8 * 2 * nr * (nz + 1) * 2);
-    L.t_jr = tk(8 * 2 * (nr + 1) * nz * 2);
-    L.t_spectra = tk(8 * 2 * (size_t)d->n_planes * 2 * ((size_t)d->n_bins + 2));
+    L.t_dens = tk(8 * ns * nr * nz);
+    L.t_recomb = tk(8 * ns * nr * nz);
+    L.t_jz = tk(8 * ns * nr * (nz + 1) * 2);
+    L.t_jr = tk(8 * ns * (nr + 1) * nz * 2);
+    L.t_spectra = tk(8 * ns * (size_t)d->n_planes * 2 * ((size_t)d->n_bins + 2));
     L.t_digests = tk((d->flags & KARL_FLAG_DIGESTS) ? 8 * np : 0);
     L.t_hist = tk((d->flags & KARL_FLAG_HISTORY) ? 8 * KARL_NHIST * np : 0);
-    L.t_dense = tk(d->n_dens_bins > 0 ? 8 * 2 * nr * nz * ((size_t)d->n_dens_bins + 2) : 0);
+    L.t_dense = tk(d->n_dens_bins > 0 ? 8 * ns * nr * nz * ((size_t)d->n_dens_bins + 2) : 0);
     L.tally_bytes = t;
     L.tallies = take(t);
     L.snapshot = take(t);
     L.control = take(kControlBytes);
-    L.fields = take(8 * (2 * nr * nz + 2 * nr * (nz + 1) + 2 * (nr + 1) * nz));
+    L.fields = take(8 * (ns * nr * nz + ns * nr * (nz + 1) + ns * (nr + 1) * nz));
     L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
     L.queues = take(4 * L.queue_entries * kQueueEntryBytes);
     L.total = off;
@@ -135,6 +138,9 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     if (d->n_r < 1 || d->n_r > 2047 || d->n_z < 1 || d->n_z >= (1 << 19))
         return fail(KARL_EINVAL, "grid must have 1 <= n_r <= 2047 and 1 <= n_z < 2^19");
     if (d->n_e < 2 || d->n_e > 1024) return fail(KARL_EINVAL, "n_e must be in 2..1024");
+    if (d->n_species != 0 && (d->n_species < 2 || d->n_species > KARL_MAX_SPECIES))
+        return fail(KARL_EINVAL, "n_species must be in 2..%d (0: 2)", KARL_MAX_SPECIES);
+    const int ns = species_count(d);
     if (d->n_proc < 0 || d->n_proc > KARL_MAX_PROC)
         return fail(KARL_EINVAL, "n_proc must be in 0..%d", KARL_MAX_PROC);
     if (d->n_bins < 1 || d->n_bins > (1 << 20)) return fail(KARL_EINVAL, "n_bins must be in 1..2^20");
@@ -147,17 +153,17 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     for (int k = 0; k < d->n_z; ++k)
         if (!std::isfinite(d->n_gas[k]) || d->n_gas[k] < 0.0)
             return fail(KARL_EINVAL, "n_gas[%d] must be finite and >= 0", k);
-    for (int f = 0; f < 2; ++f) {
-        const double* fld = f ? d->n_elec : d->n_ion;
+    for (int f = 0; f < ns; ++f) {
+        const double* fld = d->n_field[f];
         if (fld)
             for (int k = 0; k < d->n_r * d->n_z; ++k)
                 if (!std::isfinite(fld[k]) || fld[k] < 0.0)
-                    return fail(KARL_EINVAL, "%s[%d] must be finite and >= 0", f ? "n_elec" : "n_ion", k);
+                    return fail(KARL_EINVAL, "n_field[%d][%d] must be finite and >= 0", f, k);
     }
     if (!std::isfinite(d->t_gas) || d->t_gas < 0.0) return fail(KARL_EINVAL, "t_gas must be >= 0");
     if (!finite_pos(d->m_gas)) return fail(KARL_EINVAL, "m_gas must be positive");
     if (!std::isfinite(d->bz)) return fail(KARL_EINVAL, "bz must be finite");
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < ns; ++s) {
         const karl_species_desc& sp = d->species[s];
         if (!finite_pos(sp.mass)) return fail(KARL_EINVAL, "species %d: mass must be positive", s);
         if (!std::isfinite(sp.charge) || (d->bz != 0.0 && sp.charge == 0.0))
@@ -171,13 +177,30 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
             if (!(sp.edges[b] < sp.edges[b + 1]))
                 return fail(KARL_EINVAL, "species %d: edges must increase", s);
     }
+    int partner_of[KARL_MAX_SPECIES] = {-1, -1, -1, -1};
     for (int i = 0; i < d->n_proc; ++i) {
         const karl_process_desc& p = d->proc[i];
-        if (p.kind < KARL_ELASTIC || p.kind > KARL_RECOMBINATION)
+        if (p.kind < KARL_ELASTIC || p.kind > KARL_CLUSTERING)
             return fail(KARL_EINVAL, "process %d: unknown kind %d", i, p.kind);
-        if (p.species < 0 || p.species > 1) return fail(KARL_EINVAL, "process %d: species", i);
+        if (p.species < 0 || p.species >= ns) return fail(KARL_EINVAL, "process %d: species", i);
         if (p.target != KARL_TARGET_GAS && p.target != KARL_TARGET_FIELD)
             return fail(KARL_EINVAL, "process %d: target", i);
+        if (p.kind == KARL_IONIZATION && (p.product < 1 || p.product >= ns))
+            return fail(KARL_EINVAL, "process %d: ionization product must be an ion species 1..%d", i, ns - 1);
+        if (p.kind == KARL_CLUSTERING && (p.product < 0 || p.product >= ns || p.product == p.species))
+            return fail(KARL_EINVAL, "process %d: clustering product must be another species", i);
+        if (p.density_power < 0 || p.density_power > 2)
+            return fail(KARL_EINVAL, "process %d: density_power must be 0, 1 or 2", i);
+        if (p.density_power == 2 && p.target != KARL_TARGET_GAS)
+            return fail(KARL_EINVAL, "process %d: density_power 2 needs a gas target", i);
+        if ((p.target == KARL_TARGET_FIELD || p.kind == KARL_RECOMBINATION) && (p.partner < 0 || p.partner >= ns))
+            return fail(KARL_EINVAL, "process %d: partner species", i);
+        if (p.target == KARL_TARGET_FIELD) {
+            if (partner_of[p.species] >= 0 && partner_of[p.species] != p.partner)
+                return fail(KARL_EINVAL, "process %d: all field processes of species %d must share one partner",
+                            i, p.species);
+            partner_of[p.species] = p.partner;
+        }
         if (!p.xs) return fail(KARL_EINVAL, "process %d: table missing", i);
         if (!std::isfinite(p.e_th) || p.e_th < 0.0) return fail(KARL_EINVAL, "process %d: e_th", i);
         if (p.kind == KARL_IONIZATION && !(p.e_th > 0.0))
@@ -212,7 +235,7 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
         if (!finite_pos(d->beta_e0) || !finite_pos(d->beta_fmax) || !std::isfinite(d->beta_z))
             return fail(KARL_EINVAL, "beta source needs e0 > 0 and f_max > 0");
     } else if (d->source == KARL_SOURCE_BEAM || d->source == KARL_SOURCE_PAIR) {
-        if (d->beam_species < 0 || d->beam_species > 1 || !std::isfinite(d->beam_energy) ||
+        if (d->beam_species < 0 || d->beam_species >= ns || !std::isfinite(d->beam_energy) ||
             d->beam_energy < 0.0)
             return fail(KARL_EINVAL, "beam needs a species slot and an energy >= 0");
         if (d->source == KARL_SOURCE_PAIR && (!std::isfinite(d->beam_energy_1) || d->beam_energy_1 < 0.0))
@@ -229,7 +252,7 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     if (d->n_dens_bins < 0 || d->n_dens_bins > 4096)
         return fail(KARL_EINVAL, "n_dens_bins must be in 0..4096");
     if (d->n_dens_bins > 0)
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < ns; ++s) {
             const double* e = d->species[s].dens_edges;
             if (!e) return fail(KARL_EINVAL, "species %d: density energy edges missing", s);
             for (int b = 0; b < d->n_dens_bins; ++b)
@@ -554,13 +577,17 @@ karl_status upload_real(const Job& j, size_t off, const std::vector<double>& v) 
     return KARL_OK;
 }
 
-// flight segments and interactions (both species) counted so far
+// flight segments and interactions (all species) counted so far
 karl_status read_steps(Job* j, hipStream_t s, int64_t* segs, int64_t* ints) {
-    unsigned long long c[4] = {0ull, 0ull, 0ull, 0ull};
+    static_assert(KARL_C_COLL == KARL_C_STEP + KARL_MAX_SPECIES, "counter layout");
+    unsigned long long c[2 * KARL_MAX_SPECIES] = {};
     HIP_CHECK(hipMemcpyAsync(c, j->dj.counters + KARL_C_STEP, sizeof(c), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    *segs = (int64_t)(c[0] + c[1]);
-    *ints = (int64_t)(c[2] + c[3]);
+    *segs = *ints = 0;
+    for (int k = 0; k < KARL_MAX_SPECIES; ++k) {
+        *segs += (int64_t)c[k];
+        *ints += (int64_t)c[KARL_MAX_SPECIES + k];
+    }
     return KARL_OK;
 }
 
@@ -685,17 +712,23 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
 
     // ---- host-side tables
     const int nz = d->n_z, nr = d->n_r;
+    const int ns = species_count(d);
+    // three-body tables (k/v, m^5, ~1e-44) are stored scaled by 2^100 in FP32, whose smallest
+    // normal number is 1.2e-38; the kernel multiplies the rate by 2^-100 again
+    const double p2scale = d->precision == KARL_FP32 ? std::ldexp(1.0, -100) : 1.0;
     std::vector<double> xs((size_t)d->n_proc * d->n_e);
-    for (int i = 0; i < d->n_proc; ++i)
-        std::memcpy(&xs[(size_t)i * d->n_e], d->proc[i].xs, sizeof(double) * (size_t)d->n_e);
+    for (int i = 0; i < d->n_proc; ++i) {
+        const double sc = d->proc[i].density_power == 2 ? 1.0 / p2scale : 1.0;
+        for (int k = 0; k < d->n_e; ++k) xs[(size_t)i * d->n_e + k] = d->proc[i].xs[k] * sc;
+    }
     std::vector<double> ngas(d->n_gas, d->n_gas + nz);
     std::vector<double> zf(nz + 1), rf(nr + 1), zcdf(nz + 1);
     for (int k = 0; k <= nz; ++k) zf[k] = d->length * (double)k / (double)nz;
     for (int k = 0; k <= nr; ++k) rf[k] = d->radius * (double)k / (double)nr;
     zcdf[0] = 0.0;
     for (int k = 0; k < nz; ++k) zcdf[k + 1] = zcdf[k] + d->n_gas[k];
-    std::vector<double> edges(2 * ((size_t)d->n_bins + 1));
-    for (int s = 0; s < 2; ++s)
+    std::vector<double> edges((size_t)ns * ((size_t)d->n_bins + 1));
+    for (int s = 0; s < ns; ++s)
         std::memcpy(&edges[(size_t)s * (d->n_bins + 1)], d->species[s].edges,
                     sizeof(double) * ((size_t)d->n_bins + 1));
     std::vector<int32_t> plane_of(nz + 1, -1);
@@ -708,19 +741,18 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     TRY(upload_real(*j, L.rf, rf));
     TRY(upload_real(*j, L.zcdf, zcdf));
     if (uses_fields(d)) {
-        // field[0] electrons (target of ions), field[1] ions (target of electrons); absent: 0
-        TRY_HIP(karl::launch_fill_u64((unsigned long long*)(j->ws + L.tfield), (size_t)2 * nr * nz, 0ull, nullptr));
-        if (d->n_elec)
-            TRY_HIP(hipMemcpy(j->ws + L.tfield, d->n_elec, sizeof(double) * (size_t)nr * nz, hipMemcpyHostToDevice));
-        if (d->n_ion)
-            TRY_HIP(hipMemcpy(j->ws + L.tfield + 8 * (size_t)nr * nz, d->n_ion, sizeof(double) * (size_t)nr * nz,
-                              hipMemcpyHostToDevice));
+        // one density field per species; absent: 0
+        TRY_HIP(karl::launch_fill_u64((unsigned long long*)(j->ws + L.tfield), (size_t)ns * nr * nz, 0ull, nullptr));
+        for (int f = 0; f < ns; ++f)
+            if (d->n_field[f])
+                TRY_HIP(hipMemcpy(j->ws + L.tfield + 8 * (size_t)f * nr * nz, d->n_field[f],
+                                  sizeof(double) * (size_t)nr * nz, hipMemcpyHostToDevice));
     }
     TRY_HIP(hipMemcpy(j->ws + L.edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice));
     TRY_HIP(hipMemcpy(j->ws + L.plane_of, plane_of.data(), sizeof(int32_t) * plane_of.size(), hipMemcpyHostToDevice));
     if (d->n_dens_bins > 0) {
-        std::vector<double> de(2 * ((size_t)d->n_dens_bins + 1));
-        for (int s = 0; s < 2; ++s)
+        std::vector<double> de((size_t)ns * ((size_t)d->n_dens_bins + 1));
+        for (int s = 0; s < ns; ++s)
             std::memcpy(&de[(size_t)s * (d->n_dens_bins + 1)], d->species[s].dens_edges,
                         sizeof(double) * ((size_t)d->n_dens_bins + 1));
         TRY_HIP(hipMemcpy(j->ws + L.dens_edges, de.data(), sizeof(double) * de.size(), hipMemcpyHostToDevice));
@@ -769,8 +801,21 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.beam_species = d->beam_species;
     J.flags = (int32_t)d->flags;
     J.seed = d->seed;
-    J.reserved0 = 0;
-    for (int s = 0; s < 2; ++s) {
+    J.n_species = ns;
+    for (int s = 0; s < karl::kS; ++s) {
+        J.nps[s] = 0;
+        J.field_of[s] = -1;
+        J.defer[s] = 0;
+        J.field[s] = nullptr;
+        if (s >= ns) {
+            // unused slots: harmless values (never selected by a particle)
+            J.tracked[s] = 0;
+            J.cap[s] = 1;
+            J.mass[s] = J.charge[s] = J.e_cut[s] = J.lifetime[s] = J.msum[s] = 0.0;
+            J.xs_emin[s] = J.inv_dlog[s] = J.omega[s] = J.mfrac[s] = J.gfrac[s] = 0.0;
+            J.inv_emin[s] = J.inv_om[s] = J.e_from_v2[s] = J.v2_from_e[s] = 0.0;
+            continue;
+        }
         const karl_species_desc& sp = d->species[s];
         J.tracked[s] = sp.tracked ? 1 : 0;
         J.cap[s] = sp.cap;
@@ -789,9 +834,6 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.inv_om[s] = (J.omega[s] != 0.0) ? 1.0 / J.omega[s] : 0.0;
         J.e_from_v2[s] = 0.5 * sp.mass / kQE;
         J.v2_from_e[s] = 2.0 * kQE / sp.mass;
-        J.nps[s] = 0;
-        J.uses_field[s] = 0;
-        J.defer[s] = 0;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
         const bool has_ang = i < d->n_proc && d->proc[i].ang_bins > 0;
@@ -799,24 +841,33 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.ang_nb[i] = has_ang ? d->proc[i].ang_bins : 0;
         J.ang_n[i] = has_ang ? d->proc[i].ang_nodes : 0;
         J.e_iso[i] = has_ang ? d->proc[i].e_iso : 0.0;
-        J.kind[i] = i < d->n_proc ? d->proc[i].kind : 0;
-        J.target[i] = i < d->n_proc ? d->proc[i].target : 0;
-        J.e_th[i] = i < d->n_proc ? d->proc[i].e_th : 0.0;
+        const karl_process_desc* pr = i < d->n_proc ? &d->proc[i] : nullptr;
+        J.kind[i] = pr ? pr->kind : 0;
+        J.target[i] = !pr ? karl::TGT_GAS
+                          : pr->target == KARL_TARGET_FIELD ? karl::TGT_FIELD
+                          : pr->density_power == 2 ? karl::TGT_GAS2 : karl::TGT_GAS;
+        J.product[i] = pr && (pr->kind == KARL_IONIZATION || pr->kind == KARL_CLUSTERING) ? pr->product : 0;
+        J.partner[i] = pr && (pr->target == KARL_TARGET_FIELD || pr->kind == KARL_RECOMBINATION) ? pr->partner : 0;
+        J.conv[i] = pr && pr->kind == KARL_CLUSTERING ? d->m_gas / d->species[pr->product].mass : 0.0;
+        J.e_th[i] = pr ? pr->e_th : 0.0;
         J.e_th_f[i] = (float)J.e_th[i];
     }
     for (int i = 0; i < d->n_proc; ++i) {
         const int s = d->proc[i].species;
         J.pidx[s][J.nps[s]++] = i;
-        if (d->proc[i].target == KARL_TARGET_FIELD) J.uses_field[s] = 1;
+        if (d->proc[i].target == KARL_TARGET_FIELD) J.field_of[s] = d->proc[i].partner;
     }
-    // A species without ionization never produces secondaries: its particles can wait in the
-    // deferred queue and run together in one launch after the other generations.
-    for (int s = 0; s < 2; ++s) {
-        bool ionizes = false;
+    // A species without ionization or clustering never produces particles: its particles can
+    // wait in the deferred queue and run together in one launch after the other generations.
+    for (int s = 0; s < ns; ++s) {
+        bool produces = false;
         for (int i = 0; i < d->n_proc; ++i)
-            if (d->proc[i].species == s && d->proc[i].kind == KARL_IONIZATION) ionizes = true;
-        J.defer[s] = ionizes ? 0 : 1;
+            if (d->proc[i].species == s &&
+                (d->proc[i].kind == KARL_IONIZATION || d->proc[i].kind == KARL_CLUSTERING))
+                produces = true;
+        J.defer[s] = produces ? 0 : 1;
     }
+    J.p2scale = p2scale;
     J.sigma_v = std::sqrt(kKB * d->t_gas / d->m_gas);
     J.m_gas = d->m_gas;
     J.beta_e0 = d->beta_e0;
@@ -836,8 +887,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.zf = w + L.zf;
     J.rf = w + L.rf;
     J.zcdf = w + L.zcdf;
-    J.field[0] = uses_fields(d) ? (double*)(w + L.tfield) : nullptr;
-    J.field[1] = uses_fields(d) ? (double*)(w + L.tfield + 8 * (size_t)nr * nz) : nullptr;
+    for (int f = 0; f < ns; ++f)
+        J.field[f] = uses_fields(d) ? (double*)(w + L.tfield + 8 * (size_t)f * nr * nz) : nullptr;
     J.edges = (const double*)(w + L.edges);
     J.plane_of = (const int32_t*)(w + L.plane_of);
     char* t = w + L.tallies;
@@ -896,7 +947,7 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(hipStreamSynchronize(s));
     const karl::DevJob& J = j->dj;
-    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z;
+    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z, ns = (size_t)J.n_species;
     auto get = [&](void* dst, const void* src, size_t bytes) -> karl_status {
         if (dst && src && bytes) HIP_CHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
         return KARL_OK;
@@ -904,11 +955,11 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     karl_status st;
     if ((st = get(out->counters, J.counters, 8 * KARL_NCOUNTERS)) != KARL_OK) return st;
     if ((st = get(out->ledger, J.ledger, 8 * KARL_NLEDGER)) != KARL_OK) return st;
-    if ((st = get(out->density_time, J.dens, 8 * 2 * nr * nz)) != KARL_OK) return st;
-    if ((st = get(out->recomb, J.recomb, 8 * 2 * nr * nz)) != KARL_OK) return st;
-    if ((st = get(out->jz, J.jz, 8 * 2 * nr * (nz + 1) * 2)) != KARL_OK) return st;
-    if ((st = get(out->jr, J.jr, 8 * 2 * (nr + 1) * nz * 2)) != KARL_OK) return st;
-    if ((st = get(out->spectra, J.spectra, 8 * 2 * (size_t)j->n_planes * 2 * ((size_t)j->n_bins + 2))) != KARL_OK)
+    if ((st = get(out->density_time, J.dens, 8 * ns * nr * nz)) != KARL_OK) return st;
+    if ((st = get(out->recomb, J.recomb, 8 * ns * nr * nz)) != KARL_OK) return st;
+    if ((st = get(out->jz, J.jz, 8 * ns * nr * (nz + 1) * 2)) != KARL_OK) return st;
+    if ((st = get(out->jr, J.jr, 8 * ns * (nr + 1) * nz * 2)) != KARL_OK) return st;
+    if ((st = get(out->spectra, J.spectra, 8 * ns * (size_t)j->n_planes * 2 * ((size_t)j->n_bins + 2))) != KARL_OK)
         return st;
     if (out->digests) {
         if (!J.digests) return fail(KARL_EINVAL, "digests requested but KARL_FLAG_DIGESTS not set");
@@ -916,7 +967,7 @@ karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
     }
     if (out->density_time_e) {
         if (!J.dense) return fail(KARL_EINVAL, "energy-resolved density requested but n_dens_bins is 0");
-        if ((st = get(out->density_time_e, J.dense, 8 * 2 * nr * nz * ((size_t)J.n_dens_bins + 2))) != KARL_OK)
+        if ((st = get(out->density_time_e, J.dense, 8 * ns * nr * nz * ((size_t)J.n_dens_bins + 2))) != KARL_OK)
             return st;
     }
     if (out->hist) {
@@ -939,8 +990,8 @@ karl_status karl_read_fields(void* job, double activity, double* density, double
     if (j->n_transported <= 0) return fail(KARL_ESTATE, "no primaries transported since the last reset");
     HIP_CHECK(hipSetDevice(j->device));
     hipStream_t s = (hipStream_t)hip_stream;
-    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z;
-    const size_t n_dens = 2 * nr * nz, n_jz = 2 * nr * (nz + 1), n_jr = 2 * (nr + 1) * nz;
+    const size_t nr = (size_t)j->n_r, nz = (size_t)j->n_z, ns = (size_t)j->dj.n_species;
+    const size_t n_dens = ns * nr * nz, n_jz = ns * nr * (nz + 1), n_jr = ns * (nr + 1) * nz;
     double* f = (double*)(j->ws + j->lay.fields);
     const double t_sim = (double)j->n_transported / activity;
     HIP_CHECK(karl::launch_fields(j->dj, t_sim, f, f + n_dens, f + n_dens + n_jz, s));

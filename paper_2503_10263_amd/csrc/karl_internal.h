@@ -20,9 +20,15 @@ struct QueueSoA {
     double* e;
     unsigned long long* lin;   // lineage
     uint32_t* pid;             // primary id
-    uint32_t* meta;            // species | r-cell << 2 | z-cell << 13
+    uint32_t* meta;            // species (0..3) | r-cell << 2 | z-cell << 13
     uint32_t* job;             // index into the launch's job table
 };
+
+// Target codes of the device process table: the gas (rate n sigma), a density field (rate
+// n_field sigma) and the gas squared (three-body: rate n (n sigma)).
+enum : int32_t { TGT_GAS = 0, TGT_FIELD = 1, TGT_GAS2 = 2 };
+
+constexpr int kS = KARL_MAX_SPECIES;
 
 // Everything the transport kernel needs about one job, passed by value.
 struct DevJob {
@@ -30,29 +36,33 @@ struct DevJob {
     int32_t n_r, n_z, n_e, n_proc, n_bins, n_planes;
     int32_t gc, source, beam_species, flags;
     uint32_t seed;
-    int32_t beam_ir, beam_iz, reserved0;
-    int32_t nps[2];
-    int32_t uses_field[2];       // a process of the species targets the other species' field
-    int32_t defer[2];            // products of this species go to the deferred queue
-    int32_t tracked[2];
-    int64_t cap[2];
-    double mass[2], charge[2], e_cut[2], lifetime[2];
-    double msum[2];        // mass + m_gas
-    double xs_emin[2], inv_dlog[2];
-    double omega[2];       // charge * bz / mass
-    double mfrac[2];       // mass / (mass + m_gas)
-    double gfrac[2];       // m_gas / (mass + m_gas), also E_xs / E
-    double inv_emin[2];    // 1 / xs_emin
-    double inv_om[2];      // 1 / omega (0 without field)
-    double e_from_v2[2];   // E(eV) = v^2 * e_from_v2
-    double v2_from_e[2];   // v^2 = E(eV) * v2_from_e
+    int32_t beam_ir, beam_iz, n_species;
+    int32_t nps[kS];
+    int32_t field_of[kS];        // species whose density field this species' field processes see, or -1
+    int32_t defer[kS];           // particles of this species make no products: queued for the drain
+    int32_t tracked[kS];
+    int64_t cap[kS];
+    double mass[kS], charge[kS], e_cut[kS], lifetime[kS];
+    double msum[kS];       // mass + m_gas
+    double xs_emin[kS], inv_dlog[kS];
+    double omega[kS];      // charge * bz / mass
+    double mfrac[kS];      // mass / (mass + m_gas)
+    double gfrac[kS];      // m_gas / (mass + m_gas), also E_xs / E
+    double inv_emin[kS];   // 1 / xs_emin
+    double inv_om[kS];     // 1 / omega (0 without field)
+    double e_from_v2[kS];  // E(eV) = v^2 * e_from_v2
+    double v2_from_e[kS];  // v^2 = E(eV) * v2_from_e
     double sigma_v;        // sqrt(k T / m_gas)
     double m_gas;
+    double p2scale;        // TGT_GAS2 tables are stored divided by this (FP32 range), rate times it
     double beta_e0, beta_z, beta_fmax;
     double beam_e, beam_e1, beam_pos[3], beam_dir[3];
-    int32_t pidx[2][KARL_MAX_PROC];   // global process index of the j-th process of a species
+    int32_t pidx[kS][KARL_MAX_PROC];  // global process index of the j-th process of a species
     int32_t kind[KARL_MAX_PROC];
-    int32_t target[KARL_MAX_PROC];
+    int32_t target[KARL_MAX_PROC];    // TGT_*
+    int32_t product[KARL_MAX_PROC];   // ionization / clustering product species
+    int32_t partner[KARL_MAX_PROC];   // field targets: species of the field
+    double conv[KARL_MAX_PROC];       // clustering: m_gas / m_product
     double e_th[KARL_MAX_PROC];
     float e_th_f[KARL_MAX_PROC];
     // elastic angle tables: per process edges [nb+1], theta [n], cdf [nb][n], pdf [nb][n]
@@ -65,10 +75,10 @@ struct DevJob {
     const void* zf;        // [n_z+1] z faces
     const void* rf;        // [n_r+1] r faces
     const void* zcdf;      // [n_z+1] cumulative gas weights
-    double* field[2];      // [n_r*n_z] density field of each species (m^-3), or NULL
-    const double* edges;   // [2][n_bins+1]
+    double* field[kS];     // [n_r*n_z] density field of each species (m^-3), or NULL
+    const double* edges;   // [n_species][n_bins+1]
     const int32_t* plane_of;   // [n_z+1] plane index or -1
-    const double* dens_edges;  // [2][n_dens_bins+1] or NULL
+    const double* dens_edges;  // [n_species][n_dens_bins+1] or NULL
     int32_t n_dens_bins, reserved1;
     // tallies
     unsigned long long* counters;
@@ -80,7 +90,7 @@ struct DevJob {
     unsigned long long* spectra;
     unsigned long long* digests;
     double* hist;
-    double* dense;         // [2][n_r][n_z][n_dens_bins+2] or NULL
+    double* dense;         // [n_species][n_r][n_z][n_dens_bins+2] or NULL
     unsigned int* status;
 };
 

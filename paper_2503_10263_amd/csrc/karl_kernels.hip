@@ -273,11 +273,11 @@ struct Part {
 
 template <typename Real>
 struct Lds {
-    unsigned long long* cnt;   // [48]
-    double* led;               // [24]
-    const int32_t* pidx;       // [2][16]
+    unsigned long long* cnt;   // [KARL_NCOUNTERS]
+    double* led;               // [KARL_NLEDGER]
+    const int32_t* pidx;       // [4][16]
     const int32_t* kind;       // [16]
-    const int32_t* tgt;        // [16]
+    const int32_t* tgt;        // [16] TGT_*
     const Real* eth;           // [16]
     const Real* xs;            // [n_proc][n_e]
     const Real* ngas;          // [n_z]
@@ -293,12 +293,17 @@ struct LaneCnt {
     double e_prim;
 };
 
-// Count one event of kind idx + sp: in a per-lane register, or -- when the lane's counters are
-// not kept per lane -- with one LDS atomic per distinct key of the wave.
+// Count one event of kind idx + sp: in a per-lane register (species 0 and 1), with one atomic
+// per lane (species 2 and 3), or -- when the lane's counters are not kept per lane -- with one
+// atomic per distinct key of the wave.
 template <typename Real>
 __device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int idx, int sp) {
     if (L.direct) {
         wave_count(L.cnt, idx + sp);
+        return;
+    }
+    if (sp > 1) {
+        atomicAdd(&L.cnt[idx + sp], 1ull);
         return;
     }
     switch (idx) {
@@ -311,7 +316,7 @@ __device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int id
 
 template <typename Real>
 __device__ __forceinline__ void count_evn(const Lds<Real>& L, LaneCnt& lc, int idx, int sp, uint32_t n) {
-    if (L.direct) {
+    if (L.direct || sp > 1) {
         atomicAdd(&L.cnt[idx + sp], (unsigned long long)n);
         return;
     }
@@ -345,8 +350,19 @@ __device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt,
     lc = LaneCnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
 }
 
+// Entry sp (0..3) of a per-species array of the job, chosen by selects: a species index that
+// differs between lanes stays in registers instead of becoming an indexed load.  A vector
+// select reads at most one scalar register, so the compiler copies job constants to vector
+// registers and would hoist those copies out of the persistent loop, one per slot; the empty
+// asm keeps slots 2 and 3 (used by chemistry jobs only) scalar until the select.
 template <typename T>
-__device__ __forceinline__ T sel2(int sp, T a, T b) { return sp ? b : a; }
+__device__ __forceinline__ T spv(const T (&a)[kS], int sp) {
+    T a2 = a[2], a3 = a[3];
+    asm volatile("" : "+s"(a2), "+s"(a3));
+    const T lo = (sp & 1) ? a[1] : a[0];
+    const T hi = (sp & 1) ? a3 : a2;
+    return (sp & 2) ? hi : lo;
+}
 
 // ---------------------------------------------------------------- tally helpers
 template <typename Real>
@@ -406,7 +422,7 @@ __device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess
 template <typename Real>
 __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
                        Real yp, bool at_birth) {
-    const Real iom = (Real)sel2(p.sp, J.inv_om[0], J.inv_om[1]);
+    const Real iom = (Real)spv(J.inv_om, p.sp);
     const Real gx = xp + (p.vel * p.v) * iom;
     const Real gy = yp - (p.vel * p.u) * iom;
     const Real rho = ksqrt(gx * gx + gy * gy);
@@ -427,6 +443,32 @@ __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneC
         p.ir = nir;
     }
     return rho + rl >= (Real)J.radius;
+}
+
+// Rate (m^-1) of process i at interpolation position (k, f) of the energy (eq. 1): the table
+// linear over ln E, zero below the threshold, times the target density -- the gas, the partner
+// species' field, or the gas twice for three-body reactions, n (n sigma), whose FP32 tables
+// are stored divided by p2scale to stay in range.
+template <typename Real>
+__device__ __forceinline__ Real proc_rate(const DevJob& J, const Lds<Real>& L, int i, Real exs, int k,
+                                         Real f, Real n_gas, Real n_fld) {
+    Real sig = (Real)0;
+    if (!(exs < L.eth[i])) {
+        const Real* tb = L.xs + (size_t)i * J.n_e;
+        sig = tb[k] + f * (tb[k + 1] - tb[k]);
+    }
+    const int t = L.tgt[i];
+    if (t == TGT_GAS) return n_gas * sig;
+    if (t == TGT_FIELD) return n_fld * sig;
+    return (n_gas * (n_gas * sig)) * (Real)J.p2scale;
+}
+
+// density of the field that species sp's field processes target, in cell (ir, iz)
+template <typename Real>
+__device__ __forceinline__ Real field_density(const DevJob& J, int sp, int ir, int iz) {
+    const int fo = spv(J.field_of, sp);
+    if (fo < 0) return (Real)0;
+    return (Real)spv(J.field, fo)[(size_t)ir * J.n_z + (size_t)iz];
 }
 
 // ---------------------------------------------------------------- kinematics
@@ -538,12 +580,12 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
         gh[2] = g[2] * ig;
     }
     // centre-of-mass velocity (m v + M V)/(m + M)
-    const Real mf = (Real)sel2(s, J.mfrac[0], J.mfrac[1]);
-    const Real gf = (Real)sel2(s, J.gfrac[0], J.gfrac[1]);
+    const Real mf = (Real)spv(J.mfrac, s);
+    const Real gf = (Real)spv(J.gfrac, s);
     const Real cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
     // the impact energy in the centre-of-mass frame selects the angle distribution
-    const Real ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * (Real)sel2(s, J.e_from_v2[0], J.e_from_v2[1]) * gf;
+    const Real ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * (Real)spv(J.e_from_v2, s) * gf;
     const Real mu = scatter_mu(J, pi, ecm, q.d0);
     const Real phi = (Real)kTWO_PI * q.d1;
     Real gn[3];
@@ -551,7 +593,7 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
     const Real a = gf * gm;
     const Real vn[3] = {cm[0] + a * gn[0], cm[1] + a * gn[1], cm[2] + a * gn[2]};
     const Real e0 = p.e;
-    set_velocity(p, (Real)sel2(s, J.e_from_v2[0], J.e_from_v2[1]), vn);
+    set_velocity(p, (Real)spv(J.e_from_v2, s), vn);
     p.e_gas += (double)(e0 - p.e);
 }
 
@@ -625,6 +667,18 @@ __device__ __forceinline__ uint32_t pack_meta(int sp, int ir, int iz) {
     return (uint32_t)sp | ((uint32_t)ir << 2) | ((uint32_t)iz << 13);
 }
 
+// Queue slot of a product of species q for the lanes with `want`: the deferred queue for
+// species that make no products of their own, else the next generation's.  Both reservations
+// are wave-wide, so lanes may differ in q.
+__device__ __forceinline__ unsigned long long reserve_product(const DevJob& J, const GenArgs& G, int q,
+                                                              bool want, bool* deferred) {
+    const bool dq = spv(J.defer, q) != 0;
+    const unsigned long long sd = wave_reserve(G.qdef_count, want && dq);
+    const unsigned long long so = wave_reserve(G.qout_count, want && !dq);
+    *deferred = dq;
+    return dq ? sd : so;
+}
+
 // A product that is never transported (untracked species, or born below the cutoff) is
 // counted, logged and deleted at once, exactly as its birth would do.
 template <typename Real>
@@ -649,8 +703,8 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
 template <typename Real>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                              int pi, Real xc, Real yc, LaneCnt& lc) {
-    const Real ef2 = (Real)sel2(p.sp, J.e_from_v2[0], J.e_from_v2[1]);
-    const Real v2e = (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1]);
+    const Real ef2 = (Real)spv(J.e_from_v2, p.sp);
+    const Real v2e = (Real)spv(J.v2_from_e, p.sp);
     const Real B = L.eth[pi];
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     Real V[3], g[3];
@@ -706,13 +760,14 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     const Real vf[3] = {V[0] + sf * df[0], V[1] + sf * df[1], V[2] + sf * df[2]};
     const Real vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
     const Real es = (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) * ef2;
-    const Real eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * (Real)J.e_from_v2[1];
+    const int qi = J.product[pi];   // the ion species made (molecular, or atomic if dissociative)
+    const Real eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * (Real)spv(J.e_from_v2, qi);
     const Real e0 = p.e;
     set_velocity(p, ef2, vf);
     p.e_bind += (double)B;
     p.e_gas += (double)(e0 - (p.e + es + eion + B));
 
-    // products: slow electron (slot 0) and ion (slot 1), born at the collision point
+    // products: slow electron (slot 0) and ion (slot qi), born at the collision point
     const unsigned long long lin_e = child_lineage(p.lin, p.s, 0u);
     const unsigned long long lin_i = child_lineage(p.lin, p.s, 1u);
     Real de[3] = {(Real)0, (Real)0, (Real)1};
@@ -739,27 +794,83 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
         product_inline(J, L, 0, es, lin_e, p.pid, p.ir, p.iz, KARL_CUTOFF);
         push_e = false;
     }
-    if (!J.tracked[1]) {
-        product_inline(J, L, 1, eion, lin_i, p.pid, p.ir, p.iz, KARL_UNTRACKED);
+    if (!spv(J.tracked, qi)) {
+        product_inline(J, L, qi, eion, lin_i, p.pid, p.ir, p.iz, KARL_UNTRACKED);
         push_i = false;
-    } else if (eion < (Real)J.e_cut[1]) {
-        product_inline(J, L, 1, eion, lin_i, p.pid, p.ir, p.iz, KARL_CUTOFF);
+    } else if (eion < (Real)spv(J.e_cut, qi)) {
+        product_inline(J, L, qi, eion, lin_i, p.pid, p.ir, p.iz, KARL_CUTOFF);
         push_i = false;
     }
-    // destination queues are uniform per product slot: next generation or deferred
+    // the electron's destination is uniform (slot 0); the ion's follows its species
     const QueueSoA& qe = J.defer[0] ? G.qdef : G.qout;
-    const QueueSoA& qi = J.defer[1] ? G.qdef : G.qout;
     const unsigned long long se = wave_reserve(J.defer[0] ? G.qdef_count : G.qout_count, push_e);
-    const unsigned long long si = wave_reserve(J.defer[1] ? G.qdef_count : G.qout_count, push_i);
+    bool di_def;
+    const unsigned long long si = reserve_product(J, G, qi, push_i, &di_def);
     const unsigned long long cap = (unsigned long long)G.capacity;
     if (push_e) {
         if (se < cap) queue_write(qe, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz), (uint32_t)p.job);
         else atomicOr(G.status, STATUS_OVERFLOW);
     }
     if (push_i) {
-        if (si < cap) queue_write(qi, si, xc, yc, p.z, di, eion, lin_i, p.pid, pack_meta(1, p.ir, p.iz), (uint32_t)p.job);
+        if (si < cap) queue_write(di_def ? G.qdef : G.qout, si, xc, yc, p.z, di, eion, lin_i, p.pid,
+                                  pack_meta(qi, p.ir, p.iz), (uint32_t)p.job);
         else atomicOr(G.status, STATUS_OVERFLOW);
     }
+}
+
+// Clustering (Sec. 3.3 "Clustering"): a target particle's velocity V is drawn as for elastic
+// scattering and the product (species product[pi]) moves along it with the target particle's
+// momentum, |v'| = (M/m')|V|.  The projectile is deleted ("converted"); the product is a new
+// particle at the collision point whose energy comes from the gas.
+template <typename Real>
+__device__ void k_clustering(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+                             int pi, Real xc, Real yc) {
+    const int q = J.product[pi];
+    Real V[3];
+    thermal(J, p, 2u, 3u, V);
+    const Real sc = (Real)J.conv[pi];
+    const Real vn[3] = {sc * V[0], sc * V[1], sc * V[2]};
+    const Real vm = ksqrt(vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
+    Real dn[3] = {(Real)0, (Real)0, (Real)1};
+    if (vm > (Real)0) {
+        const Real iv = (Real)1 / vm;
+        dn[0] = vn[0] * iv;
+        dn[1] = vn[1] * iv;
+        dn[2] = vn[2] * iv;
+    }
+    const Real ep = (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]) * (Real)spv(J.e_from_v2, q);
+    const unsigned long long lin = child_lineage(p.lin, p.s, 0u);
+    const int ir = p.ir, iz = p.iz;
+    const Real z = p.z;
+    p.e_gas -= (double)ep;
+    kill(J, L, p, KARL_CONVERTED);
+    bool push = true;
+    if (!spv(J.tracked, q)) {
+        product_inline(J, L, q, ep, lin, p.pid, ir, iz, KARL_UNTRACKED);
+        push = false;
+    } else if (ep < (Real)spv(J.e_cut, q)) {
+        product_inline(J, L, q, ep, lin, p.pid, ir, iz, KARL_CUTOFF);
+        push = false;
+    }
+    bool dq;
+    const unsigned long long si = reserve_product(J, G, q, push, &dq);
+    if (push) {
+        if (si < (unsigned long long)G.capacity)
+            queue_write(dq ? G.qdef : G.qout, si, xc, yc, z, dn, ep, lin, p.pid, pack_meta(q, ir, iz),
+                        (uint32_t)p.job);
+        else atomicOr(G.status, STATUS_OVERFLOW);
+    }
+}
+
+// Charge exchange (Sec. 3.3): the projectile continues with the velocity of a target particle,
+// drawn as for elastic scattering.
+template <typename Real>
+__device__ void k_charge_exchange(const DevJob& J, Part<Real>& p) {
+    Real V[3];
+    thermal(J, p, 2u, 3u, V);
+    const Real e0 = p.e;
+    set_velocity(p, (Real)spv(J.e_from_v2, p.sp), V);
+    p.e_gas += (double)(e0 - p.e);
 }
 
 // ---------------------------------------------------------------- birth (Sec. 3.5)
@@ -854,13 +965,13 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     p.s_path = (Real)0;
     p.alive = true;
     p.fly = false;
-    p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)sel2(p.sp, J.v2_from_e[0], J.v2_from_e[1])) : (Real)0;
+    p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)spv(J.v2_from_e, p.sp)) : (Real)0;
     p.dg = mix64(p.lin ^ kDIGEST0);
     atomicAdd(&L.cnt[KARL_C_BIRTH + p.sp], 1ull);
     if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 2], 1.0);
     ev(p, 1u, (uint32_t)p.sp, (uint32_t)(p.ir * J.n_z + p.iz), dig);
-    if (!sel2(p.sp, J.tracked[0], J.tracked[1])) { kill(J, L, p, KARL_UNTRACKED); return; }
-    if (p.e < (Real)sel2(p.sp, J.e_cut[0], J.e_cut[1])) { kill(J, L, p, KARL_CUTOFF); return; }
+    if (!spv(J.tracked, p.sp)) { kill(J, L, p, KARL_UNTRACKED); return; }
+    if (p.e < (Real)spv(J.e_cut, p.sp)) { kill(J, L, p, KARL_CUTOFF); return; }
     if (!(p.vel > (Real)0)) { kill(J, L, p, KARL_LIFETIME); return; }
     if (J.gc) {
         if (gc_set(J, L, p, lc, p.x, p.y, true)) {
@@ -919,9 +1030,9 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     // the process metadata below become scalar loads
     const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
     // cross sections at the current energy, rates in the current cell (eq. 1)
-    const Real exs = p.e * (Real)sel2(sp, J.gfrac[0], J.gfrac[1]);
-    const Real xl = klog(exs * (Real)sel2(sp, J.inv_emin[0], J.inv_emin[1])) *
-                    (Real)sel2(sp, J.inv_dlog[0], J.inv_dlog[1]);
+    const Real exs = p.e * (Real)spv(J.gfrac, sp);
+    const Real xl = klog(exs * (Real)spv(J.inv_emin, sp)) *
+                    (Real)spv(J.inv_dlog, sp);
     int k;
     Real f;
     if (!(xl > (Real)0)) {
@@ -935,23 +1046,12 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         f = xl - (Real)k;
     }
     const Real n_gas_cell = L.ngas[p.iz];
-    // density field of the other species (Sec. 2.2), for processes that target it
-    const Real n_fld_cell = sel2(sp, J.uses_field[0], J.uses_field[1])
-                                ? (Real)(sp ? J.field[0] : J.field[1])[(size_t)p.ir * J.n_z + (size_t)p.iz]
-                                : (Real)0;
-    const int np = sel2(sp, J.nps[0], J.nps[1]);
+    // density field of the partner species (Sec. 2.2), for processes that target it
+    const Real n_fld_cell = field_density<Real>(J, sp, p.ir, p.iz);
+    const int np = spv(J.nps, sp);
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
-    for (int j = 0; j < np; ++j) {
-        const int i = pidx[j];
-        Real sig = (Real)0;
-        if (!(exs < L.eth[i])) {
-            const Real* tb = L.xs + (size_t)i * J.n_e;
-            sig = tb[k] + f * (tb[k + 1] - tb[k]);
-        }
-        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
-        sum += nt * sig;
-    }
+    for (int j = 0; j < np; ++j) sum += proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
     const Pair<Real> q0 = draw<Real>(J.seed, p.pid, p.lin, p.s, 0u);
     const Real eta = q0.d0 + Prec<Real>::eps;
     const Real xi = q0.d1;
@@ -1021,14 +1121,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         Real run = (Real)0;
         int sel = -1, last = -1;
         for (int j = 0; j < np; ++j) {
-            const int i = pidx[j];
-            Real sig = (Real)0;
-            if (!(exs < L.eth[i])) {
-                const Real* tb = L.xs + (size_t)i * J.n_e;
-                sig = tb[k] + f * (tb[k + 1] - tb[k]);
-            }
-            const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
-            const Real rate = nt * sig;
+            const Real rate = proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
             run += rate;
             if (rate > (Real)0) last = j;
             if (sel < 0 && target < run) sel = j;
@@ -1041,8 +1134,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), dig);
         Real xc = p.x, yc = p.y;
         if (J.gc) {
-            const Real om = (Real)sel2(sp, J.omega[0], J.omega[1]);
-            const Real iom = (Real)sel2(sp, J.inv_om[0], J.inv_om[1]);
+            const Real om = (Real)spv(J.omega, sp);
+            const Real iom = (Real)spv(J.inv_om, sp);
             const Real al = -(om * (p.s_path / p.vel));
             Real sa, ca;
             ksincos(al, &sa, &ca);
@@ -1061,13 +1154,13 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             case KARL_EXCITATION: {
                 const Real ex = L.eth[pi];
                 p.e = p.e - ex;
-                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)sel2(sp, J.v2_from_e[0], J.v2_from_e[1])) : (Real)0;
+                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)spv(J.v2_from_e, sp)) : (Real)0;
                 p.e_exc += (double)ex;
                 break;
             }
             case KARL_IONIZATION:
                 if constexpr (kDrain) {
-                    // cannot happen for a deferred species; flag it rather than go on silently
+                    // a deferred species makes no products; flag it rather than go on silently
                     atomicOr(J.status, STATUS_NUMERIC);
                     kill(J, L, p, KARL_LIFETIME);
                     killed = true;
@@ -1075,16 +1168,28 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                     k_ionization(J, L, G, p, pi, xc, yc, lc);
                 }
                 break;
+            case KARL_CHARGE_EXCHANGE:
+                k_charge_exchange(J, p);
+                break;
+            case KARL_CLUSTERING:
+                if constexpr (kDrain) {
+                    atomicOr(J.status, STATUS_NUMERIC);
+                    kill(J, L, p, KARL_LIFETIME);
+                } else {
+                    k_clustering(J, L, G, p, pi, xc, yc);
+                }
+                killed = true;
+                break;
             default:
                 // one deletion logged in the partner's field (Sec. 3.3 "Recombination")
-                add_u64(&J.recomb[((size_t)(1 - sp) * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], 1ull);
+                add_u64(&J.recomb[((size_t)J.partner[pi] * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], 1ull);
                 kill(J, L, p, KARL_RECOMBINED);
                 killed = true;
                 break;
         }
         if (!killed) {
-            if (p.e < (Real)sel2(sp, J.e_cut[0], J.e_cut[1])) kill(J, L, p, KARL_CUTOFF);
-            else if (p.n_int >= sel2(sp, J.cap[0], J.cap[1])) kill(J, L, p, KARL_CAP);
+            if (p.e < (Real)spv(J.e_cut, sp)) kill(J, L, p, KARL_CUTOFF);
+            else if (p.n_int >= spv(J.cap, sp)) kill(J, L, p, KARL_CAP);
             else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
             else if (J.gc) {
                 if (gc_set(J, L, p, lc, xc, yc, false)) {
@@ -1128,7 +1233,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         else p.ir = out ? fr : fr - 1;
     }
     p.s += 1u;
-    if (p.alive && p.t_alive >= sel2(sp, J.lifetime[0], J.lifetime[1])) kill(J, L, p, KARL_LIFETIME);
+    if (p.alive && p.t_alive >= spv(J.lifetime, sp)) kill(J, L, p, KARL_LIFETIME);
 }
 
 
@@ -1174,9 +1279,9 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
     const int izc = inside ? izk : iz;              // lanes past the tube end load valid cells
     const int fz = dir ? izc + 1 : izc;             // far face of segment k
     // rates in the segment's cell at the particle's energy (the arithmetic of step())
-    const Real exs = e * (Real)sel2(sp, J.gfrac[0], J.gfrac[1]);
-    const Real xl = klog(exs * (Real)sel2(sp, J.inv_emin[0], J.inv_emin[1])) *
-                    (Real)sel2(sp, J.inv_dlog[0], J.inv_dlog[1]);
+    const Real exs = e * (Real)spv(J.gfrac, sp);
+    const Real xl = klog(exs * (Real)spv(J.inv_emin, sp)) *
+                    (Real)spv(J.inv_dlog, sp);
     int kt;
     Real f;
     if (!(xl > (Real)0)) {
@@ -1190,22 +1295,11 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
         f = xl - (Real)kt;
     }
     const Real n_gas_cell = L.ngas[izc];
-    const Real n_fld_cell = sel2(sp, J.uses_field[0], J.uses_field[1])
-                                ? (Real)(sp ? J.field[0] : J.field[1])[(size_t)ir * J.n_z + (size_t)izc]
-                                : (Real)0;
-    const int np = sel2(sp, J.nps[0], J.nps[1]);
+    const Real n_fld_cell = field_density<Real>(J, sp, ir, izc);
+    const int np = spv(J.nps, sp);
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
-    for (int q = 0; q < np; ++q) {
-        const int i = pidx[q];
-        Real sig = (Real)0;
-        if (!(exs < L.eth[i])) {
-            const Real* tb = L.xs + (size_t)i * J.n_e;
-            sig = tb[kt] + f * (tb[kt + 1] - tb[kt]);
-        }
-        const Real nt = (L.tgt[i] == KARL_TARGET_GAS) ? n_gas_cell : n_fld_cell;
-        sum += nt * sig;
-    }
+    for (int q = 0; q < np; ++q) sum += proc_rate(J, L, pidx[q], exs, kt, f, n_gas_cell, n_fld_cell);
     const Pair<Real> q0 = draw<Real>(J.seed, pid, lin, s + (uint32_t)k, 0u);
     const Real eta = q0.d0 + Prec<Real>::eps;
     const Real dist = (sum > (Real)0) ? -klog(eta) / sum : (Real)INFINITY;
@@ -1229,7 +1323,7 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
     // the flight (the particle is deleted after that crossing)
     double ta = bc_r(p.t_alive, j);
     Real path = bc_r(p.s_path, j);
-    const double life = sel2(sp, J.lifetime[0], J.lifetime[1]);
+    const double life = spv(J.lifetime, sp);
     bool life_end = false;
     for (int kk = 0; kk < m; ++kk) {
         ta += (double)bc_r(dt, kk);
@@ -1304,7 +1398,7 @@ __device__ __forceinline__ Lds<Real> global_view(const DevJob& J, unsigned long 
 // to kSlots jobs (tagged by job index) and adds a slot to its job's tallies in HBM only when the
 // slot is reused for another job or at the end of the launch.
 constexpr int kSlots = 4;
-constexpr int kSlotWords = kNCnt + kNLed;   // 48 counters + 24 ledger entries, 8 bytes each
+constexpr int kSlotWords = kNCnt + kNLed;   // counters and ledger entries, 8 bytes each
 
 __device__ __forceinline__ void slot_flush(const DevJob* jobs, int job, unsigned long long* w) {
     // called by one lane
@@ -1480,7 +1574,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         unsigned long long* s_cnt = (unsigned long long*)lds_raw;
         double* s_led = (double*)(lds_raw + kNCnt * 8);
         int32_t* s_pidx = (int32_t*)(lds_raw + (kNCnt + kNLed) * 8);
-        int32_t* s_kind = s_pidx + 2 * KARL_MAX_PROC;
+        int32_t* s_kind = s_pidx + kS * KARL_MAX_PROC;
         int32_t* s_tgt = s_kind + KARL_MAX_PROC;
         Real* s_eth = (Real*)(s_tgt + KARL_MAX_PROC);
         Real* s_xs = s_eth + KARL_MAX_PROC;
@@ -1489,7 +1583,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         Real* s_rf = s_zf + (J.n_z + 1);
         for (int i = tid; i < kNCnt; i += blockDim.x) s_cnt[i] = 0ull;
         for (int i = tid; i < kNLed; i += blockDim.x) s_led[i] = 0.0;
-        for (int i = tid; i < 2 * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
+        for (int i = tid; i < kS * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
         for (int i = tid; i < KARL_MAX_PROC; i += blockDim.x) {
             s_kind[i] = J.kind[i];
             s_tgt[i] = J.target[i];
@@ -1547,7 +1641,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
             if (p.alive || p.start) advance<Real, kDrain>(jobs[0], L0, G, p, lc);
         } else {
             bool todo = p.alive || p.start;
-            const int key = 2 * p.job + (p.start ? 0 : p.sp);
+            const int key = kS * p.job + (p.start ? 0 : p.sp);
             for (;;) {
                 const unsigned long long m = __ballot(todo);
                 if (!m) break;
@@ -1596,15 +1690,16 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
 }
 
 // Normalised fields (Sec. 2.2 eq. 3 with t_sim = N_prim / activity, eq. 4; Sec. 2.3 currents):
-// density per species and segment minus recombinations per volume for the ion species,
+// density per species and segment minus the recombinations logged in its field per volume,
 // currents through the z-faces of each ring and the r-faces of each z-segment.
 __global__ void fields_kernel(const DevJob J, double t_sim, double* density, double* jz_cur,
                               double* jr_cur) {
     const int nr = J.n_r, nz = J.n_z;
     const double dz = J.length / (double)nz;
-    const size_t n_dens = (size_t)2 * nr * nz;
-    const size_t n_jz = (size_t)2 * nr * (nz + 1);
-    const size_t n_jr = (size_t)2 * (nr + 1) * nz;
+    const size_t ns = (size_t)J.n_species;
+    const size_t n_dens = ns * nr * nz;
+    const size_t n_jz = ns * nr * (nz + 1);
+    const size_t n_jr = ns * (nr + 1) * nz;
     const size_t total = n_dens + n_jz + n_jr;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
@@ -1645,7 +1740,7 @@ __global__ void fields_kernel(const DevJob J, double t_sim, double* density, dou
 __global__ void target_fields_kernel(const DevJob J, double t_sim) {
     const int nr = J.n_r, nz = J.n_z;
     const double dz = J.length / (double)nz;
-    const size_t n = (size_t)2 * nr * nz;
+    const size_t n = (size_t)J.n_species * nr * nz;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         const int s = (int)(t / ((size_t)nr * nz));
         const size_t cell = t % ((size_t)nr * nz);
@@ -1707,7 +1802,7 @@ __global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long l
 
 size_t lds_bytes(const DevJob& j, int precision) {
     const size_t rs = precision == KARL_FP32 ? sizeof(float) : sizeof(double);
-    size_t b = (size_t)(kNCnt + kNLed) * 8 + (size_t)4 * KARL_MAX_PROC * sizeof(int32_t);
+    size_t b = (size_t)(kNCnt + kNLed) * 8 + (size_t)(kS + 2) * KARL_MAX_PROC * sizeof(int32_t);
     b += rs * KARL_MAX_PROC;
     b += rs * ((size_t)j.n_proc * j.n_e + (size_t)j.n_z + (size_t)(j.n_z + 1) + (size_t)(j.n_r + 1));
     return (b + 15) & ~(size_t)15;
@@ -1754,8 +1849,8 @@ size_t batched_lds_bytes() {
 
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s) {
-    const size_t total = (size_t)2 * j.n_r * j.n_z + (size_t)2 * j.n_r * (j.n_z + 1) +
-                         (size_t)2 * (j.n_r + 1) * j.n_z;
+    const size_t ns = (size_t)j.n_species;
+    const size_t total = ns * j.n_r * j.n_z + ns * j.n_r * (j.n_z + 1) + ns * (j.n_r + 1) * j.n_z;
     size_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fields_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, t_sim, density, jz, jr);

@@ -48,7 +48,8 @@ constexpr int kFloorWindow = 8;
 // A job descriptor together with copies of every host array it points to.
 struct OwnedDesc {
     karl_job_desc d{};
-    std::vector<double> n_gas, n_ion, n_elec, edges[2], dens_edges[2], xs[KARL_MAX_PROC];
+    std::vector<double> n_gas, n_field[KARL_MAX_SPECIES], edges[KARL_MAX_SPECIES],
+        dens_edges[KARL_MAX_SPECIES], xs[KARL_MAX_PROC];
     std::vector<double> ang_edges[KARL_MAX_PROC], ang_theta[KARL_MAX_PROC], ang_pdf[KARL_MAX_PROC];
     std::vector<int32_t> planes;
 
@@ -56,15 +57,13 @@ struct OwnedDesc {
         d = s;
         n_gas.assign(s.n_gas, s.n_gas + s.n_z);
         d.n_gas = n_gas.data();
-        if (s.n_ion) {
-            n_ion.assign(s.n_ion, s.n_ion + (size_t)s.n_r * s.n_z);
-            d.n_ion = n_ion.data();
-        }
-        if (s.n_elec) {
-            n_elec.assign(s.n_elec, s.n_elec + (size_t)s.n_r * s.n_z);
-            d.n_elec = n_elec.data();
-        }
-        for (int k = 0; k < 2; ++k) {
+        // an out-of-range species count is rejected by validation; copy no more than fits
+        const int ns = (s.n_species >= 2 && s.n_species <= KARL_MAX_SPECIES) ? s.n_species : 2;
+        for (int k = 0; k < ns; ++k) {
+            if (s.n_field[k]) {
+                n_field[k].assign(s.n_field[k], s.n_field[k] + (size_t)s.n_r * s.n_z);
+                d.n_field[k] = n_field[k].data();
+            }
             edges[k].assign(s.species[k].edges, s.species[k].edges + s.n_bins + 1);
             d.species[k].edges = edges[k].data();
             if (s.n_dens_bins > 0 && s.species[k].dens_edges) {

@@ -16,17 +16,20 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libkarl.so")
 
 MAX_PROC = 16
-NCOUNTERS = 48
-NLEDGER = 24
+MAX_SPECIES = 4
+NCOUNTERS = 80
+NLEDGER = 48
 NHIST = 4
-NREASON = 8
+NREASON = 9
 FP64, FP32 = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 MAPPINGS = {"auto": MAP_AUTO, "lane": MAP_LANE, "wave": MAP_WAVE}
 FLAG_DIGESTS, FLAG_HISTORY = 1, 2
-# counter indices (KARL_C_* of include/karl.h); pairs are [electron, ion]
-C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 2, 4, 6, 8
-C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES, C_PROC, C_DEATH = 10, 11, 12, 16, 32
+# counter and ledger indices (KARL_C_*, KARL_L_* of include/karl.h); per-species entries have
+# MAX_SPECIES slots (0 electrons, 1.. ions)
+C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 4, 8, 12, 16
+C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES, C_PROC, C_DEATH = 20, 21, 22, 24, 40
+L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 37, 38, 39, 40
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDEVICE",
@@ -60,7 +63,8 @@ class SpeciesDesc(C.Structure):
 
 class ProcessDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("target", C.c_int32),
-                ("reserved0", C.c_int32), ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
+                ("product", C.c_int32), ("partner", C.c_int32), ("density_power", C.c_int32),
+                ("e_th", C.c_double), ("xs", C.POINTER(C.c_double)),
                 ("ang_bins", C.c_int32), ("ang_nodes", C.c_int32), ("e_iso", C.c_double),
                 ("ang_edges", C.POINTER(C.c_double)), ("ang_theta", C.POINTER(C.c_double)),
                 ("ang_pdf", C.POINTER(C.c_double))]
@@ -69,9 +73,10 @@ class ProcessDesc(C.Structure):
 class JobDesc(C.Structure):
     _fields_ = [("radius", C.c_double), ("length", C.c_double), ("n_r", C.c_int32),
                 ("n_z", C.c_int32), ("n_gas", C.POINTER(C.c_double)),
-                ("n_ion", C.POINTER(C.c_double)), ("n_elec", C.POINTER(C.c_double)),
+                ("n_field", C.POINTER(C.c_double) * MAX_SPECIES),
                 ("t_gas", C.c_double), ("m_gas", C.c_double),
-                ("bz", C.c_double), ("species", SpeciesDesc * 2), ("n_proc", C.c_int32),
+                ("bz", C.c_double), ("species", SpeciesDesc * MAX_SPECIES),
+                ("n_species", C.c_int32), ("n_proc", C.c_int32),
                 ("n_e", C.c_int32), ("proc", ProcessDesc * MAX_PROC), ("source", C.c_int32),
                 ("beam_species", C.c_int32), ("beta_e0", C.c_double), ("beta_z", C.c_double),
                 ("beta_fmax", C.c_double), ("beam_energy", C.c_double),
@@ -181,13 +186,17 @@ class Descriptor:
         d = JobDesc()
         d.radius, d.length, d.n_r, d.n_z = w.radius, w.length, w.n_r, w.n_z
         d.n_gas = _dptr(self._hold(w.n_gas, np.float64))
-        if w.n_ion is not None:
-            d.n_ion = _dptr(self._hold(w.n_ion, np.float64))
-        if getattr(w, "n_elec", None) is not None:
-            d.n_elec = _dptr(self._hold(w.n_elec, np.float64))
+        # density fields: slot 0 electrons (n_elec), slot 1 ions (n_ion), further slots from
+        # the workload's extra_fields mapping
+        fields = {0: getattr(w, "n_elec", None), 1: w.n_ion}
+        fields.update(getattr(w, "extra_fields", None) or {})
+        for k, f in fields.items():
+            if f is not None:
+                d.n_field[k] = _dptr(self._hold(f, np.float64))
         d.t_gas, d.m_gas, d.bz = w.t_gas, w.m_gas, w.bz
         nb = len(w.species[0].edges) - 1
-        for s in range(2):
+        d.n_species = len(w.species)
+        for s in range(len(w.species)):
             sp = w.species[s]
             ds = d.species[s]
             ds.mass, ds.charge, ds.e_cut, ds.lifetime = sp.mass, sp.charge, sp.e_cut, sp.lifetime
@@ -196,12 +205,12 @@ class Descriptor:
             ds.xs_emin, ds.xs_emax = sp.xs_emin, sp.xs_emax
             edges = self._hold(sp.edges, np.float64)
             if len(edges) != nb + 1:
-                raise ValueError("both species need the same number of spectrum bins")
+                raise ValueError("every species needs the same number of spectrum bins")
             ds.edges = _dptr(edges)
             if getattr(w, "dens_edges", None) is not None:
                 de = self._hold(w.dens_edges[s], np.float64)
                 if len(de) != len(w.dens_edges[0]):
-                    raise ValueError("both species need the same number of density energy bins")
+                    raise ValueError("every species needs the same number of density energy bins")
                 ds.dens_edges = _dptr(de)
                 d.n_dens_bins = len(de) - 1
         d.n_proc = len(w.processes)
@@ -209,6 +218,10 @@ class Descriptor:
         for i, p in enumerate(w.processes):
             dp = d.proc[i]
             dp.kind, dp.species, dp.target, dp.e_th = p.kind, p.species, p.target, p.e_th
+            dp.product = getattr(p, "product", 1)
+            partner = getattr(p, "partner", None)
+            dp.partner = (1 - p.species) if partner is None else partner
+            dp.density_power = getattr(p, "density_power", 1)
             xs = self._hold(p.xs, np.float64)
             if len(xs) != w.n_e:
                 raise ValueError(f"process {i}: table has {len(xs)} nodes, expected {w.n_e}")
@@ -253,14 +266,15 @@ class Descriptor:
 
 def tally_shapes(w, digests: bool, history: bool) -> Dict[str, tuple]:
     nb = len(w.species[0].edges) - 1
+    ns = len(w.species)
     s = {
         "counters": ((NCOUNTERS,), np.int64), "ledger": ((NLEDGER,), np.float64),
-        "density_time": ((2, w.n_r, w.n_z), np.float64), "recomb": ((2, w.n_r, w.n_z), np.int64),
-        "jz": ((2, w.n_r, w.n_z + 1, 2), np.int64), "jr": ((2, w.n_r + 1, w.n_z, 2), np.int64),
-        "spectra": ((2, len(w.planes), 2, nb + 2), np.int64),
+        "density_time": ((ns, w.n_r, w.n_z), np.float64), "recomb": ((ns, w.n_r, w.n_z), np.int64),
+        "jz": ((ns, w.n_r, w.n_z + 1, 2), np.int64), "jr": ((ns, w.n_r + 1, w.n_z, 2), np.int64),
+        "spectra": ((ns, len(w.planes), 2, nb + 2), np.int64),
     }
     if getattr(w, "dens_edges", None) is not None:
-        s["density_time_e"] = ((2, w.n_r, w.n_z, len(w.dens_edges[0]) + 1), np.float64)
+        s["density_time_e"] = ((ns, w.n_r, w.n_z, len(w.dens_edges[0]) + 1), np.float64)
     if digests:
         s["digests"] = ((w.n_primaries,), np.uint64)
     if history:
@@ -360,9 +374,10 @@ def _read_tallies(h, w, digests, history, stream=None, only=None) -> Dict[str, n
 
 
 def _read_fields(h, w, activity, stream=None) -> Dict[str, np.ndarray]:
-    dens = np.zeros((2, w.n_r, w.n_z))
-    jz = np.zeros((2, w.n_r, w.n_z + 1))
-    jr = np.zeros((2, w.n_r + 1, w.n_z))
+    ns = len(w.species)
+    dens = np.zeros((ns, w.n_r, w.n_z))
+    jz = np.zeros((ns, w.n_r, w.n_z + 1))
+    jr = np.zeros((ns, w.n_r + 1, w.n_z))
     check(lib().karl_read_fields(h, float(activity), _dptr(dens), _dptr(jz), _dptr(jr),
                                  Job._stream(stream)))
     return {"density": dens, "jz": jz, "jr": jr}

@@ -13,8 +13,8 @@ from . import karl
 
 
 def collisions_of(counters: np.ndarray) -> int:
-    """Performed interactions of both species (KARL_C_COLL pair of the counters)."""
-    return int(counters[karl.C_COLL] + counters[karl.C_COLL + 1])
+    """Performed interactions of all species (the KARL_C_COLL entries of the counters)."""
+    return int(sum(counters[karl.C_COLL + k] for k in range(karl.MAX_SPECIES)))
 
 
 def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], realtime: bool = True,

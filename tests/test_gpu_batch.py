@@ -108,8 +108,8 @@ def test_many_jobs_counters_equal_alone():
     for k, (w, job) in enumerate(zip(ws, jobs)):
         g = job.read_tallies()
         c = g["counters"]
-        n_ion = sum(int(c[16 + i]) for i, p in enumerate(w.processes) if p.kind == W.IONIZATION)
-        assert c[0] == w.n_primaries + n_ion and c[1] == n_ion, f"job {k}"
+        n_ion = sum(int(c[karl.C_PROC + i]) for i, p in enumerate(w.processes) if p.kind == W.IONIZATION)
+        assert c[karl.C_BIRTH] == w.n_primaries + n_ion and c[karl.C_BIRTH + 1] == n_ion, f"job {k}"
         alone, _ = run_gpu(w, [(0, w.n_primaries)], precision="fp32")
         for key in ["counters", "recomb", "jz", "jr", "spectra"]:
             np.testing.assert_array_equal(g[key], alone[key], err_msg=f"job {k}: {key}")

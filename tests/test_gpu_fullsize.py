@@ -32,13 +32,15 @@ def _gpu():
 
 
 def _identities(c, L, n_primaries, processes, energy_rtol):
-    n_ion = sum(int(c[16 + i]) for i, p in enumerate(processes) if p.kind == W.IONIZATION)
-    assert c[0] == n_primaries + n_ion            # electrons: primaries + one per ionization
-    assert c[1] == n_ion                          # ions: one per ionization
-    deaths = c[32:48].reshape(2, 8)
-    assert deaths[0].sum() == c[0] and deaths[1].sum() == c[1]   # each deleted exactly once
-    out = L[1:17].sum() + L[17] + L[18] + L[19]
-    assert abs(out / L[0] - 1.0) < energy_rtol
+    from paper_2503_10263_amd import karl as K
+    nr = K.NREASON
+    n_ion = sum(int(c[K.C_PROC + i]) for i, p in enumerate(processes) if p.kind == W.IONIZATION)
+    assert c[K.C_BIRTH] == n_primaries + n_ion    # electrons: primaries + one per ionization
+    assert c[K.C_BIRTH + 1] == n_ion              # ions: one per ionization
+    deaths = c[K.C_DEATH:K.C_DEATH + 2 * nr].reshape(2, nr)
+    assert deaths[0].sum() == c[K.C_BIRTH] and deaths[1].sum() == c[K.C_BIRTH + 1]   # each deleted once
+    out = L[K.L_E_DEATH:K.L_E_DEATH + 2 * nr].sum() + L[K.L_E_EXC] + L[K.L_E_BIND] + L[K.L_E_GAS]
+    assert abs(out / L[K.L_E_PRIMARY] - 1.0) < energy_rtol
 
 
 def test_full_case_bench_batch_sampled_histories():
@@ -52,7 +54,7 @@ def test_full_case_bench_batch_sampled_histories():
     finally:
         job.close()
     _identities(g["counters"], g["ledger"], BENCH_BATCH, w.processes, 1e-10)
-    assert g["counters"][32 + 8 + W.REASONS.index("cap")] > 0      # cap-bound ions present
+    assert g["counters"][karl.C_DEATH + karl.NREASON + W.REASONS.index("cap")] > 0   # cap-bound ions
     assert np.all(g["digests"][BENCH_BATCH:] == 0)
 
     def one(pid):

@@ -8,6 +8,7 @@ and ragged tails."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2503_10263_amd import workloads as W
 from parity_util import parity, run_gpu, run_oracle, compare_tallies
 
@@ -27,13 +28,13 @@ def test_tiny_straight_line():
     """The tiny case: 1e4 beta electrons, 1 m tube, B = 0, three processes."""
     w = W.cfg_tiny(n_primaries=10000)
     g, o, frac = parity(w)
-    assert g["counters"][0] == o["counters"][0] >= 10000
+    assert g["counters"][oracle.C_BIRTH] == o["counters"][oracle.C_BIRTH] >= 10000
 
 
 def test_tiny_dense_column_many_generations():
     w = W.cfg_tiny(n_primaries=3000, column_cm2=1.0e18)
     g, o, frac = parity(w)
-    assert o["counters"][W.MAX_PROC + 1] > 100      # ionizations happened
+    assert o["counters"][oracle.C_PROC + 1] > 100   # ionizations happened
 
 
 def test_guiding_centre_grid():
@@ -49,8 +50,8 @@ def test_full_case_capped_ions():
     w = W.cfg_full(n_primaries=60)
     w.species[W.ION].cap = 3000
     g, o, frac = parity(w)
-    assert o["counters"][1] > 0                         # ions were born and tracked
-    assert o["counters"][W.MAX_PROC * 2 + 8 + W.REASONS.index("cap")] > 0
+    assert o["counters"][oracle.C_BIRTH + 1] > 0        # ions were born and tracked
+    assert o["counters"][oracle.C_DEATH + oracle.NREASON + W.REASONS.index("cap")] > 0
 
 
 def test_excitation_beam_planes():
@@ -108,7 +109,9 @@ def test_energy_and_particle_conservation_gpu():
     c, L, h = g["counters"], g["ledger"], g["hist"]
     np.testing.assert_array_equal(h[:, 2], h[:, 3])
     assert np.max(np.abs(h[:, 0] - h[:, 1]) / h[:, 0]) < 1e-10
-    deaths = c[32:48].reshape(2, 8)
-    assert deaths[0].sum() == c[0] and deaths[1].sum() == c[1]
-    out = L[1:17].sum() + L[17] + L[18] + L[19]
-    assert abs(out / L[0] - 1.0) < 1e-11
+    from paper_2503_10263_amd import karl as K
+    nr = K.NREASON
+    deaths = c[K.C_DEATH:K.C_DEATH + 2 * nr].reshape(2, nr)
+    assert deaths[0].sum() == c[K.C_BIRTH] and deaths[1].sum() == c[K.C_BIRTH + 1]
+    out = L[K.L_E_DEATH:K.L_E_DEATH + 2 * nr].sum() + L[K.L_E_EXC] + L[K.L_E_BIND] + L[K.L_E_GAS]
+    assert abs(out / L[K.L_E_PRIMARY] - 1.0) < 1e-11

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
+from paper_2503_10263_amd import karl as K
 from paper_2503_10263_amd import workloads as W
 from parity_util import run_oracle
 
@@ -90,10 +91,13 @@ def test_fp32_statistics_against_fp64_oracle(bz, column):
             assert stats.chi2.sf(chi2, dof) > 0.01, (end, chi2, dof)
     def deposited(t):
         L = t["ledger"]
-        escaped = L[1:17].reshape(2, 8)[:, :3].sum()      # ends and wall
-        return (L[0] - escaped) / N
+        nr = K.NREASON
+        escaped = L[K.L_E_DEATH:K.L_E_DEATH + 2 * nr].reshape(2, nr)[:, :3].sum()   # ends and wall
+        return (L[K.L_E_PRIMARY] - escaped) / N
     dg, do = deposited(g), deposited(o)
     assert abs(dg / do - 1.0) < 1e-3, (dg, do)
     # particle bookkeeping is exact in any precision
     c = g["counters"]
-    assert c[32:40].sum() == c[0] and c[40:48].sum() == c[1]
+    nr = K.NREASON
+    assert c[K.C_DEATH:K.C_DEATH + nr].sum() == c[K.C_BIRTH]
+    assert c[K.C_DEATH + nr:K.C_DEATH + 2 * nr].sum() == c[K.C_BIRTH + 1]
