@@ -803,37 +803,37 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.seed = d->seed;
     J.n_species = ns;
     for (int s = 0; s < karl::kS; ++s) {
-        J.nps[s] = 0;
-        J.field_of[s] = -1;
-        J.defer[s] = 0;
-        J.field[s] = nullptr;
+        J.sc.nps[s] = 0;
+        J.sc.field_of[s] = -1;
+        J.sc.defer[s] = 0;
+        J.sc.field[s] = nullptr;
         if (s >= ns) {
             // unused slots: harmless values (never selected by a particle)
-            J.tracked[s] = 0;
-            J.cap[s] = 1;
-            J.mass[s] = J.charge[s] = J.e_cut[s] = J.lifetime[s] = J.msum[s] = 0.0;
-            J.xs_emin[s] = J.inv_dlog[s] = J.omega[s] = J.mfrac[s] = J.gfrac[s] = 0.0;
-            J.inv_emin[s] = J.inv_om[s] = J.e_from_v2[s] = J.v2_from_e[s] = 0.0;
+            J.sc.tracked[s] = 0;
+            J.sc.cap[s] = 1;
+            J.sc.mass[s] = J.sc.charge[s] = J.sc.e_cut[s] = J.sc.lifetime[s] = J.sc.msum[s] = 0.0;
+            J.sc.xs_emin[s] = J.sc.inv_dlog[s] = J.sc.omega[s] = J.sc.mfrac[s] = J.sc.gfrac[s] = 0.0;
+            J.sc.inv_emin[s] = J.sc.inv_om[s] = J.sc.e_from_v2[s] = J.sc.v2_from_e[s] = 0.0;
             continue;
         }
         const karl_species_desc& sp = d->species[s];
-        J.tracked[s] = sp.tracked ? 1 : 0;
-        J.cap[s] = sp.cap;
-        J.mass[s] = sp.mass;
-        J.charge[s] = sp.charge;
-        J.e_cut[s] = sp.e_cut;
-        J.lifetime[s] = sp.lifetime;
-        J.msum[s] = sp.mass + d->m_gas;
-        J.xs_emin[s] = sp.xs_emin;
-        J.inv_dlog[s] = (double)(d->n_e - 1) / std::log(sp.xs_emax / sp.xs_emin);
-        J.omega[s] = sp.charge * d->bz / sp.mass;
+        J.sc.tracked[s] = sp.tracked ? 1 : 0;
+        J.sc.cap[s] = sp.cap;
+        J.sc.mass[s] = sp.mass;
+        J.sc.charge[s] = sp.charge;
+        J.sc.e_cut[s] = sp.e_cut;
+        J.sc.lifetime[s] = sp.lifetime;
+        J.sc.msum[s] = sp.mass + d->m_gas;
+        J.sc.xs_emin[s] = sp.xs_emin;
+        J.sc.inv_dlog[s] = (double)(d->n_e - 1) / std::log(sp.xs_emax / sp.xs_emin);
+        J.sc.omega[s] = sp.charge * d->bz / sp.mass;
         const double mt = sp.mass + d->m_gas;
-        J.mfrac[s] = sp.mass / mt;
-        J.gfrac[s] = d->m_gas / mt;
-        J.inv_emin[s] = 1.0 / sp.xs_emin;
-        J.inv_om[s] = (J.omega[s] != 0.0) ? 1.0 / J.omega[s] : 0.0;
-        J.e_from_v2[s] = 0.5 * sp.mass / kQE;
-        J.v2_from_e[s] = 2.0 * kQE / sp.mass;
+        J.sc.mfrac[s] = sp.mass / mt;
+        J.sc.gfrac[s] = d->m_gas / mt;
+        J.sc.inv_emin[s] = 1.0 / sp.xs_emin;
+        J.sc.inv_om[s] = (J.sc.omega[s] != 0.0) ? 1.0 / J.sc.omega[s] : 0.0;
+        J.sc.e_from_v2[s] = 0.5 * sp.mass / kQE;
+        J.sc.v2_from_e[s] = 2.0 * kQE / sp.mass;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
         const bool has_ang = i < d->n_proc && d->proc[i].ang_bins > 0;
@@ -854,8 +854,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     }
     for (int i = 0; i < d->n_proc; ++i) {
         const int s = d->proc[i].species;
-        J.pidx[s][J.nps[s]++] = i;
-        if (d->proc[i].target == KARL_TARGET_FIELD) J.field_of[s] = d->proc[i].partner;
+        J.pidx[s][J.sc.nps[s]++] = i;
+        if (d->proc[i].target == KARL_TARGET_FIELD) J.sc.field_of[s] = d->proc[i].partner;
     }
     // A species without ionization or clustering never produces particles: its particles can
     // wait in the deferred queue and run together in one launch after the other generations.
@@ -865,7 +865,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
             if (d->proc[i].species == s &&
                 (d->proc[i].kind == KARL_IONIZATION || d->proc[i].kind == KARL_CLUSTERING))
                 produces = true;
-        J.defer[s] = produces ? 0 : 1;
+        J.sc.defer[s] = produces ? 0 : 1;
     }
     J.p2scale = p2scale;
     J.sigma_v = std::sqrt(kKB * d->t_gas / d->m_gas);
@@ -888,7 +888,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.rf = w + L.rf;
     J.zcdf = w + L.zcdf;
     for (int f = 0; f < ns; ++f)
-        J.field[f] = uses_fields(d) ? (double*)(w + L.tfield + 8 * (size_t)f * nr * nz) : nullptr;
+        J.sc.field[f] = uses_fields(d) ? (double*)(w + L.tfield + 8 * (size_t)f * nr * nz) : nullptr;
     J.edges = (const double*)(w + L.edges);
     J.plane_of = (const int32_t*)(w + L.plane_of);
     char* t = w + L.tallies;
@@ -1008,7 +1008,7 @@ karl_status karl_update_target_fields(void* job, double activity, void* hip_stre
     if (!(activity > 0.0) || !std::isfinite(activity))
         return fail(KARL_EINVAL, "activity must be positive and finite");
     if (j->n_transported <= 0) return fail(KARL_ESTATE, "no primaries transported since the last reset");
-    if (!j->dj.field[0]) return KARL_OK;   // no process targets a field
+    if (!j->dj.sc.field[0]) return KARL_OK;   // no process targets a field
     HIP_CHECK(hipSetDevice(j->device));
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_CHECK(karl::launch_target_fields(j->dj, (double)j->n_transported / activity, s));

@@ -30,13 +30,10 @@ enum : int32_t { TGT_GAS = 0, TGT_FIELD = 1, TGT_GAS2 = 2 };
 
 constexpr int kS = KARL_MAX_SPECIES;
 
-// Everything the transport kernel needs about one job, passed by value.
-struct DevJob {
-    double radius, length;
-    int32_t n_r, n_z, n_e, n_proc, n_bins, n_planes;
-    int32_t gc, source, beam_species, flags;
-    uint32_t seed;
-    int32_t beam_ir, beam_iz, n_species;
+// Per-species constants of a job, indexed by species slot.  Single-job launches stage them in
+// LDS (one indexed read per use, whatever the species mix of a wave); batched launches read
+// them from HBM with a wave-uniform species.
+struct SpeciesConst {
     int32_t nps[kS];
     int32_t field_of[kS];        // species whose density field this species' field processes see, or -1
     int32_t defer[kS];           // particles of this species make no products: queued for the drain
@@ -52,6 +49,17 @@ struct DevJob {
     double inv_om[kS];     // 1 / omega (0 without field)
     double e_from_v2[kS];  // E(eV) = v^2 * e_from_v2
     double v2_from_e[kS];  // v^2 = E(eV) * v2_from_e
+    double* field[kS];     // [n_r*n_z] density field of each species (m^-3), or NULL
+};
+
+// Everything the transport kernel needs about one job, passed by value.
+struct DevJob {
+    double radius, length;
+    int32_t n_r, n_z, n_e, n_proc, n_bins, n_planes;
+    int32_t gc, source, beam_species, flags;
+    uint32_t seed;
+    int32_t beam_ir, beam_iz, n_species;
+    SpeciesConst sc;
     double sigma_v;        // sqrt(k T / m_gas)
     double m_gas;
     double p2scale;        // TGT_GAS2 tables are stored divided by this (FP32 range), rate times it
@@ -75,7 +83,6 @@ struct DevJob {
     const void* zf;        // [n_z+1] z faces
     const void* rf;        // [n_r+1] r faces
     const void* zcdf;      // [n_z+1] cumulative gas weights
-    double* field[kS];     // [n_r*n_z] density field of each species (m^-3), or NULL
     const double* edges;   // [n_species][n_bins+1]
     const int32_t* plane_of;   // [n_z+1] plane index or -1
     const double* dens_edges;  // [n_species][n_dens_bins+1] or NULL

@@ -185,6 +185,7 @@ __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint
 }
 
 template <typename Real> struct Pair { Real d0, d1; };
+template <typename Real> struct Vec3 { Real x, y, z; };   // passed by value: stays in registers
 
 // one slot of the draw schedule: key (seed, pid), counter (step, slot, lineage)
 template <typename Real>
@@ -283,6 +284,7 @@ struct Lds {
     const Real* ngas;          // [n_z]
     const Real* zf;            // [n_z+1]
     const Real* rf;            // [n_r+1]
+    const SpeciesConst* sc;    // per-species constants (LDS copy, or the job's in HBM)
     bool direct;               // per-event counts go straight to cnt (wave-aggregated)
 };
 
@@ -350,19 +352,6 @@ __device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt,
     lc = LaneCnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
 }
 
-// Entry sp (0..3) of a per-species array of the job, chosen by selects: a species index that
-// differs between lanes stays in registers instead of becoming an indexed load.  A vector
-// select reads at most one scalar register, so the compiler copies job constants to vector
-// registers and would hoist those copies out of the persistent loop, one per slot; the empty
-// asm keeps slots 2 and 3 (used by chemistry jobs only) scalar until the select.
-template <typename T>
-__device__ __forceinline__ T spv(const T (&a)[kS], int sp) {
-    T a2 = a[2], a3 = a[3];
-    asm volatile("" : "+s"(a2), "+s"(a3));
-    const T lo = (sp & 1) ? a[1] : a[0];
-    const T hi = (sp & 1) ? a3 : a2;
-    return (sp & 2) ? hi : lo;
-}
 
 // ---------------------------------------------------------------- tally helpers
 template <typename Real>
@@ -422,7 +411,7 @@ __device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess
 template <typename Real>
 __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
                        Real yp, bool at_birth) {
-    const Real iom = (Real)spv(J.inv_om, p.sp);
+    const Real iom = (Real)L.sc->inv_om[p.sp];
     const Real gx = xp + (p.vel * p.v) * iom;
     const Real gy = yp - (p.vel * p.u) * iom;
     const Real rho = ksqrt(gx * gx + gy * gy);
@@ -465,10 +454,10 @@ __device__ __forceinline__ Real proc_rate(const DevJob& J, const Lds<Real>& L, i
 
 // density of the field that species sp's field processes target, in cell (ir, iz)
 template <typename Real>
-__device__ __forceinline__ Real field_density(const DevJob& J, int sp, int ir, int iz) {
-    const int fo = spv(J.field_of, sp);
+__device__ __forceinline__ Real field_density(const DevJob& J, const Lds<Real>& L, int sp, int ir, int iz) {
+    const int fo = L.sc->field_of[sp];
     if (fo < 0) return (Real)0;
-    return (Real)spv(J.field, fo)[(size_t)ir * J.n_z + (size_t)iz];
+    return (Real)L.sc->field[fo][(size_t)ir * J.n_z + (size_t)iz];
 }
 
 // ---------------------------------------------------------------- kinematics
@@ -564,12 +553,12 @@ __device__ Real scatter_mu(const DevJob& J, int pi, Real ecm, Real u) {
     return (Real)cs;
 }
 
+// V: the target particle's velocity (thermal(), slots 2 and 3 of the step)
 template <typename Real>
-__device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
+__device__ double k_elastic(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int pi, Vec3<Real> tv) {
+    const Real V[3] = {tv.x, tv.y, tv.z};
     const int s = p.sp;
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
-    Real V[3];
-    thermal(J, p, 2u, 3u, V);
     const Real g[3] = {v[0] - V[0], v[1] - V[1], v[2] - V[2]};
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     Real gh[3] = {(Real)0, (Real)0, (Real)1};
@@ -580,12 +569,12 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
         gh[2] = g[2] * ig;
     }
     // centre-of-mass velocity (m v + M V)/(m + M)
-    const Real mf = (Real)spv(J.mfrac, s);
-    const Real gf = (Real)spv(J.gfrac, s);
+    const Real mf = (Real)L.sc->mfrac[s];
+    const Real gf = (Real)L.sc->gfrac[s];
     const Real cm[3] = {mf * v[0] + gf * V[0], mf * v[1] + gf * V[1], mf * v[2] + gf * V[2]};
     const Pair<Real> q = draw<Real>(J.seed, p.pid, p.lin, p.s, 1u);
     // the impact energy in the centre-of-mass frame selects the angle distribution
-    const Real ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * (Real)spv(J.e_from_v2, s) * gf;
+    const Real ecm = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * (Real)L.sc->e_from_v2[s] * gf;
     const Real mu = scatter_mu(J, pi, ecm, q.d0);
     const Real phi = (Real)kTWO_PI * q.d1;
     Real gn[3];
@@ -593,8 +582,8 @@ __device__ void k_elastic(const DevJob& J, Part<Real>& p, int pi) {
     const Real a = gf * gm;
     const Real vn[3] = {cm[0] + a * gn[0], cm[1] + a * gn[1], cm[2] + a * gn[2]};
     const Real e0 = p.e;
-    set_velocity(p, (Real)spv(J.e_from_v2, s), vn);
-    p.e_gas += (double)(e0 - p.e);
+    set_velocity(p, (Real)L.sc->e_from_v2[s], vn);
+    return (double)(e0 - p.e);
 }
 
 // Kim-Rudd BEB secondary-energy distribution (Q = 1) on w = W/B in [0,(t-1)/2]: exact
@@ -670,9 +659,10 @@ __device__ __forceinline__ uint32_t pack_meta(int sp, int ir, int iz) {
 // Queue slot of a product of species q for the lanes with `want`: the deferred queue for
 // species that make no products of their own, else the next generation's.  Both reservations
 // are wave-wide, so lanes may differ in q.
-__device__ __forceinline__ unsigned long long reserve_product(const DevJob& J, const GenArgs& G, int q,
+template <typename Real>
+__device__ __forceinline__ unsigned long long reserve_product(const Lds<Real>& L, const GenArgs& G, int q,
                                                               bool want, bool* deferred) {
-    const bool dq = spv(J.defer, q) != 0;
+    const bool dq = L.sc->defer[q] != 0;
     const unsigned long long sd = wave_reserve(G.qdef_count, want && dq);
     const unsigned long long so = wave_reserve(G.qout_count, want && !dq);
     *deferred = dq;
@@ -702,13 +692,12 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
 
 template <typename Real>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                             int pi, Real xc, Real yc, LaneCnt& lc) {
-    const Real ef2 = (Real)spv(J.e_from_v2, p.sp);
-    const Real v2e = (Real)spv(J.v2_from_e, p.sp);
+                             int pi, Real xc, Real yc, LaneCnt& lc, Vec3<Real> tv) {
+    const Real ef2 = (Real)L.sc->e_from_v2[p.sp];
+    const Real v2e = (Real)L.sc->v2_from_e[p.sp];
     const Real B = L.eth[pi];
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
-    Real V[3], g[3];
-    thermal(J, p, 2u, 3u, V);
+    Real V[3] = {tv.x, tv.y, tv.z}, g[3];
     g[0] = v[0] - V[0];
     g[1] = v[1] - V[1];
     g[2] = v[2] - V[2];
@@ -761,7 +750,7 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     const Real vs[3] = {V[0] + ss * ds[0], V[1] + ss * ds[1], V[2] + ss * ds[2]};
     const Real es = (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]) * ef2;
     const int qi = J.product[pi];   // the ion species made (molecular, or atomic if dissociative)
-    const Real eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * (Real)spv(J.e_from_v2, qi);
+    const Real eion = (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]) * (Real)L.sc->e_from_v2[qi];
     const Real e0 = p.e;
     set_velocity(p, ef2, vf);
     p.e_bind += (double)B;
@@ -787,25 +776,25 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
         di[2] = V[2] * iv;
     }
     bool push_e = true, push_i = true;
-    if (!J.tracked[0]) {
+    if (!J.sc.tracked[0]) {
         product_inline(J, L, 0, es, lin_e, p.pid, p.ir, p.iz, KARL_UNTRACKED);
         push_e = false;
-    } else if (es < (Real)J.e_cut[0]) {
+    } else if (es < (Real)J.sc.e_cut[0]) {
         product_inline(J, L, 0, es, lin_e, p.pid, p.ir, p.iz, KARL_CUTOFF);
         push_e = false;
     }
-    if (!spv(J.tracked, qi)) {
+    if (!L.sc->tracked[qi]) {
         product_inline(J, L, qi, eion, lin_i, p.pid, p.ir, p.iz, KARL_UNTRACKED);
         push_i = false;
-    } else if (eion < (Real)spv(J.e_cut, qi)) {
+    } else if (eion < (Real)L.sc->e_cut[qi]) {
         product_inline(J, L, qi, eion, lin_i, p.pid, p.ir, p.iz, KARL_CUTOFF);
         push_i = false;
     }
     // the electron's destination is uniform (slot 0); the ion's follows its species
-    const QueueSoA& qe = J.defer[0] ? G.qdef : G.qout;
-    const unsigned long long se = wave_reserve(J.defer[0] ? G.qdef_count : G.qout_count, push_e);
+    const QueueSoA& qe = J.sc.defer[0] ? G.qdef : G.qout;
+    const unsigned long long se = wave_reserve(J.sc.defer[0] ? G.qdef_count : G.qout_count, push_e);
     bool di_def;
-    const unsigned long long si = reserve_product(J, G, qi, push_i, &di_def);
+    const unsigned long long si = reserve_product(L, G, qi, push_i, &di_def);
     const unsigned long long cap = (unsigned long long)G.capacity;
     if (push_e) {
         if (se < cap) queue_write(qe, se, xc, yc, p.z, de, es, lin_e, p.pid, pack_meta(0, p.ir, p.iz), (uint32_t)p.job);
@@ -824,10 +813,9 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
 // particle at the collision point whose energy comes from the gas.
 template <typename Real>
 __device__ void k_clustering(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                             int pi, Real xc, Real yc) {
+                             int pi, Real xc, Real yc, Vec3<Real> tv) {
+    const Real V[3] = {tv.x, tv.y, tv.z};
     const int q = J.product[pi];
-    Real V[3];
-    thermal(J, p, 2u, 3u, V);
     const Real sc = (Real)J.conv[pi];
     const Real vn[3] = {sc * V[0], sc * V[1], sc * V[2]};
     const Real vm = ksqrt(vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
@@ -838,22 +826,22 @@ __device__ void k_clustering(const DevJob& J, const Lds<Real>& L, const GenArgs&
         dn[1] = vn[1] * iv;
         dn[2] = vn[2] * iv;
     }
-    const Real ep = (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]) * (Real)spv(J.e_from_v2, q);
+    const Real ep = (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]) * (Real)L.sc->e_from_v2[q];
     const unsigned long long lin = child_lineage(p.lin, p.s, 0u);
     const int ir = p.ir, iz = p.iz;
     const Real z = p.z;
     p.e_gas -= (double)ep;
     kill(J, L, p, KARL_CONVERTED);
     bool push = true;
-    if (!spv(J.tracked, q)) {
+    if (!L.sc->tracked[q]) {
         product_inline(J, L, q, ep, lin, p.pid, ir, iz, KARL_UNTRACKED);
         push = false;
-    } else if (ep < (Real)spv(J.e_cut, q)) {
+    } else if (ep < (Real)L.sc->e_cut[q]) {
         product_inline(J, L, q, ep, lin, p.pid, ir, iz, KARL_CUTOFF);
         push = false;
     }
     bool dq;
-    const unsigned long long si = reserve_product(J, G, q, push, &dq);
+    const unsigned long long si = reserve_product(L, G, q, push, &dq);
     if (push) {
         if (si < (unsigned long long)G.capacity)
             queue_write(dq ? G.qdef : G.qout, si, xc, yc, z, dn, ep, lin, p.pid, pack_meta(q, ir, iz),
@@ -865,12 +853,11 @@ __device__ void k_clustering(const DevJob& J, const Lds<Real>& L, const GenArgs&
 // Charge exchange (Sec. 3.3): the projectile continues with the velocity of a target particle,
 // drawn as for elastic scattering.
 template <typename Real>
-__device__ void k_charge_exchange(const DevJob& J, Part<Real>& p) {
-    Real V[3];
-    thermal(J, p, 2u, 3u, V);
+__device__ double k_charge_exchange(const DevJob& J, const Lds<Real>& L, Part<Real>& p, Vec3<Real> tv) {
+    const Real V[3] = {tv.x, tv.y, tv.z};
     const Real e0 = p.e;
-    set_velocity(p, (Real)spv(J.e_from_v2, p.sp), V);
-    p.e_gas += (double)(e0 - p.e);
+    set_velocity(p, (Real)L.sc->e_from_v2[p.sp], V);
+    return (double)(e0 - p.e);
 }
 
 // ---------------------------------------------------------------- birth (Sec. 3.5)
@@ -965,13 +952,13 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     p.s_path = (Real)0;
     p.alive = true;
     p.fly = false;
-    p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)spv(J.v2_from_e, p.sp)) : (Real)0;
+    p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)L.sc->v2_from_e[p.sp]) : (Real)0;
     p.dg = mix64(p.lin ^ kDIGEST0);
     atomicAdd(&L.cnt[KARL_C_BIRTH + p.sp], 1ull);
     if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 2], 1.0);
     ev(p, 1u, (uint32_t)p.sp, (uint32_t)(p.ir * J.n_z + p.iz), dig);
-    if (!spv(J.tracked, p.sp)) { kill(J, L, p, KARL_UNTRACKED); return; }
-    if (p.e < (Real)spv(J.e_cut, p.sp)) { kill(J, L, p, KARL_CUTOFF); return; }
+    if (!L.sc->tracked[p.sp]) { kill(J, L, p, KARL_UNTRACKED); return; }
+    if (p.e < (Real)L.sc->e_cut[p.sp]) { kill(J, L, p, KARL_CUTOFF); return; }
     if (!(p.vel > (Real)0)) { kill(J, L, p, KARL_LIFETIME); return; }
     if (J.gc) {
         if (gc_set(J, L, p, lc, p.x, p.y, true)) {
@@ -1030,9 +1017,9 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     // the process metadata below become scalar loads
     const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
     // cross sections at the current energy, rates in the current cell (eq. 1)
-    const Real exs = p.e * (Real)spv(J.gfrac, sp);
-    const Real xl = klog(exs * (Real)spv(J.inv_emin, sp)) *
-                    (Real)spv(J.inv_dlog, sp);
+    const Real exs = p.e * (Real)L.sc->gfrac[sp];
+    const Real xl = klog(exs * (Real)L.sc->inv_emin[sp]) *
+                    (Real)L.sc->inv_dlog[sp];
     int k;
     Real f;
     if (!(xl > (Real)0)) {
@@ -1047,8 +1034,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     }
     const Real n_gas_cell = L.ngas[p.iz];
     // density field of the partner species (Sec. 2.2), for processes that target it
-    const Real n_fld_cell = field_density<Real>(J, sp, p.ir, p.iz);
-    const int np = spv(J.nps, sp);
+    const Real n_fld_cell = field_density<Real>(J, L, sp, p.ir, p.iz);
+    const int np = L.sc->nps[sp];
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
     for (int j = 0; j < np; ++j) sum += proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
@@ -1134,8 +1121,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), dig);
         Real xc = p.x, yc = p.y;
         if (J.gc) {
-            const Real om = (Real)spv(J.omega, sp);
-            const Real iom = (Real)spv(J.inv_om, sp);
+            const Real om = (Real)L.sc->omega[sp];
+            const Real iom = (Real)L.sc->inv_om[sp];
             const Real al = -(om * (p.s_path / p.vel));
             Real sa, ca;
             ksincos(al, &sa, &ca);
@@ -1147,15 +1134,27 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             yc = p.y + (p.vel * p.u) * iom;
         }
         bool killed = false;
-        switch (L.kind[pi]) {
+        const int kd = L.kind[pi];
+        // every class but excitation and recombination starts from a target particle's velocity
+        // (slots 2 and 3 of the step): drawn once here for all of them
+        Vec3<Real> tv{(Real)0, (Real)0, (Real)0};
+        if (kd != KARL_EXCITATION && kd != KARL_RECOMBINATION) {
+            Real V[3];
+            thermal(J, p, 2u, 3u, V);
+            tv = Vec3<Real>{V[0], V[1], V[2]};
+        }
+        // energy losses of the collision, added once after it (one update site per ledger keeps
+        // the loss accumulators in registers)
+        double d_exc = 0.0, d_gas = 0.0;
+        switch (kd) {
             case KARL_ELASTIC:
-                k_elastic(J, p, pi);
+                d_gas = k_elastic(J, L, p, pi, tv);
                 break;
             case KARL_EXCITATION: {
                 const Real ex = L.eth[pi];
                 p.e = p.e - ex;
-                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)spv(J.v2_from_e, sp)) : (Real)0;
-                p.e_exc += (double)ex;
+                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)L.sc->v2_from_e[sp]) : (Real)0;
+                d_exc = (double)ex;
                 break;
             }
             case KARL_IONIZATION:
@@ -1165,18 +1164,18 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                     kill(J, L, p, KARL_LIFETIME);
                     killed = true;
                 } else {
-                    k_ionization(J, L, G, p, pi, xc, yc, lc);
+                    k_ionization(J, L, G, p, pi, xc, yc, lc, tv);
                 }
                 break;
             case KARL_CHARGE_EXCHANGE:
-                k_charge_exchange(J, p);
+                d_gas = k_charge_exchange(J, L, p, tv);
                 break;
             case KARL_CLUSTERING:
                 if constexpr (kDrain) {
                     atomicOr(J.status, STATUS_NUMERIC);
                     kill(J, L, p, KARL_LIFETIME);
                 } else {
-                    k_clustering(J, L, G, p, pi, xc, yc);
+                    k_clustering(J, L, G, p, pi, xc, yc, tv);
                 }
                 killed = true;
                 break;
@@ -1188,8 +1187,10 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
                 break;
         }
         if (!killed) {
-            if (p.e < (Real)spv(J.e_cut, sp)) kill(J, L, p, KARL_CUTOFF);
-            else if (p.n_int >= spv(J.cap, sp)) kill(J, L, p, KARL_CAP);
+            p.e_exc += d_exc;
+            p.e_gas += d_gas;
+            if (p.e < (Real)L.sc->e_cut[sp]) kill(J, L, p, KARL_CUTOFF);
+            else if (p.n_int >= L.sc->cap[sp]) kill(J, L, p, KARL_CAP);
             else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
             else if (J.gc) {
                 if (gc_set(J, L, p, lc, xc, yc, false)) {
@@ -1233,7 +1234,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         else p.ir = out ? fr : fr - 1;
     }
     p.s += 1u;
-    if (p.alive && p.t_alive >= spv(J.lifetime, sp)) kill(J, L, p, KARL_LIFETIME);
+    if (p.alive && p.t_alive >= L.sc->lifetime[sp]) kill(J, L, p, KARL_LIFETIME);
 }
 
 
@@ -1279,9 +1280,9 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
     const int izc = inside ? izk : iz;              // lanes past the tube end load valid cells
     const int fz = dir ? izc + 1 : izc;             // far face of segment k
     // rates in the segment's cell at the particle's energy (the arithmetic of step())
-    const Real exs = e * (Real)spv(J.gfrac, sp);
-    const Real xl = klog(exs * (Real)spv(J.inv_emin, sp)) *
-                    (Real)spv(J.inv_dlog, sp);
+    const Real exs = e * (Real)L.sc->gfrac[sp];
+    const Real xl = klog(exs * (Real)L.sc->inv_emin[sp]) *
+                    (Real)L.sc->inv_dlog[sp];
     int kt;
     Real f;
     if (!(xl > (Real)0)) {
@@ -1295,8 +1296,8 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
         f = xl - (Real)kt;
     }
     const Real n_gas_cell = L.ngas[izc];
-    const Real n_fld_cell = field_density<Real>(J, sp, ir, izc);
-    const int np = spv(J.nps, sp);
+    const Real n_fld_cell = field_density<Real>(J, L, sp, ir, izc);
+    const int np = L.sc->nps[sp];
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     Real sum = (Real)0;
     for (int q = 0; q < np; ++q) sum += proc_rate(J, L, pidx[q], exs, kt, f, n_gas_cell, n_fld_cell);
@@ -1323,7 +1324,7 @@ __device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& 
     // the flight (the particle is deleted after that crossing)
     double ta = bc_r(p.t_alive, j);
     Real path = bc_r(p.s_path, j);
-    const double life = spv(J.lifetime, sp);
+    const double life = L.sc->lifetime[sp];
     bool life_end = false;
     for (int kk = 0; kk < m; ++kk) {
         ta += (double)bc_r(dt, kk);
@@ -1391,7 +1392,7 @@ template <typename Real>
 __device__ __forceinline__ Lds<Real> global_view(const DevJob& J, unsigned long long* cnt, double* led) {
     return Lds<Real>{cnt, led, &J.pidx[0][0], J.kind, J.target, EthOf<Real>::get(J),
                      (const Real*)J.xs, (const Real*)J.n_gas, (const Real*)J.zf, (const Real*)J.rf,
-                     true};
+                     &J.sc, true};
 }
 
 // Per-wave LDS counter slots of batched launches: each wave keeps the counters and ledger of up
@@ -1581,6 +1582,9 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         Real* s_ngas = s_xs + (size_t)J.n_proc * J.n_e;
         Real* s_zf = s_ngas + J.n_z;
         Real* s_rf = s_zf + (J.n_z + 1);
+        // species constants after the tables, at an 8-byte aligned offset of the LDS block
+        const size_t sc_off = ((size_t)((unsigned char*)(s_rf + (J.n_r + 1)) - lds_raw) + 7) & ~(size_t)7;
+        SpeciesConst* s_sc = (SpeciesConst*)(lds_raw + sc_off);
         for (int i = tid; i < kNCnt; i += blockDim.x) s_cnt[i] = 0ull;
         for (int i = tid; i < kNLed; i += blockDim.x) s_led[i] = 0.0;
         for (int i = tid; i < kS * KARL_MAX_PROC; i += blockDim.x) s_pidx[i] = J.pidx[i / KARL_MAX_PROC][i % KARL_MAX_PROC];
@@ -1597,8 +1601,12 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         for (int i = tid; i <= J.n_z; i += blockDim.x) s_zf[i] = g_zf[i];
         const Real* g_rf = (const Real*)J.rf;
         for (int i = tid; i <= J.n_r; i += blockDim.x) s_rf[i] = g_rf[i];
+        static_assert(sizeof(SpeciesConst) % 8 == 0, "species constants copied in 8-byte words");
+        const unsigned long long* g_sc = (const unsigned long long*)&J.sc;
+        for (int i = tid; i < (int)(sizeof(SpeciesConst) / 8); i += blockDim.x)
+            ((unsigned long long*)s_sc)[i] = g_sc[i];
         __syncthreads();
-        L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf, false};
+        L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf, s_sc, false};
     }
 
     // batched: this wave's counter slots and their job tags
@@ -1750,7 +1758,7 @@ __global__ void target_fields_kernel(const DevJob J, double t_sim) {
         const double vol = kPI * (r1 * r1 - r0 * r0) * dz;
         double d = J.dens[t] / (t_sim * vol);
         d -= (double)J.recomb[t] / vol;
-        if (J.field[s]) J.field[s][cell] = d > 0.0 ? d : 0.0;
+        if (J.sc.field[s]) J.sc.field[s][cell] = d > 0.0 ? d : 0.0;
     }
 }
 
@@ -1805,6 +1813,7 @@ size_t lds_bytes(const DevJob& j, int precision) {
     size_t b = (size_t)(kNCnt + kNLed) * 8 + (size_t)(kS + 2) * KARL_MAX_PROC * sizeof(int32_t);
     b += rs * KARL_MAX_PROC;
     b += rs * ((size_t)j.n_proc * j.n_e + (size_t)j.n_z + (size_t)(j.n_z + 1) + (size_t)(j.n_r + 1));
+    b += 8 + sizeof(SpeciesConst);   // alignment slack and the species constants
     return (b + 15) & ~(size_t)15;
 }
 
