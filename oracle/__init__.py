@@ -29,7 +29,7 @@ NREASON = 9
 C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 4, 8, 12, 16
 C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES = 20, 21, 22
 C_PROC, C_DEATH = 24, 40
-L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 37, 38, 39, 40
+L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE, L_E_FIELD = 0, 1, 37, 38, 39, 40, 44
 
 
 def build(force: bool = True) -> str:
@@ -70,7 +70,11 @@ class _Desc(C.Structure):
                 ("beam_pos", C.c_double * 3), ("beam_dir", C.c_double * 3),
                 ("beam_energy_1", C.c_double), ("seed", C.c_uint32), ("n_bins", C.c_int32), ("n_planes", C.c_int32),
                 ("pad2", C.c_int32), ("planes", C.POINTER(C.c_int32)),
-                ("n_primaries", C.c_int64), ("n_dens_bins", C.c_int32), ("pad3", C.c_int32)]
+                ("n_primaries", C.c_int64), ("n_dens_bins", C.c_int32), ("mover", C.c_int32),
+                ("boris_dt", C.c_double * MAX_SPECIES), ("field_nr", C.c_int32),
+                ("field_nz", C.c_int32), ("field_radius", C.c_double),
+                ("field_length", C.c_double), ("e_field", C.POINTER(C.c_double)),
+                ("b_field", C.POINTER(C.c_double))]
 
 
 class _Tallies(C.Structure):
@@ -117,6 +121,9 @@ def lib():
         L.ko_debug_collide.restype = C.c_int
         L.ko_debug_angle.argtypes = [C.POINTER(_Desc), C.c_int, C.c_double, C.c_double]
         L.ko_debug_angle.restype = C.c_double
+        L.ko_debug_boris.argtypes = [C.POINTER(_Desc), C.c_int, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
+        L.ko_debug_boris.restype = C.c_int
         L.ko_debug_helix.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_double, C.c_double,
                                      C.POINTER(C.c_double)]
@@ -222,6 +229,25 @@ class Desc:
         d.n_planes = len(planes)
         d.planes = planes.ctypes.data_as(C.POINTER(C.c_int32))
         d.n_primaries = w.n_primaries
+        # mover and field arrays (Sec. 3.1 "Boris mover"; VectorFieldFromArray)
+        d.mover = getattr(w, "mover", 0)
+        for s, dt in enumerate(getattr(w, "boris_dt", None) or []):
+            d.boris_dt[s] = dt
+        shapes = set()
+        for name in ("e_field", "b_field"):
+            arr = getattr(w, name, None)
+            if arr is not None:
+                a = np.ascontiguousarray(arr, dtype=np.float64)
+                if a.ndim != 3 or a.shape[2] != 3:
+                    raise ValueError(f"{name} must have shape [nr][nz][3]")
+                shapes.add(a.shape)
+                if len(shapes) > 1:
+                    raise ValueError("e_field and b_field share one binning")
+                self.keep.append(a)
+                setattr(d, name, _dptr(a))
+                d.field_nr, d.field_nz = a.shape[0], a.shape[1]
+                d.field_radius = w.field_radius
+                d.field_length = w.field_length
         self.d = d
 
 
@@ -329,6 +355,19 @@ def angle(w, proc: int, e_cm: float, u: float) -> float:
     """Polar centre-of-mass scattering angle of elastic process `proc` (rad)."""
     D = Desc(w)
     return float(lib().ko_debug_angle(C.byref(D.d), int(proc), float(e_cm), float(u)))
+
+
+def boris(w, sp: int, pos, vel, n: int) -> np.ndarray:
+    """n Boris pushes of a particle of species sp (no segments, no interactions):
+    position (m) and velocity (m/s)."""
+    D = Desc(w)
+    x = np.ascontiguousarray(pos, dtype=np.float64)
+    v = np.ascontiguousarray(vel, dtype=np.float64)
+    out = np.zeros(6)
+    rc = lib().ko_debug_boris(C.byref(D.d), int(sp), _dptr(x), _dptr(v), int(n), _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the Boris push")
+    return out
 
 
 def helix(charge, mass, bz, pos, direction, speed, path) -> np.ndarray:

@@ -17,6 +17,11 @@
  *     field when the particle leaves it (Sec. 3.1, eq. (3) numerator).
  *   - drift mover for a uniform axial field without electric field: exact helix about
  *     the guiding centre (Sec. 3.1 "Drift mover" and "Comparison").
+ *   - Boris mover (Sec. 3.1 "Boris mover"): pushes of a fixed time step per species with the
+ *     electric and magnetic fields of the particle's cylindrical field bin; the movement ends
+ *     when the particle leaves the domain, its segment or its energy bin (no interaction, a
+ *     new distance is drawn) or when the moved distance exceeds the drawn one (interaction
+ *     at the current position); the time counter of the movement goes to its segment.
  *   - terminator: geometry, interaction cap, lifetime; deletion logger (Sec. 3.2).
  *   - interactions (Sec. 3.3): elastic scattering with a thermal target and a CM-frame
  *     rotation; excitation E' = E - E_x without deflection; ionization with target
@@ -262,6 +267,8 @@ typedef struct {
     double v2_from_e[KO_MAX_SPECIES]; /* v^2 = E(eV) * v2_from_e = E 2 e / m */
     double sigma_v;      /* thermal target speed scale sqrt(kT/M) */
     double conv[KO_MAX_PROC];         /* clustering: M / m_product (momentum of the target) */
+    int boris;                        /* Boris mover */
+    double boris_h[KO_MAX_SPECIES];   /* q dt / (2 m) of the Boris push */
     int32_t nps[KO_MAX_SPECIES];
     int32_t pidx[KO_MAX_SPECIES][KO_MAX_PROC];
     /* compensated accumulators */
@@ -355,7 +362,20 @@ static int ctx_init(ctx_t* c, const ko_desc* d, ko_tallies* t) {
     }
     if (d->source == KO_SOURCE_BEAM && (d->beam_species < 0 || d->beam_species >= c->n_species))
         return -1;
-    c->gc = (d->bz != 0.0);
+    c->boris = (d->mover == KO_MOVER_BORIS);
+    if (d->mover != KO_MOVER_DRIFT && d->mover != KO_MOVER_BORIS) return -1;
+    if (!c->boris && (d->e_field || d->b_field)) return -1;   /* the drift mover: uniform B only */
+    if ((d->e_field || d->b_field) &&
+        (d->field_nr < 1 || d->field_nz < 1 || !(d->field_radius > 0.0) || !(d->field_length > 0.0)))
+        return -1;
+    if (c->boris)
+        for (int s = 0; s < c->n_species; ++s) {
+            const double dt = d->boris_dt[s];
+            if (!(dt > 0.0) || !(d->sp[s].lifetime < INFINITY) || !(d->sp[s].lifetime / dt <= 2147483648.0))
+                return -1;
+            c->boris_h[s] = 0.5 * dt * d->sp[s].charge / d->sp[s].mass;
+        }
+    c->gc = (d->bz != 0.0) && !c->boris;
     return 0;
 }
 
@@ -760,6 +780,257 @@ static void k_charge_exchange(ctx_t* c, part_t* p, double* gas) {
 }
 
 /* ------------------------------------------------------------------ */
+/* rates and interaction, shared by both movers                        */
+/* ------------------------------------------------------------------ */
+/* rate[j] = n_target sigma_j of every process of the particle's species in its current cell
+   (eq. 1); returns their sum */
+static double rates(ctx_t* c, part_t* p, double* rate) {
+    const ko_desc* d = c->d;
+    if (p->e != p->e_rates) eval_sigmas(c, p);
+    const int np = c->nps[p->sp];
+    const int32_t* pidx = c->pidx[p->sp];
+    double sum = 0.0;
+    for (int j = 0; j < np; ++j) {
+        const ko_process* pr = &d->proc[pidx[j]];
+        if (pr->target == KO_TARGET_GAS) {
+            double n = d->n_gas[p->iz];
+            /* three-body clustering: rate k n^2, written as n (n sigma) with sigma = k/v */
+            rate[j] = (pr->density_power == 2) ? n * (n * p->sig[j]) : n * p->sig[j];
+        } else {
+            /* the density field of the partner species (Sec. 2.2) */
+            const double* f = d->n_field[pr->partner];
+            double nt = f ? f[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
+            rate[j] = nt * p->sig[j];
+        }
+        sum += rate[j];
+    }
+    return sum;
+}
+
+/* The interaction (Sec. 2.1: chosen with weight sigma_i n_i) at position (xc, yc, p->z), and the
+   terminator's checks after it. */
+static void interact(ctx_t* c, part_t* p, const double* rate, double sum, double xi, double xc,
+                     double yc) {
+    const ko_desc* d = c->d;
+    ko_tallies* T = c->t;
+    const ko_species* S = &d->sp[p->sp];
+    const int np = c->nps[p->sp];
+    const int32_t* pidx = c->pidx[p->sp];
+    double target = xi * sum;
+    double run = 0.0;
+    int sel = -1, last = -1;
+    for (int j = 0; j < np; ++j) {
+        run += rate[j];
+        if (rate[j] > 0.0) last = j;
+        if (sel < 0 && target < run) sel = j;
+    }
+    if (sel < 0) sel = last;
+    int pi = pidx[sel];
+    const ko_process* pr = &d->proc[pi];
+    T->counters[KO_C_COLL + p->sp] += 1;
+    T->counters[KO_C_PROC + pi] += 1;
+    p->n_int += 1;
+    ev(p, 2, (uint32_t)pi, (uint32_t)(p->ir * d->n_z + p->iz));
+    int killed = 0;
+    if (pr->kind == KO_ELASTIC) {
+        double gas;
+        k_elastic(c, p, pi, &gas);
+        p->e_gas += gas;
+    } else if (pr->kind == KO_EXCITATION) {
+        p->e = p->e - pr->e_th;
+        p->vel = (p->e > 0.0) ? sqrt(p->e * c->v2_from_e[p->sp]) : 0.0;
+        p->e_exc += pr->e_th;
+    } else if (pr->kind == KO_IONIZATION) {
+        products_t out;
+        k_ionization(c, p, pi, xc, yc, &out);
+        p->e_bind += pr->e_th;
+        p->e_gas += out.gas;
+        for (int j = 0; j < out.n; ++j) push(c, &out.s[j]);
+    } else if (pr->kind == KO_CHARGE_EXCHANGE) {
+        double gas;
+        k_charge_exchange(c, p, &gas);
+        p->e_gas += gas;
+    } else if (pr->kind == KO_CLUSTERING) {
+        seed_t prod;
+        double gas;
+        k_clustering(c, p, pi, xc, yc, &prod, &gas);
+        p->e_gas += gas;
+        kill(c, p, KO_CONVERTED);
+        push(c, &prod);
+        killed = 1;
+    } else { /* recombination: one deletion logged in the partner's field (Sec. 3.3) */
+        T->recomb[((size_t)pr->partner * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz] += 1;
+        kill(c, p, KO_RECOMBINED);
+        killed = 1;
+    }
+    if (!killed) {
+        if (p->e < S->e_cut) kill(c, p, KO_CUTOFF);
+        else if (p->n_int >= S->cap) kill(c, p, KO_CAP);
+        else if (!(p->vel > 0.0)) kill(c, p, KO_LIFETIME);
+        else if (c->gc) {
+            if (gc_set(c, p, xc, yc, 0)) {
+                cross_r(c, p, d->n_r, 1);
+                kill(c, p, KO_WALL);
+            }
+        }
+    }
+}
+
+/* crossing of z-face f in direction dir (1: +z) in the particle's ring: current collector and
+   spectrum plane */
+static void cross_z(ctx_t* c, part_t* p, int f, int dir) {
+    const ko_desc* d = c->d;
+    ko_tallies* T = c->t;
+    T->counters[KO_C_ZCROSS + p->sp] += 1;
+    T->jz[(((size_t)p->sp * d->n_r + (size_t)p->ir) * (d->n_z + 1) + (size_t)f) * 2 + (size_t)dir] += 1;
+    ev(p, 3, (uint32_t)dir, (uint32_t)(p->ir * (d->n_z + 1) + f));
+    int pl = c->plane_of[f];
+    if (pl >= 0) {
+        int bin = find_bin(d->sp[p->sp].edges, d->n_bins, p->e);
+        T->spectra[(((size_t)p->sp * d->n_planes + (size_t)pl) * 2 + (size_t)dir) * (d->n_bins + 2) + (size_t)bin] += 1;
+        ev(p, 5, (uint32_t)(pl * 2 + dir), (uint32_t)bin);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Boris mover (Sec. 3.1 "Boris mover")                                */
+/* ------------------------------------------------------------------ */
+/* field vector of array `arr` ([field_nr][field_nz] bins of (r, phi, z) components over the
+   field's radius and height) at (x, y, z) in Cartesian components; zero outside the binning */
+static void field_at(const ko_desc* d, const double* arr, double x, double y, double z, double out[3]) {
+    out[0] = out[1] = out[2] = 0.0;
+    if (!arr) return;
+    double r = sqrt(x * x + y * y);
+    if (!(r < d->field_radius) || !(z >= 0.0) || !(z < d->field_length)) return;
+    int ir = (int)((r / d->field_radius) * (double)d->field_nr);
+    int iz = (int)((z / d->field_length) * (double)d->field_nz);
+    if (ir > d->field_nr - 1) ir = d->field_nr - 1;
+    if (iz > d->field_nz - 1) iz = d->field_nz - 1;
+    const double* f = arr + ((size_t)ir * d->field_nz + (size_t)iz) * 3;
+    double cp = 1.0, sp = 0.0;
+    if (r > 0.0) { cp = x / r; sp = y / r; }
+    out[0] = f[0] * cp - f[1] * sp;
+    out[1] = f[0] * sp + f[1] * cp;
+    out[2] = f[2];
+}
+
+/* one push: half an electric kick, the magnetic rotation with Omega = h B and
+   t = 2 Omega / (1 + Omega.Omega), the second half kick (h = q dt / 2m), then x += v dt */
+static void boris_push(const ctx_t* c, part_t* p, double dt) {
+    const ko_desc* d = c->d;
+    double E[3], B[3];
+    field_at(d, d->e_field, p->x, p->y, p->z, E);
+    if (d->b_field) field_at(d, d->b_field, p->x, p->y, p->z, B);
+    else { B[0] = 0.0; B[1] = 0.0; B[2] = d->bz; }
+    const double h = c->boris_h[p->sp];
+    double v[3] = {p->vel * p->u, p->vel * p->v, p->vel * p->w};
+    double vm[3] = {v[0] + h * E[0], v[1] + h * E[1], v[2] + h * E[2]};
+    double W[3] = {h * B[0], h * B[1], h * B[2]};
+    double f = 2.0 / (1.0 + (W[0] * W[0] + W[1] * W[1] + W[2] * W[2]));
+    double t[3] = {f * W[0], f * W[1], f * W[2]};
+    double vp[3] = {vm[0] + (vm[1] * W[2] - vm[2] * W[1]),
+                    vm[1] + (vm[2] * W[0] - vm[0] * W[2]),
+                    vm[2] + (vm[0] * W[1] - vm[1] * W[0])};
+    double vq[3] = {vm[0] + (vp[1] * t[2] - vp[2] * t[1]),
+                    vm[1] + (vp[2] * t[0] - vp[0] * t[2]),
+                    vm[2] + (vp[0] * t[1] - vp[1] * t[0])};
+    double vn[3] = {vq[0] + h * E[0], vq[1] + h * E[1], vq[2] + h * E[2]};
+    p->x = p->x + vn[0] * dt;
+    p->y = p->y + vn[1] * dt;
+    p->z = p->z + vn[2] * dt;
+    set_velocity(p, c->e_from_v2[p->sp], vn);
+}
+
+/* end of a movement: its time to the segment (and energy bin) it was spent in, the work of
+   the electric field on it to the ledger */
+static void end_movement(ctx_t* c, part_t* p, double e0m, int eb) {
+    const ko_desc* d = c->d;
+    if (c->dense_s && p->t_cell != 0.0) {
+        size_t k = ((((size_t)p->sp * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz) *
+                    (size_t)(d->n_dens_bins + 2)) + (size_t)eb;
+        nadd(&c->dense_s[k], &c->dense_c[k], p->t_cell);
+    }
+    flush_time(c, p);
+    double work = p->e - e0m;
+    if (work != 0.0) {
+        ledger_add(c, KO_L_E_FIELD, work);
+        hist_add(c, p, 1, -work);
+    }
+}
+
+static void transport_boris(ctx_t* c, part_t* p) {
+    const ko_desc* d = c->d;
+    ko_tallies* T = c->t;
+    const ko_species* S = &d->sp[p->sp];
+    const double dt = d->boris_dt[p->sp];
+    double rate[KO_MAX_PROC];
+    int moving = 0, eb = 0;
+    double dr = 0.0, e0m = 0.0;
+    while (p->alive) {
+        if (!moving) {
+            /* a new distance from the mean free path at the current position, eq. (2) */
+            double sum = rates(c, p, rate);
+            pair_t q0 = draw(d->seed, p->pid, p->lineage, p->s, 0);
+            dr = (sum > 0.0) ? -ko_log(q0.d0 + TWO_M53) / sum : INFINITY;
+            moving = 1;
+            e0m = p->e;
+            eb = c->dense_s ? find_bin(S->dens_edges, d->n_dens_bins, p->e) : 0;
+        }
+        boris_push(c, p, dt);
+        dr -= p->vel * dt;
+        p->t_cell += dt;
+        p->t_alive += dt;
+        T->counters[KO_C_STEP + p->sp] += 1;
+        double r = sqrt(p->x * p->x + p->y * p->y);
+        if (p->z < 0.0) {
+            end_movement(c, p, e0m, eb);
+            for (int f = p->iz; f >= 0; --f) cross_z(c, p, f, 0);
+            kill(c, p, KO_EXIT_LOW);
+        } else if (!(p->z < d->length)) {
+            end_movement(c, p, e0m, eb);
+            for (int f = p->iz + 1; f <= d->n_z; ++f) cross_z(c, p, f, 1);
+            kill(c, p, KO_EXIT_HIGH);
+        } else {
+            int niz = count_faces_le(c->zf, d->n_z, p->z);
+            int nir = count_faces_le(c->rf, d->n_r, r);
+            int wall = !(r < d->radius);
+            if (wall || niz != p->iz || nir != p->ir) {
+                /* left the segment: the movement stops without an interaction */
+                end_movement(c, p, e0m, eb);
+                moving = 0;
+                if (niz > p->iz) for (int f = p->iz + 1; f <= niz; ++f) cross_z(c, p, f, 1);
+                else for (int f = p->iz; f > niz; --f) cross_z(c, p, f, 0);
+                p->iz = niz;
+                int rto = wall ? d->n_r : nir;
+                if (rto > p->ir) for (int f = p->ir + 1; f <= rto; ++f) cross_r(c, p, f, 1);
+                else for (int f = p->ir; f > rto; --f) cross_r(c, p, f, 0);
+                if (wall) kill(c, p, KO_WALL);
+                else p->ir = nir;
+            } else if (c->dense_s && find_bin(S->dens_edges, d->n_dens_bins, p->e) != eb) {
+                /* left the energy bin: the movement stops without an interaction */
+                end_movement(c, p, e0m, eb);
+                moving = 0;
+            } else if (dr < 0.0) {
+                /* the drawn distance is used up: interaction here, chosen with the rates at the
+                   current energy and segment (none if they all vanished on the way) */
+                end_movement(c, p, e0m, eb);
+                moving = 0;
+                double sum = rates(c, p, rate);
+                if (sum > 0.0) {
+                    pair_t q = draw(d->seed, p->pid, p->lineage, p->s, 0);
+                    interact(c, p, rate, sum, q.d1, p->x, p->y);
+                }
+            }
+        }
+        p->s += 1;
+        if (p->alive && p->t_alive >= S->lifetime) {
+            if (moving) end_movement(c, p, e0m, eb);
+            kill(c, p, KO_LIFETIME);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* one particle from birth to deletion                                 */
 /* ------------------------------------------------------------------ */
 static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
@@ -791,26 +1062,13 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
         }
     }
 
-    const int np = c->nps[p->sp];
-    const int32_t* pidx = c->pidx[p->sp];
+    if (c->boris) {
+        transport_boris(c, p);
+        return;
+    }
     double rate[KO_MAX_PROC];
     while (p->alive) {
-        if (p->e != p->e_rates) eval_sigmas(c, p);
-        double sum = 0.0;
-        for (int j = 0; j < np; ++j) {
-            const ko_process* pr = &d->proc[pidx[j]];
-            if (pr->target == KO_TARGET_GAS) {
-                double n = d->n_gas[p->iz];
-                /* three-body clustering: rate k n^2, written as n (n sigma) with sigma = k/v */
-                rate[j] = (pr->density_power == 2) ? n * (n * p->sig[j]) : n * p->sig[j];
-            } else {
-                /* the density field of the partner species (Sec. 2.2) */
-                const double* f = d->n_field[pr->partner];
-                double nt = f ? f[(size_t)p->ir * d->n_z + (size_t)p->iz] : 0.0;
-                rate[j] = nt * p->sig[j];
-            }
-            sum += rate[j];
-        }
+        double sum = rates(c, p, rate);
         pair_t q0 = draw(d->seed, p->pid, p->lineage, p->s, 0);
         double eta = q0.d0 + TWO_M53;
         double xi = q0.d1;
@@ -878,21 +1136,6 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
 
         if (dist < sg) {
             /* ---- collision ---- */
-            double target = xi * sum;
-            double run = 0.0;
-            int sel = -1, last = -1;
-            for (int j = 0; j < np; ++j) {
-                run += rate[j];
-                if (rate[j] > 0.0) last = j;
-                if (sel < 0 && target < run) sel = j;
-            }
-            if (sel < 0) sel = last;
-            int pi = pidx[sel];
-            const ko_process* pr = &d->proc[pi];
-            T->counters[KO_C_COLL + p->sp] += 1;
-            T->counters[KO_C_PROC + pi] += 1;
-            p->n_int += 1;
-            ev(p, 2, (uint32_t)pi, (uint32_t)(p->ir * d->n_z + p->iz));
             double xc = p->x, yc = p->y;
             if (c->gc) {
                 double om = c->omega[p->sp], iom = c->inv_om[p->sp];
@@ -906,64 +1149,14 @@ static void transport(ctx_t* c, const seed_t* b, uint32_t pid) {
                 xc = p->x - (p->vel * p->v) * iom;
                 yc = p->y + (p->vel * p->u) * iom;
             }
-            int killed = 0;
-            if (pr->kind == KO_ELASTIC) {
-                double gas;
-                k_elastic(c, p, pi, &gas);
-                p->e_gas += gas;
-            } else if (pr->kind == KO_EXCITATION) {
-                p->e = p->e - pr->e_th;
-                p->vel = (p->e > 0.0) ? sqrt(p->e * c->v2_from_e[p->sp]) : 0.0;
-                p->e_exc += pr->e_th;
-            } else if (pr->kind == KO_IONIZATION) {
-                products_t out;
-                k_ionization(c, p, pi, xc, yc, &out);
-                p->e_bind += pr->e_th;
-                p->e_gas += out.gas;
-                for (int j = 0; j < out.n; ++j) push(c, &out.s[j]);
-            } else if (pr->kind == KO_CHARGE_EXCHANGE) {
-                double gas;
-                k_charge_exchange(c, p, &gas);
-                p->e_gas += gas;
-            } else if (pr->kind == KO_CLUSTERING) {
-                seed_t prod;
-                double gas;
-                k_clustering(c, p, pi, xc, yc, &prod, &gas);
-                p->e_gas += gas;
-                kill(c, p, KO_CONVERTED);
-                push(c, &prod);
-                killed = 1;
-            } else { /* recombination: one deletion logged in the partner's field (Sec. 3.3) */
-                T->recomb[((size_t)pr->partner * d->n_r + (size_t)p->ir) * d->n_z + (size_t)p->iz] += 1;
-                kill(c, p, KO_RECOMBINED);
-                killed = 1;
-            }
-            if (!killed) {
-                if (p->e < S->e_cut) kill(c, p, KO_CUTOFF);
-                else if (p->n_int >= S->cap) kill(c, p, KO_CAP);
-                else if (!(p->vel > 0.0)) kill(c, p, KO_LIFETIME);
-                else if (c->gc) {
-                    if (gc_set(c, p, xc, yc, 0)) {
-                        cross_r(c, p, d->n_r, 1);
-                        kill(c, p, KO_WALL);
-                    }
-                }
-            }
+            interact(c, p, rate, sum, xi, xc, yc);
         } else if (which == 1) {
             /* ---- z-face ---- */
             int f = zface;
             int dir = (p->w > 0.0) ? 1 : 0;
             p->z = c->zf[f];
             flush_time(c, p);
-            T->counters[KO_C_ZCROSS + p->sp] += 1;
-            T->jz[(((size_t)p->sp * d->n_r + (size_t)p->ir) * (d->n_z + 1) + (size_t)f) * 2 + (size_t)dir] += 1;
-            ev(p, 3, (uint32_t)dir, (uint32_t)(p->ir * (d->n_z + 1) + f));
-            int pl = c->plane_of[f];
-            if (pl >= 0) {
-                int bin = find_bin(S->edges, d->n_bins, p->e);
-                T->spectra[(((size_t)p->sp * d->n_planes + (size_t)pl) * 2 + (size_t)dir) * (d->n_bins + 2) + (size_t)bin] += 1;
-                ev(p, 5, (uint32_t)(pl * 2 + dir), (uint32_t)bin);
-            }
+            cross_z(c, p, f, dir);
             if (f == 0) kill(c, p, KO_EXIT_LOW);
             else if (f == d->n_z) kill(c, p, KO_EXIT_HIGH);
             else p->iz = dir ? f : f - 1;
@@ -1192,6 +1385,27 @@ double ko_debug_angle(const ko_desc* d, int proc, double e_cm, double u) {
     if (proc < 0 || proc >= d->n_proc) return -1.0;
     double mu = scatter_mu(&d->proc[proc], e_cm, u);
     return acos(mu);
+}
+
+int ko_debug_boris(const ko_desc* d, int sp, const double x[3], const double v[3], int n,
+                   double out[6]) {
+    ko_tallies dummy;
+    memset(&dummy, 0, sizeof(dummy));
+    ctx_t c;
+    if (ctx_init(&c, d, &dummy) != 0 || !c.boris || sp < 0 || sp >= c.n_species || n < 0) {
+        ctx_free(&c);
+        return -1;
+    }
+    part_t P;
+    memset(&P, 0, sizeof(P));
+    P.sp = sp;
+    P.x = x[0]; P.y = x[1]; P.z = x[2];
+    set_velocity(&P, c.e_from_v2[sp], v);
+    for (int k = 0; k < n; ++k) boris_push(&c, &P, d->boris_dt[sp]);
+    out[0] = P.x; out[1] = P.y; out[2] = P.z;
+    out[3] = P.vel * P.u; out[4] = P.vel * P.v; out[5] = P.vel * P.w;
+    ctx_free(&c);
+    return 0;
 }
 
 void ko_debug_helix(double charge, double mass, double bz, const double pos[3],

@@ -35,6 +35,9 @@ enum { KO_TARGET_GAS = 0, KO_TARGET_FIELD = 1 };
 /* KO_SOURCE_PAIR: both species from the beam position and direction, even primary ids electrons
    at beam_energy, odd ids ions at beam_energy_1 */
 enum { KO_SOURCE_BETA = 0, KO_SOURCE_BEAM = 1, KO_SOURCE_PAIR = 2 };
+/* movers (Sec. 3.1): drift (exact helix in a uniform axial field, straight lines without one)
+   or Boris pushes with electric and magnetic fields from arrays */
+enum { KO_MOVER_DRIFT = 0, KO_MOVER_BORIS = 1 };
 /* KO_CONVERTED: the projectile of a clustering reaction, replaced by its product */
 enum { KO_EXIT_LOW = 0, KO_EXIT_HIGH, KO_WALL, KO_CUTOFF, KO_RECOMBINED, KO_CAP,
        KO_LIFETIME, KO_UNTRACKED, KO_CONVERTED, KO_NREASON };
@@ -61,6 +64,7 @@ enum { KO_EXIT_LOW = 0, KO_EXIT_HIGH, KO_WALL, KO_CUTOFF, KO_RECOMBINED, KO_CAP,
                                   frame, charge exchange, and minus the energy of clustering and
                                   ionization products, whose velocity is a target particle's */
 #define KO_L_T_ALIVE       40  /* [4] summed particle lifetimes (s)               */
+#define KO_L_E_FIELD       44  /* work of the electric field (Boris mover)        */
 #define KO_NLEDGER         48
 
 #define KO_NHIST           4   /* per history: E_in, E_accounted, n_born, n_dead  */
@@ -127,7 +131,16 @@ typedef struct {
     const int32_t* planes;       /* [n_planes] z-face indices */
     int64_t n_primaries;
     int32_t n_dens_bins;         /* energy bins of the density field (Sec. 3.4); 0: none */
-    int32_t pad3;
+    int32_t mover;               /* KO_MOVER_DRIFT or KO_MOVER_BORIS */
+    /* Boris mover: time step per species (s), and the fields as arrays over a cylindrical
+       binning of field_radius x field_length in field_nr x field_nz bins, each bin a vector of
+       (r, phi, z) components; zero outside the binning (VectorFieldFromArray, Sec. 3.8).
+       e_field NULL: no electric field; b_field NULL: the uniform axial field bz */
+    double boris_dt[KO_MAX_SPECIES];
+    int32_t field_nr, field_nz;
+    double field_radius, field_length;
+    const double* e_field;       /* [field_nr][field_nz][3] V/m */
+    const double* b_field;       /* [field_nr][field_nz][3] T */
 } ko_desc;
 
 typedef struct {
@@ -177,6 +190,10 @@ int ko_birth(const ko_desc* d, int64_t pid, double out[8]);
    clustering product is reported as the ion), out[14]=energy to gas, out[15]=w (ionization) */
 int ko_debug_collide(const ko_desc* d, int proc, int64_t pid, uint64_t lineage, uint32_t s,
                      double e, const double dir[3], double out[16]);
+/* n Boris pushes of a particle of species sp from position x[3] with velocity v[3] (m/s),
+   without segments or interactions: out[0..2] position, out[3..5] velocity */
+int ko_debug_boris(const ko_desc* d, int sp, const double x[3], const double v[3], int n,
+                   double out[6]);
 /* helix: position and direction after path length `path` (guiding-centre formulas) */
 void ko_debug_helix(double charge, double mass, double bz, const double pos[3],
                     const double dir[3], double speed, double path, double out[6]);

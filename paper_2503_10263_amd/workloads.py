@@ -59,6 +59,10 @@ TARGET_GAS = 0
 TARGET_FIELD = 1            # the density field of the process's partner species
 TARGET_ION_FIELD = TARGET_FIELD
 
+# movers (Sec. 3.1): drift (helix / straight line) or Boris pushes with field arrays
+MOVER_DRIFT = 0
+MOVER_BORIS = 1
+
 # primary source
 SOURCE_BETA = 0
 SOURCE_BEAM = 1
@@ -156,6 +160,12 @@ class Workload:
     dens_edges: Optional[tuple] = None    # per-species energy-bin edges of the density field
     beam_energy_1: float = 0.0            # eV: ion energy of SOURCE_PAIR
     extra_fields: Optional[dict] = None   # slot (2, 3) -> [n_r*n_z] m^-3 density field
+    mover: int = MOVER_DRIFT
+    boris_dt: Optional[list] = None       # s, per species (Boris mover)
+    e_field: Optional[np.ndarray] = None  # [nr][nz][3] (E_r, E_phi, E_z) V/m over the field binning
+    b_field: Optional[np.ndarray] = None  # [nr][nz][3] (B_r, B_phi, B_z) T; None: (0, 0, bz)
+    field_radius: float = 0.0             # m, extent of the field binning
+    field_length: float = 0.0
 
     @property
     def n_bins(self) -> int:
@@ -555,6 +565,25 @@ def hydrogen_chemistry(n_primaries: int = 4000, bz: float = 2.5, column_cm2: flo
         n_gas=np.full(n_z, n), n_ion=None, t_gas=80.0, m_gas=M_H2, bz=bz, species=species,
         processes=procs, n_e=n_e, source=SOURCE_BETA, seed=seed, planes=[0, n_z // 2, n_z],
         n_primaries=n_primaries, n_elec=n_e_field, extra_fields={3: n_h3_field})
+
+
+def uniform_vector_field(nr: int, nz: int, vec_cyl) -> np.ndarray:
+    """[nr][nz][3] array holding the same (r, phi, z) components in every bin."""
+    return np.tile(np.asarray(vec_cyl, np.float64), (nr, nz, 1))
+
+
+def with_boris(w: Workload, dt, lifetime, e_field=None, b_field=None, field_radius=None,
+               field_length=None) -> Workload:
+    """Switch a workload to the Boris mover (Sec. 3.1): time step and (finite) lifetime per
+    species, optional field arrays over a cylindrical binning (default: the job's cylinder)."""
+    w.mover = MOVER_BORIS
+    w.boris_dt = list(dt)
+    for sp, life in zip(w.species, lifetime):
+        sp.lifetime = life
+    w.e_field, w.b_field = e_field, b_field
+    w.field_radius = w.radius if field_radius is None else field_radius
+    w.field_length = w.length if field_length is None else field_length
+    return w
 
 
 def with_primaries(w: Workload, n: int) -> Workload:
