@@ -71,6 +71,14 @@ enum { KARL_FP64 = 0, KARL_FP32 = 1 };
    needs nothing from segments before it: results do not depend on the mapping.  Straight-line
    jobs and batched launches use LANE. */
 enum { KARL_MAP_AUTO = 0, KARL_MAP_LANE = 1, KARL_MAP_WAVE = 2 };
+/* movers (Sec. 3.1): KARL_MOVER_DRIFT moves along the exact helix about the guiding centre in
+   the uniform axial field bz (straight lines when bz = 0) and stops at every segment face;
+   KARL_MOVER_BORIS advances each particle by Boris pushes of a fixed time step per species with
+   the electric and magnetic fields of its field bin (one push per transport step), and stops a
+   movement when the particle leaves the domain, its segment or its energy bin (no interaction,
+   a new distance is drawn) or when the moved distance exceeds the drawn one (interaction at the
+   current position).  The time of a movement goes to the segment and energy bin it started in. */
+enum { KARL_MOVER_DRIFT = 0, KARL_MOVER_BORIS = 1 };
 
 /* job flags */
 #define KARL_FLAG_DIGESTS 1u   /* per-primary 64-bit digest of the event sequence          */
@@ -104,6 +112,7 @@ enum { KARL_EXIT_LOW = 0, KARL_EXIT_HIGH, KARL_WALL, KARL_CUTOFF, KARL_RECOMBINE
                                     ionization and clustering products (a target particle's
                                     velocity)                                           */
 #define KARL_L_T_ALIVE       40  /* [4] summed particle lifetimes (s)                   */
+#define KARL_L_E_FIELD       44  /* work of the electric field on the particles (eV)    */
 #define KARL_NLEDGER         48
 
 #define KARL_NHIST            4  /* per-primary ledger entries                          */
@@ -184,6 +193,19 @@ typedef struct {
     int32_t mapping;              /* KARL_MAP_AUTO, KARL_MAP_LANE or KARL_MAP_WAVE */
     int32_t n_dens_bins;          /* energy bins of the energy-resolved density field (Sec. 3.4:
                                      times per segment with an energy axis), 0..4096; 0: none */
+    int32_t mover;                /* KARL_MOVER_DRIFT or KARL_MOVER_BORIS */
+    int32_t reserved1;
+    /* Boris mover: time step per species (s; every species of the job needs one, and a finite
+       lifetime of at most 2^31 steps so that every particle ends).  Fields as arrays over a
+       cylindrical binning of field_radius x field_length in field_nr x field_nz bins, each bin a
+       vector of (r, phi, z) components, zero outside the binning (Sec. 3.8 "Vector field",
+       from arrays); e_field NULL: no electric field, b_field NULL: the uniform axial field bz.
+       The drift mover takes no field arrays. */
+    double boris_dt[KARL_MAX_SPECIES];
+    int32_t field_nr, field_nz;
+    double field_radius, field_length;
+    const double* e_field;        /* [field_nr][field_nz][3] V/m */
+    const double* b_field;        /* [field_nr][field_nz][3] T */
 } karl_job_desc;
 
 /* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements, with

@@ -47,7 +47,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte offsets of every region of a job's workspace.
 struct Layout {
-    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of, angles, dens_edges;
+    size_t devjob, xs, n_gas, zf, rf, zcdf, tfield, edges, plane_of, angles, dens_edges, e_fld, b_fld;
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist, t_dense;
     size_t snapshot, control, fields, queues, queue_entries;
@@ -100,6 +100,9 @@ Layout make_layout(const karl_job_desc* d) {
     L.plane_of = take(4 * (nz + 1));
     L.angles = take(8 * angle_doubles(d));
     L.dens_edges = take(d->n_dens_bins > 0 ? 8 * ns * ((size_t)d->n_dens_bins + 1) : 0);
+    const size_t fbins = (size_t)std::max(d->field_nr, 0) * (size_t)std::max(d->field_nz, 0) * 3;
+    L.e_fld = take(d->e_field ? 8 * fbins : 0);
+    L.b_fld = take(d->b_field ? 8 * fbins : 0);
     // tallies: one contiguous block so that a snapshot is one copy
     size_t t = 0;
     auto tk = [&](size_t bytes) {
@@ -251,6 +254,28 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     }
     if (d->n_dens_bins < 0 || d->n_dens_bins > 4096)
         return fail(KARL_EINVAL, "n_dens_bins must be in 0..4096");
+    if (d->mover != KARL_MOVER_DRIFT && d->mover != KARL_MOVER_BORIS)
+        return fail(KARL_EINVAL, "mover must be KARL_MOVER_DRIFT or KARL_MOVER_BORIS");
+    if (d->mover == KARL_MOVER_DRIFT && (d->e_field || d->b_field))
+        return fail(KARL_EINVAL, "field arrays need the Boris mover (the drift mover takes the uniform bz)");
+    if (d->e_field || d->b_field) {
+        if (d->field_nr < 1 || d->field_nr > 65536 || d->field_nz < 1 || d->field_nz > 65536 ||
+            !finite_pos(d->field_radius) || !finite_pos(d->field_length))
+            return fail(KARL_EINVAL, "field arrays need 1..65536 bins per axis and a positive radius and height");
+        const size_t nb = (size_t)d->field_nr * (size_t)d->field_nz * 3;
+        for (const double* a : {d->e_field, d->b_field})
+            if (a)
+                for (size_t k = 0; k < nb; ++k)
+                    if (!std::isfinite(a[k])) return fail(KARL_EINVAL, "field arrays must be finite");
+    }
+    if (d->mover == KARL_MOVER_BORIS)
+        for (int s = 0; s < ns; ++s) {
+            const double dt = d->boris_dt[s];
+            if (!finite_pos(dt)) return fail(KARL_EINVAL, "species %d: the Boris mover needs a time step > 0", s);
+            if (!std::isfinite(d->species[s].lifetime) || !(d->species[s].lifetime / dt <= 2147483648.0))
+                return fail(KARL_EINVAL,
+                            "species %d: the Boris mover needs a finite lifetime of at most 2^31 time steps", s);
+        }
     if (d->n_dens_bins > 0)
         for (int s = 0; s < ns; ++s) {
             const double* e = d->species[s].dens_edges;
@@ -689,7 +714,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->lay = make_layout(d);
     j->chunk = d->chunk > 0 ? d->chunk : kDefaultChunk;
     j->mapping = d->mapping;
-    j->chosen = (d->bz == 0.0) ? KARL_MAP_LANE : d->mapping;   // flights meet r-faces without a field
+    // flights meet r-faces without a field; the Boris mover has no wave-cooperative flight
+    j->chosen = (d->bz == 0.0 || d->mover == KARL_MOVER_BORIS) ? KARL_MAP_LANE : d->mapping;
     const Layout& L = j->lay;
     auto cleanup = [&](karl_status s) {
         j->run.release();
@@ -757,6 +783,11 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
                         sizeof(double) * ((size_t)d->n_dens_bins + 1));
         TRY_HIP(hipMemcpy(j->ws + L.dens_edges, de.data(), sizeof(double) * de.size(), hipMemcpyHostToDevice));
     }
+    if (d->e_field || d->b_field) {
+        const size_t nb = (size_t)d->field_nr * (size_t)d->field_nz * 3;
+        if (d->e_field) TRY_HIP(hipMemcpy(j->ws + L.e_fld, d->e_field, 8 * nb, hipMemcpyHostToDevice));
+        if (d->b_field) TRY_HIP(hipMemcpy(j->ws + L.b_fld, d->b_field, 8 * nb, hipMemcpyHostToDevice));
+    }
     // angle tables with the cumulative areas of the piecewise linear densities (trapezoids,
     // left to right)
     size_t ang_off = 0;
@@ -796,7 +827,15 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     J.n_proc = d->n_proc;
     J.n_bins = d->n_bins;
     J.n_planes = d->n_planes;
-    J.gc = d->bz != 0.0 ? 1 : 0;
+    J.boris = d->mover == KARL_MOVER_BORIS ? 1 : 0;
+    J.gc = (d->bz != 0.0 && !J.boris) ? 1 : 0;   // the Boris mover follows the particle itself
+    J.bz = d->bz;
+    J.field_nr = d->field_nr;
+    J.field_nz = d->field_nz;
+    J.field_radius = d->field_radius;
+    J.field_length = d->field_length;
+    J.e_fld = d->e_field ? (const double*)(j->ws + L.e_fld) : nullptr;
+    J.b_fld = d->b_field ? (const double*)(j->ws + L.b_fld) : nullptr;
     J.source = d->source;
     J.beam_species = d->beam_species;
     J.flags = (int32_t)d->flags;
@@ -814,6 +853,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
             J.sc.mass[s] = J.sc.charge[s] = J.sc.e_cut[s] = J.sc.lifetime[s] = J.sc.msum[s] = 0.0;
             J.sc.xs_emin[s] = J.sc.inv_dlog[s] = J.sc.omega[s] = J.sc.mfrac[s] = J.sc.gfrac[s] = 0.0;
             J.sc.inv_emin[s] = J.sc.inv_om[s] = J.sc.e_from_v2[s] = J.sc.v2_from_e[s] = 0.0;
+            J.sc.boris_dt[s] = J.sc.boris_h[s] = 0.0;
             continue;
         }
         const karl_species_desc& sp = d->species[s];
@@ -834,6 +874,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
         J.sc.inv_om[s] = (J.sc.omega[s] != 0.0) ? 1.0 / J.sc.omega[s] : 0.0;
         J.sc.e_from_v2[s] = 0.5 * sp.mass / kQE;
         J.sc.v2_from_e[s] = 2.0 * kQE / sp.mass;
+        J.sc.boris_dt[s] = d->mover == KARL_MOVER_BORIS ? d->boris_dt[s] : 0.0;
+        J.sc.boris_h[s] = d->mover == KARL_MOVER_BORIS ? 0.5 * d->boris_dt[s] * sp.charge / sp.mass : 0.0;
     }
     for (int i = 0; i < KARL_MAX_PROC; ++i) {
         const bool has_ang = i < d->n_proc && d->proc[i].ang_bins > 0;
@@ -865,7 +907,8 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
             if (d->proc[i].species == s &&
                 (d->proc[i].kind == KARL_IONIZATION || d->proc[i].kind == KARL_CLUSTERING))
                 produces = true;
-        J.sc.defer[s] = produces ? 0 : 1;
+        // the drain launch has no Boris mover: Boris jobs keep every particle in the generations
+        J.sc.defer[s] = (produces || J.boris) ? 0 : 1;
     }
     J.p2scale = p2scale;
     J.sigma_v = std::sqrt(kKB * d->t_gas / d->m_gas);

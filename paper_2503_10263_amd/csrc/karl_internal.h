@@ -49,6 +49,8 @@ struct SpeciesConst {
     double inv_om[kS];     // 1 / omega (0 without field)
     double e_from_v2[kS];  // E(eV) = v^2 * e_from_v2
     double v2_from_e[kS];  // v^2 = E(eV) * v2_from_e
+    double boris_dt[kS];   // Boris time step (s)
+    double boris_h[kS];    // q dt / (2 m) of the Boris push
     double* field[kS];     // [n_r*n_z] density field of each species (m^-3), or NULL
 };
 
@@ -59,6 +61,12 @@ struct DevJob {
     int32_t gc, source, beam_species, flags;
     uint32_t seed;
     int32_t beam_ir, beam_iz, n_species;
+    int32_t boris;               // Boris mover (KARL_MOVER_BORIS)
+    int32_t field_nr, field_nz;  // field binning of e_fld / b_fld
+    double field_radius, field_length;
+    double bz;                   // uniform axial field when b_fld is NULL
+    const double* e_fld;         // [field_nr][field_nz][3] (r, phi, z) components, or NULL
+    const double* b_fld;
     SpeciesConst sc;
     double sigma_v;        // sqrt(k T / m_gas)
     double m_gas;

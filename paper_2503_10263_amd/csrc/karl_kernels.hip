@@ -269,7 +269,10 @@ struct Part {
     int64_t n_int;
     bool alive;
     bool start;            // fetched, not yet started
-    bool fly;              // the last segment ended on a z-face (guiding-centre mode)
+    bool fly;              // guiding-centre mode: the last segment ended on a z-face;
+                           // Boris mover: a movement is under way (s_path: its remaining distance)
+    Real e0m;              // Boris mover: energy at the start of the movement
+    int32_t eb;            // Boris mover: energy bin of the movement (energy-resolved density)
 };
 
 template <typename Real>
@@ -1004,6 +1007,301 @@ __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) 
     return lo + 1;
 }
 
+// crossing of z-face f in direction dir (1: +z) in the particle's ring: current collector and
+// spectrum plane (Sec. 2.3, 3.4)
+template <typename Real>
+__device__ __forceinline__ void cross_z(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc,
+                                        int f, int dir, int sp) {
+    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    count_ev(L, lc, KARL_C_ZCROSS, sp);
+    add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)p.ir) * (J.n_z + 1) + (size_t)f) * 2 + (size_t)dir], 1ull);
+    ev(p, 3u, (uint32_t)dir, (uint32_t)(p.ir * (J.n_z + 1) + f), dig);
+    const int pl = J.plane_of[f];
+    if (pl >= 0) {
+        const int bin = spectrum_bin(J, sp, (double)p.e);
+        add_u64(&J.spectra[(((size_t)sp * J.n_planes + (size_t)pl) * 2 + (size_t)dir) * (J.n_bins + 2) + (size_t)bin], 1ull);
+        ev(p, 5u, (uint32_t)(pl * 2 + dir), (uint32_t)bin, dig);
+    }
+}
+
+// Counters and digest event of an interaction of process pi.
+template <typename Real>
+__device__ __forceinline__ void count_interaction(const DevJob& J, const Lds<Real>& L, LaneCnt& lc,
+                                                  Part<Real>& p, int sp, int pi) {
+    count_ev(L, lc, KARL_C_COLL, sp);
+    wave_count(L.cnt, KARL_C_PROC + pi);
+    p.n_int += 1;
+    ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), (J.flags & KARL_FLAG_DIGESTS) != 0);
+}
+
+// The interaction chosen for process pi (Sec. 2.1, 3.3) at the collision point (xc, yc, p.z),
+// after count_interaction: the kinematics of its class and the terminator's checks after it.
+template <typename Real, int kDrain>
+__device__ __forceinline__ void interact(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+                         LaneCnt& lc, int sp, int pi, Real xc, Real yc) {
+    bool killed = false;
+    const int kd = L.kind[pi];
+    // every class but excitation and recombination starts from a target particle's velocity
+    // (slots 2 and 3 of the step): drawn once here for all of them
+    Vec3<Real> tv{(Real)0, (Real)0, (Real)0};
+    if (kd != KARL_EXCITATION && kd != KARL_RECOMBINATION) {
+        Real V[3];
+        thermal(J, p, 2u, 3u, V);
+        tv = Vec3<Real>{V[0], V[1], V[2]};
+    }
+    // energy losses of the collision, added once after it (one update site per ledger keeps
+    // the loss accumulators in registers)
+    double d_exc = 0.0, d_gas = 0.0;
+    switch (kd) {
+        case KARL_ELASTIC:
+            d_gas = k_elastic(J, L, p, pi, tv);
+            break;
+        case KARL_EXCITATION: {
+            const Real ex = L.eth[pi];
+            p.e = p.e - ex;
+            p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)L.sc->v2_from_e[sp]) : (Real)0;
+            d_exc = (double)ex;
+            break;
+        }
+        case KARL_IONIZATION:
+            if constexpr (kDrain) {
+                // a deferred species makes no products; flag it rather than go on silently
+                atomicOr(J.status, STATUS_NUMERIC);
+                kill(J, L, p, KARL_LIFETIME);
+                killed = true;
+            } else {
+                k_ionization(J, L, G, p, pi, xc, yc, lc, tv);
+            }
+            break;
+        case KARL_CHARGE_EXCHANGE:
+            d_gas = k_charge_exchange(J, L, p, tv);
+            break;
+        case KARL_CLUSTERING:
+            if constexpr (kDrain) {
+                atomicOr(J.status, STATUS_NUMERIC);
+                kill(J, L, p, KARL_LIFETIME);
+            } else {
+                k_clustering(J, L, G, p, pi, xc, yc, tv);
+            }
+            killed = true;
+            break;
+        default:
+            // one deletion logged in the partner's field (Sec. 3.3 "Recombination")
+            add_u64(&J.recomb[((size_t)J.partner[pi] * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], 1ull);
+            kill(J, L, p, KARL_RECOMBINED);
+            killed = true;
+            break;
+    }
+    if (!killed) {
+        p.e_exc += d_exc;
+        p.e_gas += d_gas;
+        if (p.e < (Real)L.sc->e_cut[sp]) kill(J, L, p, KARL_CUTOFF);
+        else if (p.n_int >= L.sc->cap[sp]) kill(J, L, p, KARL_CAP);
+        else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
+        else if (J.gc) {
+            if (gc_set(J, L, p, lc, xc, yc, false)) {
+                cross_r(J, L, p, lc, J.n_r, 1);
+                kill(J, L, p, KARL_WALL);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Boris mover (Sec. 3.1)
+// Field vector of an array over the job's field binning ((r, phi, z) components per (r, z) bin)
+// at (x, y, z), in Cartesian components; zero outside the binning.
+template <typename Real>
+__device__ __forceinline__ void field_at(const DevJob& J, const double* arr, Real x, Real y, Real z,
+                                         Real out[3]) {
+    out[0] = out[1] = out[2] = (Real)0;
+    if (!arr) return;
+    const Real r = ksqrt(x * x + y * y);
+    if (!(r < (Real)J.field_radius) || !(z >= (Real)0) || !(z < (Real)J.field_length)) return;
+    int ir = (int)((r / (Real)J.field_radius) * (Real)J.field_nr);
+    int iz = (int)((z / (Real)J.field_length) * (Real)J.field_nz);
+    if (ir > J.field_nr - 1) ir = J.field_nr - 1;
+    if (iz > J.field_nz - 1) iz = J.field_nz - 1;
+    const double* f = arr + ((size_t)ir * J.field_nz + (size_t)iz) * 3;
+    Real cp = (Real)1, sn = (Real)0;
+    if (r > (Real)0) {
+        cp = x / r;
+        sn = y / r;
+    }
+    const Real fr = (Real)f[0], fp = (Real)f[1];
+    out[0] = fr * cp - fp * sn;
+    out[1] = fr * sn + fp * cp;
+    out[2] = (Real)f[2];
+}
+
+// One push of time step dt: half an electric kick, the rotation with Omega = h B and
+// t = 2 Omega / (1 + Omega.Omega), the second half kick (h = q dt / 2m), then x += v dt.
+template <typename Real>
+__device__ __forceinline__ void boris_push(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int sp,
+                                           Real dt) {
+    Real E[3], B[3];
+    field_at(J, J.e_fld, p.x, p.y, p.z, E);
+    if (J.b_fld) {
+        field_at(J, J.b_fld, p.x, p.y, p.z, B);
+    } else {
+        B[0] = (Real)0;
+        B[1] = (Real)0;
+        B[2] = (Real)J.bz;
+    }
+    const Real h = (Real)L.sc->boris_h[sp];
+    const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
+    const Real vm[3] = {v[0] + h * E[0], v[1] + h * E[1], v[2] + h * E[2]};
+    const Real W[3] = {h * B[0], h * B[1], h * B[2]};
+    const Real f = (Real)2 / ((Real)1 + (W[0] * W[0] + W[1] * W[1] + W[2] * W[2]));
+    const Real t[3] = {f * W[0], f * W[1], f * W[2]};
+    const Real vp[3] = {vm[0] + (vm[1] * W[2] - vm[2] * W[1]),
+                        vm[1] + (vm[2] * W[0] - vm[0] * W[2]),
+                        vm[2] + (vm[0] * W[1] - vm[1] * W[0])};
+    const Real vq[3] = {vm[0] + (vp[1] * t[2] - vp[2] * t[1]),
+                        vm[1] + (vp[2] * t[0] - vp[0] * t[2]),
+                        vm[2] + (vp[0] * t[1] - vp[1] * t[0])};
+    const Real vn[3] = {vq[0] + h * E[0], vq[1] + h * E[1], vq[2] + h * E[2]};
+    p.x = p.x + vn[0] * dt;
+    p.y = p.y + vn[1] * dt;
+    p.z = p.z + vn[2] * dt;
+    set_velocity(p, (Real)L.sc->e_from_v2[sp], vn);
+}
+
+// energy bin of the energy-resolved density field (0 below the first edge, n_dens_bins+1 at or
+// above the last)
+__device__ __forceinline__ int dense_bin(const DevJob& J, int sp, double e) {
+    const int nb = J.n_dens_bins;
+    const double* ed = J.dens_edges + (size_t)sp * (nb + 1);
+    if (e < ed[0]) return 0;
+    if (!(e < ed[nb])) return nb + 1;
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ed[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo + 1;
+}
+
+// End of a Boris movement: its time to the segment (and energy bin) it was spent in, the work
+// of the electric field on it to the ledger and the history.
+template <typename Real>
+__device__ __forceinline__ void end_movement(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int sp) {
+    if (J.dense && p.t_cell != 0.0)
+        add_f64(&J.dense[(((size_t)sp * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz) * (size_t)(J.n_dens_bins + 2) +
+                         (size_t)p.eb], p.t_cell);
+    flush_time(J, p);
+    const double work = (double)p.e - (double)p.e0m;
+    if (work != 0.0) {
+        atomicAdd(&L.led[KARL_L_E_FIELD], work);
+        if (J.flags & KARL_FLAG_HISTORY) add_f64(&J.hist[(size_t)p.pid * KARL_NHIST + 1], -work);
+    }
+    p.fly = false;
+}
+
+// One transport step of the Boris mover: start a movement if none is under way (a distance
+// from the mean free path at the current energy and segment, eq. 2), one push, then the stops
+// in the order: outside the domain (deletion), another segment or energy bin (no interaction),
+// the drawn distance used up (interaction at the current position).  Returns whether an
+// interaction is due, with its process in *pi_out.
+template <typename Real>
+__device__ __forceinline__ bool boris_move(const DevJob& J, const Lds<Real>& L, Part<Real>& p,
+                                           LaneCnt& lc, int sp, int* pi_out) {
+    const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
+    const int np = L.sc->nps[sp];
+    if (!p.fly) {
+        const Real exs = p.e * (Real)L.sc->gfrac[sp];
+        const Real xl = klog(exs * (Real)L.sc->inv_emin[sp]) * (Real)L.sc->inv_dlog[sp];
+        int k;
+        Real f;
+        if (!(xl > (Real)0)) { k = 0; f = (Real)0; }
+        else if (xl >= (Real)(J.n_e - 1)) { k = J.n_e - 2; f = (Real)1; }
+        else { k = (int)xl; f = xl - (Real)k; }
+        const Real n_gas_cell = L.ngas[p.iz];
+        const Real n_fld_cell = field_density<Real>(J, L, sp, p.ir, p.iz);
+        Real sum = (Real)0;
+        for (int j = 0; j < np; ++j) sum += proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
+        const Pair<Real> q0 = draw<Real>(J.seed, p.pid, p.lin, p.s, 0u);
+        p.s_path = (sum > (Real)0) ? -klog(q0.d0 + Prec<Real>::eps) / sum : (Real)INFINITY;
+        p.fly = true;
+        p.e0m = p.e;
+        p.eb = J.dense ? dense_bin(J, sp, (double)p.e) : 0;
+    }
+    const Real dt = (Real)L.sc->boris_dt[sp];
+    boris_push(J, L, p, sp, dt);
+    p.s_path -= p.vel * dt;
+    p.t_cell += (double)dt;
+    p.t_alive += (double)dt;
+    count_ev(L, lc, KARL_C_STEP, sp);
+    const Real r = ksqrt(p.x * p.x + p.y * p.y);
+    if (p.z < (Real)0) {
+        end_movement(J, L, p, sp);
+        for (int fz = p.iz; fz >= 0; --fz) cross_z(J, L, p, lc, fz, 0, sp);
+        kill(J, L, p, KARL_EXIT_LOW);
+    } else if (!(p.z < (Real)J.length)) {
+        end_movement(J, L, p, sp);
+        for (int fz = p.iz + 1; fz <= J.n_z; ++fz) cross_z(J, L, p, lc, fz, 1, sp);
+        kill(J, L, p, KARL_EXIT_HIGH);
+    } else {
+        int niz = p.iz;
+        while (niz + 1 < J.n_z && L.zf[niz + 1] <= p.z) ++niz;
+        while (niz > 0 && !(L.zf[niz] <= p.z)) --niz;
+        const int nir = r_cell(L.rf, J.n_r, r, p.ir);
+        const bool wall = !(r < (Real)J.radius);
+        if (wall || niz != p.iz || nir != p.ir) {
+            // another segment: the movement stops without an interaction
+            end_movement(J, L, p, sp);
+            if (niz > p.iz) {
+                for (int fz = p.iz + 1; fz <= niz; ++fz) cross_z(J, L, p, lc, fz, 1, sp);
+            } else {
+                for (int fz = p.iz; fz > niz; --fz) cross_z(J, L, p, lc, fz, 0, sp);
+            }
+            p.iz = niz;
+            const int rto = wall ? J.n_r : nir;
+            if (rto > p.ir) {
+                for (int fr = p.ir + 1; fr <= rto; ++fr) cross_r(J, L, p, lc, fr, 1);
+            } else {
+                for (int fr = p.ir; fr > rto; --fr) cross_r(J, L, p, lc, fr, 0);
+            }
+            if (wall) kill(J, L, p, KARL_WALL);
+            else p.ir = nir;
+        } else if (J.dense && dense_bin(J, sp, (double)p.e) != p.eb) {
+            // another energy bin: the movement stops without an interaction
+            end_movement(J, L, p, sp);
+        } else if (p.s_path < (Real)0) {
+            // the drawn distance is used up: interaction here, with the rates at the current
+            // energy and segment (none if they all vanished on the way)
+            end_movement(J, L, p, sp);
+            const Real exs = p.e * (Real)L.sc->gfrac[sp];
+            const Real xl = klog(exs * (Real)L.sc->inv_emin[sp]) * (Real)L.sc->inv_dlog[sp];
+            int k;
+            Real f;
+            if (!(xl > (Real)0)) { k = 0; f = (Real)0; }
+            else if (xl >= (Real)(J.n_e - 1)) { k = J.n_e - 2; f = (Real)1; }
+            else { k = (int)xl; f = xl - (Real)k; }
+            const Real n_gas_cell = L.ngas[p.iz];
+            const Real n_fld_cell = field_density<Real>(J, L, sp, p.ir, p.iz);
+            Real sum = (Real)0;
+            for (int j = 0; j < np; ++j) sum += proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
+            if (sum > (Real)0) {
+                const Real target = draw<Real>(J.seed, p.pid, p.lin, p.s, 0u).d1 * sum;
+                Real run = (Real)0;
+                int sel = -1, last = -1;
+                for (int j = 0; j < np; ++j) {
+                    const Real rate = proc_rate(J, L, pidx[j], exs, k, f, n_gas_cell, n_fld_cell);
+                    run += rate;
+                    if (rate > (Real)0) last = j;
+                    if (sel < 0 && target < run) sel = j;
+                }
+                if (sel < 0) sel = last;
+                *pi_out = pidx[sel];
+                count_interaction(J, L, lc, p, sp, pidx[sel]);
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------- one flight segment
 // kDrain: the launch that runs the deferred queue, whose species have no ionization process
 // (the job setup defers exactly those); the ionization branch is left out of that kernel.
@@ -1011,11 +1309,19 @@ __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) 
 template <typename Real, int kDrain = 0>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
-    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
-    p.fly = false;
     // batched launches serve the lanes of a wave by (job, species): the species is uniform and
     // the process metadata below become scalar loads
     const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
+    bool coll = false;   // an interaction is due: process pi at (xc, yc, p.z)
+    int pi = 0;
+    Real xc = (Real)0, yc = (Real)0;
+    if (kDrain == 0 && J.boris) {
+        coll = boris_move(J, L, p, lc, sp, &pi);
+        xc = p.x;
+        yc = p.y;
+    } else {
+    const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
+    p.fly = false;
     // cross sections at the current energy, rates in the current cell (eq. 1)
     const Real exs = p.e * (Real)L.sc->gfrac[sp];
     const Real xl = klog(exs * (Real)L.sc->inv_emin[sp]) *
@@ -1114,12 +1420,10 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             if (sel < 0 && target < run) sel = j;
         }
         if (sel < 0) sel = last;
-        const int pi = pidx[sel];
-        count_ev(L, lc, KARL_C_COLL, sp);
-        wave_count(L.cnt, KARL_C_PROC + pi);
-        p.n_int += 1;
-        ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), dig);
-        Real xc = p.x, yc = p.y;
+        pi = pidx[sel];
+        count_interaction(J, L, lc, p, sp, pi);
+        xc = p.x;
+        yc = p.y;
         if (J.gc) {
             const Real om = (Real)L.sc->omega[sp];
             const Real iom = (Real)L.sc->inv_om[sp];
@@ -1133,87 +1437,16 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             xc = p.x - (p.vel * p.v) * iom;
             yc = p.y + (p.vel * p.u) * iom;
         }
-        bool killed = false;
-        const int kd = L.kind[pi];
-        // every class but excitation and recombination starts from a target particle's velocity
-        // (slots 2 and 3 of the step): drawn once here for all of them
-        Vec3<Real> tv{(Real)0, (Real)0, (Real)0};
-        if (kd != KARL_EXCITATION && kd != KARL_RECOMBINATION) {
-            Real V[3];
-            thermal(J, p, 2u, 3u, V);
-            tv = Vec3<Real>{V[0], V[1], V[2]};
-        }
-        // energy losses of the collision, added once after it (one update site per ledger keeps
-        // the loss accumulators in registers)
-        double d_exc = 0.0, d_gas = 0.0;
-        switch (kd) {
-            case KARL_ELASTIC:
-                d_gas = k_elastic(J, L, p, pi, tv);
-                break;
-            case KARL_EXCITATION: {
-                const Real ex = L.eth[pi];
-                p.e = p.e - ex;
-                p.vel = (p.e > (Real)0) ? ksqrt(p.e * (Real)L.sc->v2_from_e[sp]) : (Real)0;
-                d_exc = (double)ex;
-                break;
-            }
-            case KARL_IONIZATION:
-                if constexpr (kDrain) {
-                    // a deferred species makes no products; flag it rather than go on silently
-                    atomicOr(J.status, STATUS_NUMERIC);
-                    kill(J, L, p, KARL_LIFETIME);
-                    killed = true;
-                } else {
-                    k_ionization(J, L, G, p, pi, xc, yc, lc, tv);
-                }
-                break;
-            case KARL_CHARGE_EXCHANGE:
-                d_gas = k_charge_exchange(J, L, p, tv);
-                break;
-            case KARL_CLUSTERING:
-                if constexpr (kDrain) {
-                    atomicOr(J.status, STATUS_NUMERIC);
-                    kill(J, L, p, KARL_LIFETIME);
-                } else {
-                    k_clustering(J, L, G, p, pi, xc, yc, tv);
-                }
-                killed = true;
-                break;
-            default:
-                // one deletion logged in the partner's field (Sec. 3.3 "Recombination")
-                add_u64(&J.recomb[((size_t)J.partner[pi] * J.n_r + (size_t)p.ir) * J.n_z + (size_t)p.iz], 1ull);
-                kill(J, L, p, KARL_RECOMBINED);
-                killed = true;
-                break;
-        }
-        if (!killed) {
-            p.e_exc += d_exc;
-            p.e_gas += d_gas;
-            if (p.e < (Real)L.sc->e_cut[sp]) kill(J, L, p, KARL_CUTOFF);
-            else if (p.n_int >= L.sc->cap[sp]) kill(J, L, p, KARL_CAP);
-            else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
-            else if (J.gc) {
-                if (gc_set(J, L, p, lc, xc, yc, false)) {
-                    cross_r(J, L, p, lc, J.n_r, 1);
-                    kill(J, L, p, KARL_WALL);
-                }
-            }
-        }
+        // the drain launch (no Boris mover) interacts here; the others share one site below
+        if constexpr (kDrain != 0) interact<Real, kDrain>(J, L, G, p, lc, sp, pi, xc, yc);
+        else coll = true;
     } else if (which == 1) {
         // ---- z-face: current collector, spectrum plane, exit ----
         const int fz = zface;
         const int dir = (p.w > (Real)0) ? 1 : 0;
         p.z = L.zf[fz];
         flush_time(J, p);
-        count_ev(L, lc, KARL_C_ZCROSS, sp);
-        add_u64(&J.jz[(((size_t)sp * J.n_r + (size_t)p.ir) * (J.n_z + 1) + (size_t)fz) * 2 + (size_t)dir], 1ull);
-        ev(p, 3u, (uint32_t)dir, (uint32_t)(p.ir * (J.n_z + 1) + fz), dig);
-        const int pl = J.plane_of[fz];
-        if (pl >= 0) {
-            const int bin = spectrum_bin(J, sp, (double)p.e);
-            add_u64(&J.spectra[(((size_t)sp * J.n_planes + (size_t)pl) * 2 + (size_t)dir) * (J.n_bins + 2) + (size_t)bin], 1ull);
-            ev(p, 5u, (uint32_t)(pl * 2 + dir), (uint32_t)bin, dig);
-        }
+        cross_z(J, L, p, lc, fz, dir, sp);
         if (fz == 0) kill(J, L, p, KARL_EXIT_LOW);
         else if (fz == J.n_z) kill(J, L, p, KARL_EXIT_HIGH);
         else p.iz = dir ? fz : fz - 1;
@@ -1233,8 +1466,15 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         if (fr == J.n_r) kill(J, L, p, KARL_WALL);
         else p.ir = out ? fr : fr - 1;
     }
+    }
+    if constexpr (kDrain == 0) {
+        if (coll) interact<Real, kDrain>(J, L, G, p, lc, sp, pi, xc, yc);
+    }
     p.s += 1u;
-    if (p.alive && p.t_alive >= L.sc->lifetime[sp]) kill(J, L, p, KARL_LIFETIME);
+    if (p.alive && p.t_alive >= L.sc->lifetime[sp]) {
+        if (kDrain == 0 && J.boris && p.fly) end_movement(J, L, p, sp);
+        kill(J, L, p, KARL_LIFETIME);
+    }
 }
 
 
@@ -1266,7 +1506,7 @@ __device__ __forceinline__ float bc_r(float x, int j) {
 // digest likewise.  The interaction itself is left to the next regular step, which draws the
 // same numbers, so results equal those of segment-by-segment transport.
 template <typename Real>
-__device__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
+__device__ __forceinline__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                             LaneCnt& lc, int j) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     const int k = (int)lane_id();

@@ -49,7 +49,7 @@ constexpr int kFloorWindow = 8;
 struct OwnedDesc {
     karl_job_desc d{};
     std::vector<double> n_gas, n_field[KARL_MAX_SPECIES], edges[KARL_MAX_SPECIES],
-        dens_edges[KARL_MAX_SPECIES], xs[KARL_MAX_PROC];
+        dens_edges[KARL_MAX_SPECIES], xs[KARL_MAX_PROC], e_field, b_field;
     std::vector<double> ang_edges[KARL_MAX_PROC], ang_theta[KARL_MAX_PROC], ang_pdf[KARL_MAX_PROC];
     std::vector<int32_t> planes;
 
@@ -87,6 +87,15 @@ struct OwnedDesc {
         if (s.n_planes > 0) {
             planes.assign(s.planes, s.planes + s.n_planes);
             d.planes = planes.data();
+        }
+        const size_t fb = (size_t)std::max(s.field_nr, 0) * (size_t)std::max(s.field_nz, 0) * 3;
+        if (s.e_field) {
+            e_field.assign(s.e_field, s.e_field + fb);
+            d.e_field = e_field.data();
+        }
+        if (s.b_field) {
+            b_field.assign(s.b_field, s.b_field + fb);
+            d.b_field = b_field.data();
         }
         d.workspace = nullptr;
         d.workspace_bytes = 0;

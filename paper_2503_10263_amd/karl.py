@@ -29,7 +29,8 @@ FLAG_DIGESTS, FLAG_HISTORY = 1, 2
 # MAX_SPECIES slots (0 electrons, 1.. ions)
 C_BIRTH, C_STEP, C_COLL, C_ZCROSS, C_RCROSS = 0, 4, 8, 12, 16
 C_TARGET_REDRAW, C_BEB_TRIES, C_BETA_TRIES, C_PROC, C_DEATH = 20, 21, 22, 24, 40
-L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE = 0, 1, 37, 38, 39, 40
+L_E_PRIMARY, L_E_DEATH, L_E_EXC, L_E_BIND, L_E_GAS, L_T_ALIVE, L_E_FIELD = 0, 1, 37, 38, 39, 40, 44
+MOVER_DRIFT, MOVER_BORIS = 0, 1
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDEVICE",
@@ -87,7 +88,12 @@ class JobDesc(C.Structure):
                 ("n_primaries", C.c_int64), ("precision", C.c_int32), ("flags", C.c_uint32),
                 ("queue_capacity", C.c_int64), ("chunk", C.c_int64),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
-                ("mapping", C.c_int32), ("n_dens_bins", C.c_int32)]
+                ("mapping", C.c_int32), ("n_dens_bins", C.c_int32),
+                ("mover", C.c_int32), ("reserved1", C.c_int32),
+                ("boris_dt", C.c_double * MAX_SPECIES), ("field_nr", C.c_int32),
+                ("field_nz", C.c_int32), ("field_radius", C.c_double),
+                ("field_length", C.c_double), ("e_field", C.POINTER(C.c_double)),
+                ("b_field", C.POINTER(C.c_double))]
 
 
 class ServerDesc(C.Structure):
@@ -251,6 +257,23 @@ class Descriptor:
         d.queue_capacity = queue_capacity
         d.chunk = chunk
         d.mapping = mapping
+        # mover and field arrays (one binning shared by E and B)
+        d.mover = getattr(w, "mover", MOVER_DRIFT)
+        for s, dt in enumerate(getattr(w, "boris_dt", None) or []):
+            d.boris_dt[s] = dt
+        shapes = set()
+        for name in ("e_field", "b_field"):
+            arr = getattr(w, name, None)
+            if arr is not None:
+                a = self._hold(arr, np.float64)
+                if a.ndim != 3 or a.shape[2] != 3:
+                    raise ValueError(f"{name} must have shape [nr][nz][3]")
+                shapes.add(a.shape)
+                if len(shapes) > 1:
+                    raise ValueError("e_field and b_field share one binning")
+                setattr(d, name, _dptr(a))
+                d.field_nr, d.field_nz = a.shape[0], a.shape[1]
+                d.field_radius, d.field_length = w.field_radius, w.field_length
         self.d = d
 
     def _hold(self, a, dtype):

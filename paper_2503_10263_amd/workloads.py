@@ -586,5 +586,32 @@ def with_boris(w: Workload, dt, lifetime, e_field=None, b_field=None, field_radi
     return w
 
 
+def boris_column(n_primaries: int = 600, column_cm2: float = 2.0e15, n_r: int = 4, n_z: int = 16,
+                 b0: float = 0.05, b_max: float = 0.1, e_r: float = -30.0, seed: int = 51,
+                 field_bins: tuple = (8, 32)) -> Workload:
+    """Beta electrons and tracked H2+ moved by Boris pushes (Sec. 3.1) in a 1 m x 45 mm H2
+    column through a magnetic bottle B_z(z) = b0 + (b_max - b0)(2z/L - 1)^2 with
+    B_r = -(r/2) dB_z/dz at the bin centres and a radial electric field E_r = e_r (r/R) V/m
+    (arrays over field_bins (r, z) bins).  Electrons: elastic, BEB ionization, 12.6 eV
+    excitation; ions: Langevin elastic.  Time steps 2e-11 s (electrons; the largest gyro
+    frequency is 1.8e10 rad/s) and 1e-7 s (ions), lifetimes 2e-6 s and 2e-4 s."""
+    w = cfg_tiny(n_primaries=n_primaries, seed=seed, bz=0.0, column_cm2=column_cm2, n_r=n_r, n_z=n_z)
+    w.name = "boris column"
+    w.species[ION] = h2_ion(tracked=True, edges=np.linspace(0.0, 100.0, 20001))
+    w.processes.append(Process(ELASTIC, ION, TARGET_GAS, 0.0,
+                               xs_langevin(log_nodes(1.0e-4, 1.0e2, w.n_e)), "H2+ Langevin elastic"))
+    nfr, nfz = field_bins
+    zc = (np.arange(nfz) + 0.5) / nfz * w.length
+    rc = (np.arange(nfr) + 0.5) / nfr * w.radius
+    bz = b0 + (b_max - b0) * (2.0 * zc / w.length - 1.0) ** 2
+    dbz = (b_max - b0) * 2.0 * (2.0 * zc / w.length - 1.0) * (2.0 / w.length)
+    b = np.zeros((nfr, nfz, 3))
+    b[:, :, 2] = bz[None, :]
+    b[:, :, 0] = -0.5 * rc[:, None] * dbz[None, :]
+    e = np.zeros((nfr, nfz, 3))
+    e[:, :, 0] = e_r * (rc / w.radius)[:, None]
+    return with_boris(w, dt=[2.0e-11, 1.0e-7], lifetime=[2.0e-6, 2.0e-4], e_field=e, b_field=b)
+
+
 def with_primaries(w: Workload, n: int) -> Workload:
     return replace(w, n_primaries=n)

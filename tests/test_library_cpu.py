@@ -144,3 +144,31 @@ def test_chemistry_descriptor_rules():
     w.beam_species = 4
     w.source = W.SOURCE_BEAM
     assert rejected(w)
+
+
+def test_boris_descriptor_rules():
+    """Invalid mover descriptors are rejected before any device work."""
+    from paper_2503_10263_amd import karl
+    import math as _m
+
+    def rejected(w):
+        with pytest.raises(karl.KarlError) as ei:
+            karl.Descriptor(w, queue_capacity=1024).workspace_bytes()
+        return ei.value.code == karl.EINVAL
+
+    assert karl.Descriptor(W.boris_column(n_primaries=10), queue_capacity=1024).workspace_bytes() > 0
+    w = W.boris_column(n_primaries=10)
+    w.mover = W.MOVER_DRIFT                          # field arrays with the drift mover
+    assert rejected(w)
+    w = W.boris_column(n_primaries=10)
+    w.species[0].lifetime = _m.inf                  # a Boris particle must end
+    assert rejected(w)
+    w = W.boris_column(n_primaries=10)
+    w.boris_dt = [1e-16, 1e-7]                      # 2e10 pushes per lifetime
+    assert rejected(w)
+    w = W.boris_column(n_primaries=10)
+    w.boris_dt = [2e-11, 0.0]
+    assert rejected(w)
+    w = W.boris_column(n_primaries=10)
+    w.e_field = np.full_like(w.e_field, np.nan)
+    assert rejected(w)
