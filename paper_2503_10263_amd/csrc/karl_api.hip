@@ -341,6 +341,8 @@ struct Launcher {
     int max_blocks_drain = 0;               // single-job deferred-queue launches
     bool coop = false;                      // launch the wave-cooperative kernel
     bool dense = false;                     // the job has an energy-resolved density tally
+    bool boris = false;                     // a job of the launch uses the Boris mover
+    int max_blocks_boris = 0;               // launches of the kernel built with the Boris mover
     unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
@@ -372,15 +374,18 @@ struct Launcher {
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, dev));
         int per_cu = 0;
-        HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, false, kBlock, lds, &per_cu));
+        HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, false, false, kBlock, lds, &per_cu));
         if (per_cu < 1) per_cu = 1;
         max_blocks = per_cu * prop.multiProcessorCount;
         max_blocks_coop = max_blocks_drain = max_blocks;
+        HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, false, true, kBlock, lds, &per_cu));
+        if (per_cu < 1) per_cu = 1;
+        max_blocks_boris = per_cu * prop.multiProcessorCount;
         if (!is_batched) {
-            HIP_CHECK(karl::transport_occupancy(prec, false, true, false, kBlock, lds, &per_cu));
+            HIP_CHECK(karl::transport_occupancy(prec, false, true, false, false, kBlock, lds, &per_cu));
             if (per_cu < 1) per_cu = 1;
             max_blocks_coop = per_cu * prop.multiProcessorCount;
-            HIP_CHECK(karl::transport_occupancy(prec, false, false, true, kBlock, lds, &per_cu));
+            HIP_CHECK(karl::transport_occupancy(prec, false, false, true, false, kBlock, lds, &per_cu));
             if (per_cu < 1) per_cu = 1;
             max_blocks_drain = per_cu * prop.multiProcessorCount;
         }
@@ -471,11 +476,12 @@ struct Launcher {
             }
             const bool use_drain = drain && !batched;
             const bool use_coop = coop && !batched && !use_drain;
-            const int64_t cap_blocks = use_drain ? max_blocks_drain : use_coop ? max_blocks_coop : max_blocks;
+            const int64_t cap_blocks = use_drain ? max_blocks_drain : use_coop ? max_blocks_coop
+                                       : boris ? max_blocks_boris : max_blocks;
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > cap_blocks) blocks = cap_blocks;
             HIP_CHECK(hipEventRecord(ev0, s));
-            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, dense, g, precision,
+            HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, dense, boris, g, precision,
                                              (int)blocks, kBlock, lds, s));
             HIP_CHECK(hipEventRecord(ev1, s));
             HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
@@ -959,6 +965,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->lds = lds;
     j->run.ctl = ctl;
     j->run.dense = d->n_dens_bins > 0;
+    j->run.boris = d->mover == KARL_MOVER_BORIS;
     j->run.jobs_dev = (karl::DevJob*)(w + L.devjob);
     TRY_HIP(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
     TRY_HIP(karl::launch_fill_u64((unsigned long long*)t, L.tally_bytes / 8, 0ull, nullptr));
@@ -1197,6 +1204,9 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
     HIP_CHECK(hipSetDevice(B->device));
     Launcher& R = B->run[prec == KARL_FP32 ? 1 : 0];
     R.n_jobs = n_jobs;
+    // the kernel built with the Boris mover only when a job of the batch needs it
+    R.boris = false;
+    for (int i = 0; i < n_jobs; ++i) R.boris = R.boris || ((Job*)jobs[i])->dj.boris != 0;
     HIP_CHECK(hipMemcpyAsync(R.jobs_dev, B->host_jobs, sizeof(karl::DevJob) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
     int64_t c0 = 0;
     while (c0 < total) {

@@ -144,7 +144,7 @@ enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 
 size_t lds_bytes(const DevJob& j, int precision);
 hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain, bool dense,
-                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s);
 hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
@@ -155,7 +155,7 @@ hipError_t launch_sort_by_job(const QueueSoA& in, const QueueSoA& out, int64_t n
                               unsigned long long* cursor, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long value,
                            hipStream_t s);
-hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, int block,
+hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, bool boris, int block,
                                size_t lds, int* blocks_per_cu);
 size_t batched_lds_bytes();
 

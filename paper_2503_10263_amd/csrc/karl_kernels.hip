@@ -411,10 +411,11 @@ __device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess
 // Guiding centre from position and velocity; returns true if the orbit reaches the wall.
 // At birth the r-cell is set from the guiding-centre radius; after a collision every r-face
 // between the old and new guiding-centre radius counts as crossed.
+// sp: the particle's species (wave-uniform when the caller serves one species per pass)
 template <typename Real>
 __device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
-                       Real yp, bool at_birth) {
-    const Real iom = (Real)L.sc->inv_om[p.sp];
+                       Real yp, bool at_birth, int sp) {
+    const Real iom = (Real)L.sc->inv_om[sp];
     const Real gx = xp + (p.vel * p.v) * iom;
     const Real gy = yp - (p.vel * p.u) * iom;
     const Real rho = ksqrt(gx * gx + gy * gy);
@@ -450,9 +451,9 @@ __device__ __forceinline__ Real proc_rate(const DevJob& J, const Lds<Real>& L, i
         sig = tb[k] + f * (tb[k + 1] - tb[k]);
     }
     const int t = L.tgt[i];
-    if (t == TGT_GAS) return n_gas * sig;
-    if (t == TGT_FIELD) return n_fld * sig;
-    return (n_gas * (n_gas * sig)) * (Real)J.p2scale;
+    const Real r = ((t == TGT_FIELD) ? n_fld : n_gas) * sig;
+    if (__builtin_expect(t == TGT_GAS2, 0)) return (n_gas * r) * (Real)J.p2scale;
+    return r;
 }
 
 // density of the field that species sp's field processes target, in cell (ir, iz)
@@ -558,9 +559,9 @@ __device__ Real scatter_mu(const DevJob& J, int pi, Real ecm, Real u) {
 
 // V: the target particle's velocity (thermal(), slots 2 and 3 of the step)
 template <typename Real>
-__device__ double k_elastic(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int pi, Vec3<Real> tv) {
+__device__ double k_elastic(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int pi, Vec3<Real> tv,
+                            int s) {
     const Real V[3] = {tv.x, tv.y, tv.z};
-    const int s = p.sp;
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     const Real g[3] = {v[0] - V[0], v[1] - V[1], v[2] - V[2]};
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -695,9 +696,9 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
 
 template <typename Real>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                             int pi, Real xc, Real yc, LaneCnt& lc, Vec3<Real> tv) {
-    const Real ef2 = (Real)L.sc->e_from_v2[p.sp];
-    const Real v2e = (Real)L.sc->v2_from_e[p.sp];
+                             int pi, Real xc, Real yc, LaneCnt& lc, Vec3<Real> tv, int sp) {
+    const Real ef2 = (Real)L.sc->e_from_v2[sp];
+    const Real v2e = (Real)L.sc->v2_from_e[sp];
     const Real B = L.eth[pi];
     const Real v[3] = {p.vel * p.u, p.vel * p.v, p.vel * p.w};
     Real V[3] = {tv.x, tv.y, tv.z}, g[3];
@@ -856,16 +857,17 @@ __device__ void k_clustering(const DevJob& J, const Lds<Real>& L, const GenArgs&
 // Charge exchange (Sec. 3.3): the projectile continues with the velocity of a target particle,
 // drawn as for elastic scattering.
 template <typename Real>
-__device__ double k_charge_exchange(const DevJob& J, const Lds<Real>& L, Part<Real>& p, Vec3<Real> tv) {
+__device__ double k_charge_exchange(const DevJob& J, const Lds<Real>& L, Part<Real>& p, Vec3<Real> tv,
+                                    int sp) {
     const Real V[3] = {tv.x, tv.y, tv.z};
     const Real e0 = p.e;
-    set_velocity(p, (Real)L.sc->e_from_v2[p.sp], V);
+    set_velocity(p, (Real)L.sc->e_from_v2[sp], V);
     return (double)(e0 - p.e);
 }
 
 // ---------------------------------------------------------------- birth (Sec. 3.5)
 template <typename Real>
-__device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Real>& p,
+__device__ __forceinline__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Real>& p,
                       LaneCnt& lc) {
     p.lin = 0ull;
     p.pid = pid;
@@ -945,7 +947,7 @@ __device__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Re
 
 // common start of every particle (primary or secondary); returns with p.alive set
 template <typename Real>
-__device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc) {
+__device__ __forceinline__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     p.s = 0u;
     p.n_int = 0;
@@ -964,7 +966,7 @@ __device__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& 
     if (p.e < (Real)L.sc->e_cut[p.sp]) { kill(J, L, p, KARL_CUTOFF); return; }
     if (!(p.vel > (Real)0)) { kill(J, L, p, KARL_LIFETIME); return; }
     if (J.gc) {
-        if (gc_set(J, L, p, lc, p.x, p.y, true)) {
+        if (gc_set(J, L, p, lc, p.x, p.y, true, p.sp)) {
             cross_r(J, L, p, lc, J.n_r, 1);
             kill(J, L, p, KARL_WALL);
         }
@@ -1054,7 +1056,7 @@ __device__ __forceinline__ void interact(const DevJob& J, const Lds<Real>& L, co
     double d_exc = 0.0, d_gas = 0.0;
     switch (kd) {
         case KARL_ELASTIC:
-            d_gas = k_elastic(J, L, p, pi, tv);
+            d_gas = k_elastic(J, L, p, pi, tv, sp);
             break;
         case KARL_EXCITATION: {
             const Real ex = L.eth[pi];
@@ -1070,11 +1072,11 @@ __device__ __forceinline__ void interact(const DevJob& J, const Lds<Real>& L, co
                 kill(J, L, p, KARL_LIFETIME);
                 killed = true;
             } else {
-                k_ionization(J, L, G, p, pi, xc, yc, lc, tv);
+                k_ionization(J, L, G, p, pi, xc, yc, lc, tv, sp);
             }
             break;
         case KARL_CHARGE_EXCHANGE:
-            d_gas = k_charge_exchange(J, L, p, tv);
+            d_gas = k_charge_exchange(J, L, p, tv, sp);
             break;
         case KARL_CLUSTERING:
             if constexpr (kDrain) {
@@ -1099,7 +1101,7 @@ __device__ __forceinline__ void interact(const DevJob& J, const Lds<Real>& L, co
         else if (p.n_int >= L.sc->cap[sp]) kill(J, L, p, KARL_CAP);
         else if (!(p.vel > (Real)0)) kill(J, L, p, KARL_LIFETIME);
         else if (J.gc) {
-            if (gc_set(J, L, p, lc, xc, yc, false)) {
+            if (gc_set(J, L, p, lc, xc, yc, false, sp)) {
                 cross_r(J, L, p, lc, J.n_r, 1);
                 kill(J, L, p, KARL_WALL);
             }
@@ -1306,7 +1308,7 @@ __device__ __forceinline__ bool boris_move(const DevJob& J, const Lds<Real>& L, 
 // kDrain: the launch that runs the deferred queue, whose species have no ionization process
 // (the job setup defers exactly those); the ionization branch is left out of that kernel.
 // kDrain == 1 also leaves out the energy-resolved density tally (jobs without it), 2 keeps it.
-template <typename Real, int kDrain = 0>
+template <typename Real, int kDrain = 0, bool kBoris = false>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
                      LaneCnt& lc) {
     // batched launches serve the lanes of a wave by (job, species): the species is uniform and
@@ -1315,7 +1317,16 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     bool coll = false;   // an interaction is due: process pi at (xc, yc, p.z)
     int pi = 0;
     Real xc = (Real)0, yc = (Real)0;
-    if (kDrain == 0 && J.boris) {
+    if constexpr (!kBoris) {
+        if (J.boris) {
+            // a Boris job in a kernel built without the mover: cannot happen (the host picks the
+            // kernel by job); flag it rather than move the particle with the wrong mover
+            atomicOr(J.status, STATUS_NUMERIC);
+            kill(J, L, p, KARL_LIFETIME);
+            return;
+        }
+    }
+    if (kBoris && J.boris) {
         coll = boris_move(J, L, p, lc, sp, &pi);
         xc = p.x;
         yc = p.y;
@@ -1437,8 +1448,8 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
             xc = p.x - (p.vel * p.v) * iom;
             yc = p.y + (p.vel * p.u) * iom;
         }
-        // the drain launch (no Boris mover) interacts here; the others share one site below
-        if constexpr (kDrain != 0) interact<Real, kDrain>(J, L, G, p, lc, sp, pi, xc, yc);
+        // kernels without the Boris mover interact here; with it, the two movers share one site
+        if constexpr (!kBoris) interact<Real, kDrain>(J, L, G, p, lc, sp, pi, xc, yc);
         else coll = true;
     } else if (which == 1) {
         // ---- z-face: current collector, spectrum plane, exit ----
@@ -1467,12 +1478,12 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         else p.ir = out ? fr : fr - 1;
     }
     }
-    if constexpr (kDrain == 0) {
+    if constexpr (kBoris) {
         if (coll) interact<Real, kDrain>(J, L, G, p, lc, sp, pi, xc, yc);
     }
     p.s += 1u;
     if (p.alive && p.t_alive >= L.sc->lifetime[sp]) {
-        if (kDrain == 0 && J.boris && p.fly) end_movement(J, L, p, sp);
+        if (kBoris && J.boris && p.fly) end_movement(J, L, p, sp);
         kill(J, L, p, KARL_LIFETIME);
     }
 }
@@ -1775,7 +1786,7 @@ __device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool nee
 }
 
 // One unit of work for a lane: start its fetched particle, or move it by one flight segment.
-template <typename Real, int kDrain = 0>
+template <typename Real, int kDrain = 0, bool kBoris = false>
 __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, const GenArgs& G,
                                         Part<Real>& p, LaneCnt& lc) {
     if (p.start) {
@@ -1788,7 +1799,7 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
         }
         start_particle(J, L, p, lc);
     } else {
-        step<Real, kDrain>(J, L, G, p, lc);
+        step<Real, kDrain, kBoris>(J, L, G, p, lc);
     }
 }
 
@@ -1804,7 +1815,7 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 // (one job): the deferred-queue launch, without the birth and ionization code, which leaves
 // the kernel half the registers and twice the waves per SIMD (1: without, 2: with the
 // energy-resolved density tally).
-template <typename Real, bool kBatched, bool kCoop = false, int kDrain = 0>
+template <typename Real, bool kBatched, bool kCoop = false, int kDrain = 0, bool kBoris = false>
 __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1886,7 +1897,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
                     coop_flight(jobs[0], L0, G, p, lc, j);
                 }
             }
-            if (p.alive || p.start) advance<Real, kDrain>(jobs[0], L0, G, p, lc);
+            if (p.alive || p.start) advance<Real, kDrain, kBoris>(jobs[0], L0, G, p, lc);
         } else {
             bool todo = p.alive || p.start;
             const int key = kS * p.job + (p.start ? 0 : p.sp);
@@ -1914,7 +1925,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
                         __builtin_amdgcn_wave_barrier();
                     }
                     unsigned long long* sc = wslots + (size_t)slot * kSlotWords;
-                    advance(J, global_view<Real>(J, sc, (double*)(sc + kNCnt)), G, p, lc);
+                    advance<Real, 0, kBoris>(J, global_view<Real>(J, sc, (double*)(sc + kNCnt)), G, p, lc);
                     todo = false;
                 }
             }
@@ -2058,7 +2069,7 @@ size_t lds_bytes(const DevJob& j, int precision) {
 }
 
 hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain, bool dense,
-                            const GenArgs& g, int precision, int grid, int block, size_t lds,
+                            bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s) {
     if (drain && !batched) {
         if (precision == KARL_FP32) {
@@ -2075,19 +2086,31 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
         return hipGetLastError();
     }
     if (precision == KARL_FP32) {
-        if (batched)
-            hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        else if (coop)
+        if (batched) {
+            if (boris)
+                hipLaunchKernelGGL((transport_kernel<float, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+            else
+                hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        } else if (coop) {
             hipLaunchKernelGGL((transport_kernel<float, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        else
+        } else if (boris) {
+            hipLaunchKernelGGL((transport_kernel<float, false, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        } else {
             hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        }
     } else {
-        if (batched)
-            hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        else if (coop)
+        if (batched) {
+            if (boris)
+                hipLaunchKernelGGL((transport_kernel<double, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+            else
+                hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        } else if (coop) {
             hipLaunchKernelGGL((transport_kernel<double, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        else
+        } else if (boris) {
+            hipLaunchKernelGGL((transport_kernel<double, false, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        } else {
             hipLaunchKernelGGL((transport_kernel<double, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        }
     }
     return hipGetLastError();
 }
@@ -2136,7 +2159,7 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, int block,
+hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, bool boris, int block,
                                size_t lds, int* blocks_per_cu) {
     if (drain && !batched) {
         if (precision == KARL_FP32)
@@ -2145,16 +2168,20 @@ hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drai
     }
     if (precision == KARL_FP32) {
         if (batched)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
+            return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true, false, 0, true>, block, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
         if (coop)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, true>, block, lds);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false>, block, lds);
+        return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 0, true>, block, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false>, block, lds);
     }
     if (batched)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
+        return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true, false, 0, true>, block, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
     if (coop)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, true>, block, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false>, block, lds);
+    return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 0, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false>, block, lds);
 }
 
 }  // namespace karl
