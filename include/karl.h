@@ -206,6 +206,21 @@ typedef struct {
     double field_radius, field_length;
     const double* e_field;        /* [field_nr][field_nz][3] V/m */
     const double* b_field;        /* [field_nr][field_nz][3] T */
+    /* Deferred-queue launch in slices.  A scheduling option: the order in which particles run
+       is free (Sec. 3.9 takes the next particle at random from the list; Sec. 3.6 evens out
+       uneven loads over long cycles), and results do not depend on it, up to the summation
+       order of floating-point tallies.  The species that make no products run after the other
+       generations, in one launch over all their particles.  With slice_steps > 0, a particle
+       of that launch whose step count reaches a multiple of slice_steps goes back to the end of
+       the launch's work -- into a ring of slice_ring entries in the workspace, with its whole
+       state -- and its lane takes the next item.  So the long histories of the launch advance
+       in turn and end together, instead of the last ones started running on alone while the
+       other lanes idle.  A particle whose ring slot has not been read yet keeps its lane for
+       another slice.  slice_steps: 0 (no slices, no ring) or a power of two up to 2^30.
+       slice_ring: ring entries, 0: queue_capacity + 2^20 (the launch's particles plus its
+       lanes fit without full slots). */
+    int64_t slice_steps;
+    int64_t slice_ring;
 } karl_job_desc;
 
 /* Host buffers for karl_read_tallies; any NULL pointer is skipped.  Sizes in elements, with
@@ -275,6 +290,11 @@ karl_status karl_reset_tallies(void* job, void* hip_stream);
    secondary generations processed, *max_queue the largest generation. */
 karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches,
                            int64_t* generations, int64_t* max_queue);
+
+/* Particles that the job's deferred launches put into the ring at the end of a slice
+   (karl_job_desc.slice_steps), since creation or the last karl_reset_tallies; 0 without
+   slices.  Both pointers must be valid. */
+karl_status karl_job_slices(void* job, int64_t* ring_entries);
 
 /* The mapping karl_transport uses for this job (KARL_MAP_LANE or KARL_MAP_WAVE; KARL_MAP_AUTO
    while not yet tuned), the segments per interaction that chose it (0 if not tuned), the kernel

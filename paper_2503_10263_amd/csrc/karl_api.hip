@@ -51,6 +51,7 @@ struct Layout {
     size_t tallies, tally_bytes;
     size_t t_counters, t_ledger, t_dens, t_recomb, t_jz, t_jr, t_spectra, t_digests, t_hist, t_dense;
     size_t snapshot, control, fields, queues, queue_entries;
+    size_t ring, ring_flag, ring_cap;   // deferred launch in slices (ring_cap 0: none)
     size_t total;
 };
 
@@ -128,6 +129,11 @@ Layout make_layout(const karl_job_desc* d) {
     L.fields = take(8 * (ns * nr * nz + ns * nr * (nz + 1) + ns * (nr + 1) * nz));
     L.queue_entries = (size_t)(d->queue_capacity > 0 ? d->queue_capacity : kDefaultCapacity);
     L.queues = take(4 * L.queue_entries * kQueueEntryBytes);
+    L.ring_cap = d->slice_steps > 0 ? (size_t)(d->slice_ring > 0 ? d->slice_ring
+                                                                 : (int64_t)L.queue_entries + (1 << 20))
+                                    : 0;
+    L.ring = take(L.ring_cap * sizeof(karl::RingEntry));
+    L.ring_flag = take(8 * L.ring_cap);
     L.total = off;
     return L;
 }
@@ -288,6 +294,10 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
     if (d->precision != KARL_FP64 && d->precision != KARL_FP32)
         return fail(KARL_EINVAL, "precision must be KARL_FP64 or KARL_FP32");
     if (d->queue_capacity < 0 || d->chunk < 0) return fail(KARL_EINVAL, "negative queue/chunk size");
+    if (d->slice_steps < 0 || d->slice_steps > (int64_t(1) << 30) || (d->slice_steps & (d->slice_steps - 1)) != 0)
+        return fail(KARL_EINVAL, "slice_steps must be 0 or a power of two up to 2^30");
+    if (d->slice_ring < 0 || d->slice_ring > (int64_t(1) << 40))
+        return fail(KARL_EINVAL, "slice_ring must be in 0..2^40");
     if (d->mapping != KARL_MAP_AUTO && d->mapping != KARL_MAP_LANE && d->mapping != KARL_MAP_WAVE)
         return fail(KARL_EINVAL, "mapping must be KARL_MAP_AUTO, KARL_MAP_LANE or KARL_MAP_WAVE");
     if (need_workspace) {
@@ -333,7 +343,7 @@ struct Launcher {
     karl::DevJob* jobs_dev = nullptr;       // job table in device memory
     karl::QueueSoA q[2]{};                  // next-generation queues (ping-pong)
     karl::QueueSoA dq[2]{};                 // deferred queues (append / drain)
-    unsigned long long* ctl = nullptr;      // [0] fetch [1] qcount [2] status [3..4] dcount
+    unsigned long long* ctl = nullptr;      // [0] fetch [1] qcount [2] status [3..4] dcount [5] job status [6] wave segments [7] ring tail
     int64_t capacity = 0;
     size_t lds = 0;
     int max_blocks = 0;
@@ -343,10 +353,15 @@ struct Launcher {
     bool dense = false;                     // the job has an energy-resolved density tally
     bool boris = false;                     // a job of the launch uses the Boris mover
     int max_blocks_boris = 0;               // launches of the kernel built with the Boris mover
+    uint32_t slice_mask = 0;                // deferred launch in slices: steps per slice - 1
+    karl::RingEntry* ring = nullptr;        // its ring of particles between slices
+    unsigned long long* ring_flag = nullptr;
+    int64_t ring_cap = 0;
     unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int64_t launches = 0, generations = 0, max_queue = 0;
+    int64_t slices = 0;                     // ring entries written by deferred launches
     // batched launches: per-job item ranges, fetch counters and the queue sort's scratch
     int32_t n_jobs = 1;
     int64_t* job_first = nullptr;
@@ -409,7 +424,7 @@ struct Launcher {
 
     void reset_stats() {
         kernel_ms = 0.0;
-        launches = generations = max_queue = 0;
+        launches = generations = max_queue = slices = 0;
     }
 
     // Run every generation of n primary items (chunk of the item space starting at item_base;
@@ -480,13 +495,31 @@ struct Launcher {
                                        : boris ? max_blocks_boris : max_blocks;
             int64_t blocks = (items + kBlock - 1) / kBlock;
             if (blocks > cap_blocks) blocks = cap_blocks;
+            if (use_drain) {
+                // every lane starts on the item of its thread index; the claim counter starts
+                // after them; with slices, the ring starts empty
+                HIP_CHECK(karl::launch_fill_u64(fetch, 1, (unsigned long long)std::min<int64_t>(items, blocks * kBlock), s));
+                if (slice_mask) {
+                    g.slice_mask = slice_mask;
+                    g.ring_cap = ring_cap;
+                    g.ring = ring;
+                    g.ring_flag = ring_flag;
+                    g.ring_tail = ctl + 7;
+                    HIP_CHECK(karl::launch_fill_u64(ring_flag, (size_t)ring_cap, 0ull, s));
+                    HIP_CHECK(karl::launch_fill_u64(ctl + 7, 1, 0ull, s));
+                }
+            }
             HIP_CHECK(hipEventRecord(ev0, s));
             HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, dense, boris, g, precision,
                                              (int)blocks, kBlock, lds, s));
             HIP_CHECK(hipEventRecord(ev1, s));
             HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, s));
+            if (use_drain && slice_mask)
+                HIP_CHECK(hipMemcpyAsync(host_ctl + 6, ctl + 7, sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
+            if (use_drain && slice_mask) slices += (int64_t)host_ctl[6];
             float ms = 0.f;
             HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
             kernel_ms += ms;
@@ -544,6 +577,7 @@ struct Job {
     bool failed = false;
     int device = 0;
     size_t lds = 0;              // launch shape of the job's own launcher, set up on first use
+    int64_t slice_steps = 0;           // deferred launch in slices (0: whole histories)
     int32_t mapping = KARL_MAP_AUTO;   // requested
     int32_t chosen = KARL_MAP_AUTO;    // in use once tuned (or forced)
     double seg_per_int = 0.0;          // flight segments per interaction of the tuning chunk
@@ -558,6 +592,12 @@ karl_status ensure_launcher(Job* j) {
     karl::DevJob* table = j->run.jobs_dev;
     karl_status s = j->run.init(j->ws + j->lay.queues, j->lay.queue_entries, ctl, j->precision, false, j->lds);
     j->run.jobs_dev = table;
+    if (j->lay.ring_cap > 0) {
+        j->run.slice_mask = (uint32_t)(j->slice_steps - 1);
+        j->run.ring = (karl::RingEntry*)(j->ws + j->lay.ring);
+        j->run.ring_flag = (unsigned long long*)(j->ws + j->lay.ring_flag);
+        j->run.ring_cap = (int64_t)j->lay.ring_cap;
+    }
     return s;
 }
 
@@ -719,6 +759,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->ws = (char*)d->workspace;
     j->lay = make_layout(d);
     j->chunk = d->chunk > 0 ? d->chunk : kDefaultChunk;
+    j->slice_steps = d->slice_steps;
     j->mapping = d->mapping;
     // flights meet r-faces without a field; the Boris mover has no wave-cooperative flight
     j->chosen = (d->bz == 0.0 || d->mover == KARL_MOVER_BORIS) ? KARL_MAP_LANE : d->mapping;
@@ -1088,6 +1129,13 @@ karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches, in
     if (n_launches) *n_launches = j->run.launches;
     if (generations) *generations = j->run.generations;
     if (max_queue) *max_queue = j->run.max_queue;
+    return KARL_OK;
+}
+
+karl_status karl_job_slices(void* job, int64_t* ring_entries) {
+    Job* j = (Job*)job;
+    if (!j || !ring_entries) return fail(KARL_EINVAL, "job and ring_entries must not be NULL");
+    *ring_entries = j->run.slices;
     return KARL_OK;
 }
 

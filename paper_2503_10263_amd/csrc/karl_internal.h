@@ -138,7 +138,26 @@ struct GenArgs {
     int64_t capacity;
     unsigned int* status;          // launch status (queue overflow)
     unsigned long long* wave_segments;   // segments advanced by wave-cooperative flights (or NULL)
+    // deferred launch in slices (single job): a particle whose step count reaches a multiple of
+    // slice_mask + 1 goes to the ring when its slot is free; claim indices past n_items are ring
+    // entries.  ring_flag[k] of the entry with index i in slot k = i mod ring_cap: 2i+1 written,
+    // 2i+2 read (0: never used in this launch).  slice_mask 0: no slices.
+    uint32_t slice_mask;
+    int64_t ring_cap;
+    struct RingEntry* ring;
+    unsigned long long* ring_flag;
+    unsigned long long* ring_tail;  // ring indices reserved so far
 };
+
+// The whole state of a particle between two slices of the deferred launch.
+struct RingEntry {
+    double x, y, z, u, v, w, e, vel, s_path, t_alive, t_cell, e_exc, e_bind, e_gas;
+    unsigned long long lin, dg;
+    uint32_t pid, s;
+    int32_t sp, ir, iz, fly;
+    int64_t n_int;
+};
+static_assert(sizeof(RingEntry) == 160, "ring entries are 160 bytes");
 
 enum : unsigned int { STATUS_OVERFLOW = 1u, STATUS_NUMERIC = 2u };
 

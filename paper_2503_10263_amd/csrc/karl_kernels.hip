@@ -1803,6 +1803,161 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
     }
 }
 
+// ---------------------------------------------------------------- deferred launch in slices
+// The lanes of the deferred launch claim indices of one counter (G.fetch): index u < n_items is
+// item u of the deferred queue, u >= n_items the ring entry u - n_items.  A wave claims only
+// indices below n_items + ring_tail, i.e. items written before the launch or ring entries whose
+// producer already owns the slot, so that a claimed entry is readable a few instructions after
+// its producer took it; the lane then checks its flag once per loop iteration and never spins
+// (its producer may be another lane of the same wave).  A wave ends when every index is claimed
+// and none of its lanes holds a particle: every later ring entry is claimed by the lane that
+// wrote it, which looks for work right after.
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acquire(const unsigned long long* a) {
+    return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(unsigned long long* a, unsigned long long v) {
+    __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename Real>
+__device__ __forceinline__ void ring_write(RingEntry* e, const Part<Real>& p) {
+    e->x = (double)p.x;
+    e->y = (double)p.y;
+    e->z = (double)p.z;
+    e->u = (double)p.u;
+    e->v = (double)p.v;
+    e->w = (double)p.w;
+    e->e = (double)p.e;
+    e->vel = (double)p.vel;
+    e->s_path = (double)p.s_path;
+    e->t_alive = p.t_alive;
+    e->t_cell = p.t_cell;
+    e->e_exc = p.e_exc;
+    e->e_bind = p.e_bind;
+    e->e_gas = p.e_gas;
+    e->lin = p.lin;
+    e->dg = p.dg;
+    e->pid = p.pid;
+    e->s = p.s;
+    e->sp = p.sp;
+    e->ir = p.ir;
+    e->iz = p.iz;
+    e->fly = p.fly ? 1 : 0;
+    e->n_int = p.n_int;
+}
+
+template <typename Real>
+__device__ __forceinline__ void ring_read(const RingEntry* e, Part<Real>& p) {
+    p.x = (Real)e->x;
+    p.y = (Real)e->y;
+    p.z = (Real)e->z;
+    p.u = (Real)e->u;
+    p.v = (Real)e->v;
+    p.w = (Real)e->w;
+    p.e = (Real)e->e;
+    p.vel = (Real)e->vel;
+    p.s_path = (Real)e->s_path;
+    p.t_alive = e->t_alive;
+    p.t_cell = e->t_cell;
+    p.e_exc = e->e_exc;
+    p.e_bind = e->e_bind;
+    p.e_gas = e->e_gas;
+    p.lin = e->lin;
+    p.dg = e->dg;
+    p.pid = e->pid;
+    p.s = e->s;
+    p.sp = e->sp;
+    p.ir = e->ir;
+    p.iz = e->iz;
+    p.fly = e->fly != 0;
+    p.n_int = e->n_int;
+    p.job = 0;
+}
+
+// Work for the lanes with `need`: 1 some lane got an index, 0 every index is claimed, -1 the
+// wave lost every race for the counter this time.
+template <typename Real>
+__device__ __forceinline__ int claim(const GenArgs& G, Part<Real>& p, bool need, bool& wait) {
+    const unsigned long long m = __ballot(need);
+    const int leader = __ffsll((long long)m) - 1;
+    const unsigned long long k = (unsigned long long)__popcll(m);
+    const unsigned long long n = (unsigned long long)G.n_items;
+    unsigned long long base = 0, got = 0;
+    int res = -1;
+    if ((int)lane_id() == leader) {
+        for (int t = 0; t < 16; ++t) {
+            const unsigned long long h = ld_agent(G.fetch);
+            const unsigned long long total = n + (G.slice_mask ? ld_agent(G.ring_tail) : 0ull);
+            if (h >= total) {
+                res = 0;
+                break;
+            }
+            const unsigned long long take = (total - h < k) ? total - h : k;
+            if (atomicCAS(G.fetch, h, h + take) == h) {
+                base = h;
+                got = take;
+                res = 1;
+                break;
+            }
+        }
+    }
+    res = bc_i(res, leader);
+    if (res <= 0) return res;
+    base = bc_u64(base, leader);
+    got = bc_u64(got, leader);
+    const unsigned long long r = (unsigned long long)rank_in(m);
+    if (need && r < got) {
+        const unsigned long long u = base + r;
+        if (u < n) {
+            load_queued<Real, false>(G, (int64_t)u, p);
+            p.start = true;
+        } else {
+            p.lin = u - n;   // the claimed ring index, held in the idle lane's lineage word
+            wait = true;
+        }
+    }
+    return 1;
+}
+
+// A claimed ring entry, once its producer has written it: the lane resumes the particle.
+template <typename Real>
+__device__ __forceinline__ void take_ring(const GenArgs& G, Part<Real>& p, bool& wait) {
+    const unsigned long long i = p.lin;
+    const unsigned long long slot = i % (unsigned long long)G.ring_cap;
+    if (ld_acquire(&G.ring_flag[slot]) != 2ull * i + 1ull) return;
+    ring_read(&G.ring[slot], p);
+    st_release(&G.ring_flag[slot], 2ull * i + 2ull);   // read: the slot may take entry i + ring_cap
+    p.alive = true;
+    p.start = false;
+    wait = false;
+}
+
+// Particles of the lanes with `want` go to the end of the ring.  A slot is taken only when its
+// last entry has been read; a particle that finds its slot still in use, or keeps losing the
+// race for the ring's tail, stays on its lane for another slice.
+template <typename Real>
+__device__ __forceinline__ void ring_put(const GenArgs& G, Part<Real>& p, bool want) {
+    const unsigned long long cap = (unsigned long long)G.ring_cap;
+    for (int t = 0; t < 16 && __ballot(want); ++t) {
+        if (want) {
+            const unsigned long long j = ld_agent(G.ring_tail);
+            const unsigned long long slot = j % cap;
+            const unsigned long long free_mark = (j < cap) ? 0ull : 2ull * (j - cap) + 2ull;
+            if (ld_acquire(&G.ring_flag[slot]) != free_mark) {
+                if (ld_agent(G.ring_tail) == j) want = false;
+            } else if (atomicCAS(G.ring_tail, j, j + 1ull) == j) {
+                ring_write(&G.ring[slot], p);
+                st_release(&G.ring_flag[slot], 2ull * j + 1ull);
+                p.alive = false;
+                want = false;
+            }
+        }
+    }
+}
+
 #ifndef KARL_WAVES_PER_SIMD
 #define KARL_WAVES_PER_SIMD 1
 #endif
@@ -1884,6 +2039,37 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
     // batched: the wave's current job, first spread over the jobs by wave index
     int wjob = 0;
     if (kBatched) wjob = first_job(G, (int)(blockIdx.x * (kBlock / 64) + wid), (int)(gridDim.x * (kBlock / 64)));
+    if constexpr (kDrain != 0) {
+        // the deferred launch: every lane's first item is fixed by its thread index (the host
+        // starts the counter past them), the rest are claimed; with slices, particles go round
+        // through the ring
+        const unsigned long long gtid = (unsigned long long)blockIdx.x * kBlock + (unsigned long long)tid;
+        if (gtid < (unsigned long long)G.n_items) {
+            load_queued<Real, false>(G, (int64_t)gtid, p);
+            p.start = true;
+        }
+        bool wait = false;   // a ring entry is claimed (index in p.lin), not yet readable
+        int skip = 0;        // wave-uniform: loop iterations before idle lanes look for work again
+        for (;;) {
+            if (wait) take_ring(G, p, wait);
+            const bool need = !p.alive && !p.start && !wait;
+            if (__ballot(need)) {
+                const bool busy = __ballot(!need) != 0ull;
+                if (!busy || skip == 0) {
+                    const int c = claim<Real>(G, p, need, wait);
+                    if (c == 0 && !busy) break;   // nothing left to claim, nothing held
+                    skip = (c == 1) ? 0 : 32;
+                } else {
+                    --skip;
+                }
+            }
+            if (p.alive || p.start) advance<Real, kDrain, kBoris>(jobs[0], L0, G, p, lc);
+            if (G.slice_mask) {
+                const bool rq = p.alive && p.s != 0u && (p.s & G.slice_mask) == 0u;
+                if (__ballot(rq)) ring_put<Real>(G, p, rq);
+            }
+        }
+    } else
     for (;;) {
         const bool need = !p.alive && !p.start && !done;
         if (__ballot(need)) refill<Real, kBatched>(G, p, need, done, wjob);

@@ -39,7 +39,7 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
                 "karl_read_fields", "karl_update_target_fields", "karl_reset_tallies",
-                "karl_job_stats", "karl_job_mapping",
+                "karl_job_stats", "karl_job_slices", "karl_job_mapping",
                 "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
                 "karl_batch_stats", "karl_destroy_batch",
@@ -93,7 +93,7 @@ class JobDesc(C.Structure):
                 ("boris_dt", C.c_double * MAX_SPECIES), ("field_nr", C.c_int32),
                 ("field_nz", C.c_int32), ("field_radius", C.c_double),
                 ("field_length", C.c_double), ("e_field", C.POINTER(C.c_double)),
-                ("b_field", C.POINTER(C.c_double))]
+                ("b_field", C.POINTER(C.c_double)), ("slice_steps", C.c_int64), ("slice_ring", C.c_int64)]
 
 
 class ServerDesc(C.Structure):
@@ -139,6 +139,7 @@ def lib():
         L.karl_reset_tallies.argtypes = [C.c_void_p, C.c_void_p]
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.karl_job_slices.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.karl_job_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]
@@ -187,7 +188,7 @@ class Descriptor:
     """karl_job_desc built from a workload; keeps its host arrays alive."""
 
     def __init__(self, w, precision: int = FP64, flags: int = 0, queue_capacity: int = 0,
-                 chunk: int = 0, mapping: int = MAP_AUTO):
+                 chunk: int = 0, mapping: int = MAP_AUTO, slice_steps: int = 0, slice_ring: int = 0):
         self.keep = []
         d = JobDesc()
         d.radius, d.length, d.n_r, d.n_z = w.radius, w.length, w.n_r, w.n_z
@@ -257,6 +258,8 @@ class Descriptor:
         d.queue_capacity = queue_capacity
         d.chunk = chunk
         d.mapping = mapping
+        d.slice_steps = slice_steps
+        d.slice_ring = slice_ring
         # mover and field arrays (one binning shared by E and B)
         d.mover = getattr(w, "mover", MOVER_DRIFT)
         for s, dt in enumerate(getattr(w, "boris_dt", None) or []):
@@ -309,13 +312,15 @@ class Job:
     """One transport job on the current HIP device (workspace allocated by torch)."""
 
     def __init__(self, w, precision: str = "fp64", digests: bool = False, history: bool = False,
-                 queue_capacity: int = 0, chunk: int = 0, device=None, mapping: str = "auto"):
+                 queue_capacity: int = 0, chunk: int = 0, device=None, mapping: str = "auto",
+                 slice_steps: int = 0, slice_ring: int = 0):
         import torch
         self.w = w
         self.precision = FP32 if precision == "fp32" else FP64
         flags = (FLAG_DIGESTS if digests else 0) | (FLAG_HISTORY if history else 0)
         self.digests, self.history = digests, history
-        self.desc = Descriptor(w, self.precision, flags, queue_capacity, chunk, MAPPINGS[mapping])
+        self.desc = Descriptor(w, self.precision, flags, queue_capacity, chunk, MAPPINGS[mapping],
+                               slice_steps, slice_ring)
         self.nbytes = self.desc.workspace_bytes()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -358,6 +363,12 @@ class Job:
         check(lib().karl_job_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
         return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
                 "max_queue": q.value}
+
+    def slices(self) -> int:
+        """Particles put into the ring at the end of a slice by the deferred launches."""
+        n = C.c_int64()
+        check(lib().karl_job_slices(self.h, C.byref(n)))
+        return n.value
 
     def mapping(self) -> Dict[str, float]:
         """Mapping in use ("auto" until tuned), the segments per interaction that chose it, kernel

@@ -262,6 +262,16 @@ def _cfg1_processes(n_e: int) -> List[Process]:
 # ----------------------------------------------------------------------------
 # the five workloads
 # ----------------------------------------------------------------------------
+# Launch configuration of the measured runs.  Full case: primaries per transport call, one
+# chunk, so that the call's H2+ run in one deferred launch of about five ion lifetimes per
+# lane; that launch in slices of 2^15 steps (about half a second of an ion's 12 s), so that the
+# long histories end together.  Batched case: queue entries (76 GB of HBM), so that its 256 jobs
+# run in a few chunks with few generation launches.
+FULL_STEP_PRIMARIES = 131072
+FULL_SLICE_STEPS = 1 << 15
+BATCHED_QUEUE = 1 << 28
+
+
 def cfg_tiny(n_primaries: int = 10_000, seed: int = 1, bz: float = 0.0,
              column_cm2: float = 1.0e16, n_r: int = 1, n_z: int = 1) -> Workload:
     """Tiny plain FP64 case: 1 m tube of radius 45 mm, uniform H2 with the given column

@@ -1,7 +1,8 @@
 """Parity at the full sizes, in the launch configuration that bench.py times.
 
 Full case (1e6-primary job, 64x512 grid, tracked H2+ capped at 1e6 interactions): the
-benchmark's batch of 49152 primary ids in one karl_transport call.  The oracle computes
+benchmark's step of 131072 primary ids in one karl_transport call, as one chunk, its deferred
+launch in slices of 2^15 steps.  The oracle computes
 sampled histories one by one: their event digests and per-history energy ledgers must be
 identical.  Over the whole batch, properties that hold at any size: every particle deleted
 exactly once, one electron and one ion per ionization, the energy budget.
@@ -18,8 +19,8 @@ from paper_2503_10263_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-BENCH_BATCH = 49152
-SAMPLED = [0, 7919, 31337, BENCH_BATCH - 1]
+BENCH_BATCH = W.FULL_STEP_PRIMARIES
+SAMPLED = [0, 7919, 31337, 104729, BENCH_BATCH - 1]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,14 +44,17 @@ def _identities(c, L, n_primaries, processes, energy_rtol):
     assert abs(out / L[K.L_E_PRIMARY] - 1.0) < energy_rtol
 
 
+@pytest.mark.timeout(600)
 def test_full_case_bench_batch_sampled_histories():
     import oracle
     from paper_2503_10263_amd import karl
     w = W.cfg_full(n_primaries=1_000_000)
-    job = karl.Job(w, precision="fp64", digests=True, history=True)
+    job = karl.Job(w, precision="fp64", digests=True, history=True, chunk=BENCH_BATCH,
+                   slice_steps=W.FULL_SLICE_STEPS)
     try:
         job.transport(0, BENCH_BATCH)
         g = job.read_tallies()
+        assert job.slices() > 0          # the deferred launch ran in slices
     finally:
         job.close()
     _identities(g["counters"], g["ledger"], BENCH_BATCH, w.processes, 1e-10)
@@ -73,7 +77,7 @@ def test_batched_case_full_size_fp32():
     from paper_2503_10263_amd import karl
     ws = W.cfg_batched(n_jobs=256)
     jobs = [karl.Job(w, precision="fp32", queue_capacity=1024) for w in ws]
-    batch = karl.Batch(max_jobs=256, queue_capacity=1 << 23)
+    batch = karl.Batch(max_jobs=256, queue_capacity=W.BATCHED_QUEUE)
     try:
         batch.transport(jobs, [(0, w.n_primaries) for w in ws])
         tallies = [j.read_tallies() for j in jobs]

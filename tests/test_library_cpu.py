@@ -48,6 +48,28 @@ def test_workspace_bytes(karl):
     assert dd.workspace_bytes() >= n + 2 * 1000 * (8 + 32) - 2 * 256
 
 
+def test_slice_ring_in_the_workspace(karl):
+    """Slices of the deferred launch add a ring of 160-byte particle states and an 8-byte flag
+    per entry -- by default queue_capacity + 2^20 entries -- and nothing without slices."""
+    w = W.cfg_full(n_primaries=1000)
+    n = karl.Descriptor(w, queue_capacity=1 << 20).workspace_bytes()
+    ring = (1 << 20) + (1 << 20)
+    assert karl.Descriptor(w, queue_capacity=1 << 20, slice_ring=999).workspace_bytes() == n
+    ns = karl.Descriptor(w, queue_capacity=1 << 20, slice_steps=1 << 15).workspace_bytes()
+    assert n + ring * 168 <= ns <= n + ring * 168 + 2 * 256
+    nr = karl.Descriptor(w, queue_capacity=1 << 20, slice_steps=64, slice_ring=1000).workspace_bytes()
+    assert n + 1000 * 168 <= nr <= n + 1000 * 168 + 2 * 256
+
+
+@pytest.mark.parametrize("steps,ring", [(3, 0), (-64, 0), (1 << 31, 0), (96, 0), (64, -1)])
+def test_bad_slices_are_rejected(karl, steps, ring):
+    w = W.cfg_tiny(n_primaries=10)
+    d = karl.Descriptor(w, queue_capacity=1024, slice_steps=steps, slice_ring=ring)
+    n = C.c_uint64()
+    assert karl.lib().karl_workspace_bytes(C.byref(d.d), C.byref(n)) == karl.EINVAL
+    assert "slice" in karl.lib().karl_last_error().decode()
+
+
 def _create(karl, desc):
     h = C.c_void_p()
     return karl.lib().karl_create_job(C.byref(desc.d), C.byref(h))
