@@ -211,14 +211,14 @@ typedef struct {
        uneven loads over long cycles), and results do not depend on it, up to the summation
        order of floating-point tallies.  The species that make no products run after the other
        generations, in one launch over all their particles.  With slice_steps > 0, a particle
-       of that launch whose step count reaches a multiple of slice_steps goes back to the end of
-       the launch's work -- into a ring of slice_ring entries in the workspace, with its whole
-       state -- and its lane takes the next item.  So the long histories of the launch advance
-       in turn and end together, instead of the last ones started running on alone while the
-       other lanes idle.  A particle whose ring slot has not been read yet keeps its lane for
-       another slice.  slice_steps: 0 (no slices, no ring) or a power of two up to 2^30.
-       slice_ring: ring entries, 0: queue_capacity + 2^20 (the launch's particles plus its
-       lanes fit without full slots). */
+       of that launch goes back to the end of the launch's work every slice_steps of its steps
+       (where its slices end is staggered from particle to particle): into a ring of
+       slice_ring entries in the workspace, with its whole state, and its lane takes the next
+       item.  So the long histories of the launch advance in turn and end together, instead of
+       the last ones started running on alone while the other lanes idle.  A particle whose
+       ring slot has not been read yet keeps its lane for another slice.  slice_steps: 0 (no
+       slices, no ring) or a power of two up to 2^30.  slice_ring: ring entries, 0:
+       queue_capacity + 2^20 (the launch's particles plus its lanes fit without full slots). */
     int64_t slice_steps;
     int64_t slice_ring;
 } karl_job_desc;

@@ -297,17 +297,25 @@ struct LaneCnt {
     uint32_t step0, step1, coll0, coll1, zc0, zc1, rc0, rc1, redraw, beb, beta;
     double e_prim;
 };
+// The deferred launch's counts: species 0 (which a job defers only when its electrons make no
+// products) with one atomic per event like species 2 and 3, so that the launch keeps registers
+// for species 1 only.
+struct LaneCntLean : LaneCnt {};
+template <typename LC>
+constexpr bool kLeanCnt = __is_same(LC, LaneCntLean);
+template <bool kB, typename T, typename F> struct PickT { using type = T; };
+template <typename T, typename F> struct PickT<false, T, F> { using type = F; };
 
 // Count one event of kind idx + sp: in a per-lane register (species 0 and 1), with one atomic
 // per lane (species 2 and 3), or -- when the lane's counters are not kept per lane -- with one
 // atomic per distinct key of the wave.
-template <typename Real>
-__device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int idx, int sp) {
+template <typename Real, typename LC>
+__device__ __forceinline__ void count_ev(const Lds<Real>& L, LC& lc, int idx, int sp) {
     if (L.direct) {
         wave_count(L.cnt, idx + sp);
         return;
     }
-    if (sp > 1) {
+    if (sp > 1 || (kLeanCnt<LC> && sp == 0)) {
         atomicAdd(&L.cnt[idx + sp], 1ull);
         return;
     }
@@ -319,9 +327,9 @@ __device__ __forceinline__ void count_ev(const Lds<Real>& L, LaneCnt& lc, int id
     }
 }
 
-template <typename Real>
-__device__ __forceinline__ void count_evn(const Lds<Real>& L, LaneCnt& lc, int idx, int sp, uint32_t n) {
-    if (L.direct || sp > 1) {
+template <typename Real, typename LC>
+__device__ __forceinline__ void count_evn(const Lds<Real>& L, LC& lc, int idx, int sp, uint32_t n) {
+    if (L.direct || sp > 1 || (kLeanCnt<LC> && sp == 0)) {
         atomicAdd(&L.cnt[idx + sp], (unsigned long long)n);
         return;
     }
@@ -391,8 +399,8 @@ __device__ void kill(const DevJob& J, const Lds<Real>& L, Part<Real>& p, int rea
     p.alive = false;
 }
 
-template <typename Real>
-__device__ __forceinline__ void cross_r(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc,
+template <typename Real, typename LC>
+__device__ __forceinline__ void cross_r(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LC& lc,
                                        int f, int dir) {
     count_ev(L, lc, KARL_C_RCROSS, p.sp);
     add_u64(&J.jr[(((size_t)p.sp * (J.n_r + 1) + (size_t)f) * J.n_z + (size_t)p.iz) * 2 + (size_t)dir], 1ull);
@@ -412,8 +420,8 @@ __device__ __forceinline__ int r_cell(const Real* rf, int n_r, Real r, int guess
 // At birth the r-cell is set from the guiding-centre radius; after a collision every r-face
 // between the old and new guiding-centre radius counts as crossed.
 // sp: the particle's species (wave-uniform when the caller serves one species per pass)
-template <typename Real>
-__device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc, Real xp,
+template <typename Real, typename LC>
+__device__ bool gc_set(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LC& lc, Real xp,
                        Real yp, bool at_birth, int sp) {
     const Real iom = (Real)L.sc->inv_om[sp];
     const Real gx = xp + (p.vel * p.v) * iom;
@@ -694,9 +702,9 @@ __device__ void product_inline(const DevJob& J, const Lds<Real>& L, int sp, Real
     }
 }
 
-template <typename Real>
+template <typename Real, typename LC>
 __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                             int pi, Real xc, Real yc, LaneCnt& lc, Vec3<Real> tv, int sp) {
+                             int pi, Real xc, Real yc, LC& lc, Vec3<Real> tv, int sp) {
     const Real ef2 = (Real)L.sc->e_from_v2[sp];
     const Real v2e = (Real)L.sc->v2_from_e[sp];
     const Real B = L.eth[pi];
@@ -866,9 +874,9 @@ __device__ double k_charge_exchange(const DevJob& J, const Lds<Real>& L, Part<Re
 }
 
 // ---------------------------------------------------------------- birth (Sec. 3.5)
-template <typename Real>
+template <typename Real, typename LC>
 __device__ __forceinline__ void birth(const DevJob& J, const Lds<Real>& L, uint32_t pid, Part<Real>& p,
-                      LaneCnt& lc) {
+                      LC& lc) {
     p.lin = 0ull;
     p.pid = pid;
     if (J.source == KARL_SOURCE_BEAM || J.source == KARL_SOURCE_PAIR) {
@@ -946,8 +954,8 @@ __device__ __forceinline__ void birth(const DevJob& J, const Lds<Real>& L, uint3
 }
 
 // common start of every particle (primary or secondary); returns with p.alive set
-template <typename Real>
-__device__ __forceinline__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc) {
+template <typename Real, typename LC>
+__device__ __forceinline__ void start_particle(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LC& lc) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     p.s = 0u;
     p.n_int = 0;
@@ -1011,8 +1019,8 @@ __device__ __forceinline__ int spectrum_bin(const DevJob& J, int sp, double ee) 
 
 // crossing of z-face f in direction dir (1: +z) in the particle's ring: current collector and
 // spectrum plane (Sec. 2.3, 3.4)
-template <typename Real>
-__device__ __forceinline__ void cross_z(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LaneCnt& lc,
+template <typename Real, typename LC>
+__device__ __forceinline__ void cross_z(const DevJob& J, const Lds<Real>& L, Part<Real>& p, LC& lc,
                                         int f, int dir, int sp) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     count_ev(L, lc, KARL_C_ZCROSS, sp);
@@ -1027,8 +1035,8 @@ __device__ __forceinline__ void cross_z(const DevJob& J, const Lds<Real>& L, Par
 }
 
 // Counters and digest event of an interaction of process pi.
-template <typename Real>
-__device__ __forceinline__ void count_interaction(const DevJob& J, const Lds<Real>& L, LaneCnt& lc,
+template <typename Real, typename LC>
+__device__ __forceinline__ void count_interaction(const DevJob& J, const Lds<Real>& L, LC& lc,
                                                   Part<Real>& p, int sp, int pi) {
     count_ev(L, lc, KARL_C_COLL, sp);
     wave_count(L.cnt, KARL_C_PROC + pi);
@@ -1038,9 +1046,9 @@ __device__ __forceinline__ void count_interaction(const DevJob& J, const Lds<Rea
 
 // The interaction chosen for process pi (Sec. 2.1, 3.3) at the collision point (xc, yc, p.z),
 // after count_interaction: the kinematics of its class and the terminator's checks after it.
-template <typename Real, int kDrain>
+template <typename Real, int kDrain, typename LC>
 __device__ __forceinline__ void interact(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                         LaneCnt& lc, int sp, int pi, Real xc, Real yc) {
+                         LC& lc, int sp, int pi, Real xc, Real yc) {
     bool killed = false;
     const int kd = L.kind[pi];
     // every class but excitation and recombination starts from a target particle's velocity
@@ -1205,9 +1213,9 @@ __device__ __forceinline__ void end_movement(const DevJob& J, const Lds<Real>& L
 // in the order: outside the domain (deletion), another segment or energy bin (no interaction),
 // the drawn distance used up (interaction at the current position).  Returns whether an
 // interaction is due, with its process in *pi_out.
-template <typename Real>
+template <typename Real, typename LC>
 __device__ __forceinline__ bool boris_move(const DevJob& J, const Lds<Real>& L, Part<Real>& p,
-                                           LaneCnt& lc, int sp, int* pi_out) {
+                                           LC& lc, int sp, int* pi_out) {
     const int32_t* pidx = L.pidx + sp * KARL_MAX_PROC;
     const int np = L.sc->nps[sp];
     if (!p.fly) {
@@ -1308,9 +1316,9 @@ __device__ __forceinline__ bool boris_move(const DevJob& J, const Lds<Real>& L, 
 // kDrain: the launch that runs the deferred queue, whose species have no ionization process
 // (the job setup defers exactly those); the ionization branch is left out of that kernel.
 // kDrain == 1 also leaves out the energy-resolved density tally (jobs without it), 2 keeps it.
-template <typename Real, int kDrain = 0, bool kBoris = false>
+template <typename Real, int kDrain = 0, bool kBoris = false, typename LC>
 __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                     LaneCnt& lc) {
+                     LC& lc) {
     // batched launches serve the lanes of a wave by (job, species): the species is uniform and
     // the process metadata below become scalar loads
     const int sp = L.direct ? __builtin_amdgcn_readfirstlane(p.sp) : p.sp;
@@ -1516,9 +1524,9 @@ __device__ __forceinline__ float bc_r(float x, int j) {
 // time alive and path length by a wave-uniform loop over the crossed segments, the event
 // digest likewise.  The interaction itself is left to the next regular step, which draws the
 // same numbers, so results equal those of segment-by-segment transport.
-template <typename Real>
+template <typename Real, typename LC>
 __device__ __forceinline__ void coop_flight(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part<Real>& p,
-                            LaneCnt& lc, int j) {
+                            LC& lc, int j) {
     const bool dig = (J.flags & KARL_FLAG_DIGESTS) != 0;
     const int k = (int)lane_id();
     const Real z = bc_r(p.z, j), w = bc_r(p.w, j), e = bc_r(p.e, j), vel = bc_r(p.vel, j);
@@ -1786,9 +1794,9 @@ __device__ __forceinline__ void refill(const GenArgs& G, Part<Real>& p, bool nee
 }
 
 // One unit of work for a lane: start its fetched particle, or move it by one flight segment.
-template <typename Real, int kDrain = 0, bool kBoris = false>
+template <typename Real, int kDrain = 0, bool kBoris = false, typename LC>
 __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, const GenArgs& G,
-                                        Part<Real>& p, LaneCnt& lc) {
+                                        Part<Real>& p, LC& lc) {
     if (p.start) {
         p.start = false;
         if (!kDrain && G.mode == 0) {
@@ -2030,7 +2038,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         __builtin_amdgcn_wave_barrier();
     }
 
-    LaneCnt lc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
+    typename PickT<kDrain != 0, LaneCntLean, LaneCnt>::type lc{};
     Part<Real> p;
     p.alive = false;
     p.start = false;
@@ -2058,14 +2066,17 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
                 if (!busy || skip == 0) {
                     const int c = claim<Real>(G, p, need, wait);
                     if (c == 0 && !busy) break;   // nothing left to claim, nothing held
-                    skip = (c == 1) ? 0 : 32;
+                    skip = (c == 1) ? 0 : (c == 0) ? 32 : 4;
                 } else {
                     --skip;
                 }
             }
             if (p.alive || p.start) advance<Real, kDrain, kBoris>(jobs[0], L0, G, p, lc);
             if (G.slice_mask) {
-                const bool rq = p.alive && p.s != 0u && (p.s & G.slice_mask) == 0u;
+                // slice ends where the step count plus the (well mixed) low lineage bits is a
+                // multiple of the slice: particles that start together still leave the ring's
+                // tail and the claim counter a few at a time
+                const bool rq = p.alive && p.s != 0u && ((p.s + (uint32_t)p.lin) & G.slice_mask) == 0u;
                 if (__ballot(rq)) ring_put<Real>(G, p, rq);
             }
         }
