@@ -166,6 +166,10 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
                             bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s);
 hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s);
+// the batched kernels (their own compilation unit): launch and blocks per CU
+hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
+                                    int grid, int block, size_t lds, hipStream_t s);
+hipError_t transport_occupancy_batched(int precision, bool boris, int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
 // Regroup n queue entries by job: count per job, exclusive scan into first/count, scatter.

@@ -2256,6 +2256,32 @@ __global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long l
 
 }  // namespace
 
+#ifdef KARL_BATCHED_UNIT
+// The batched kernels, compiled in a unit of their own (see karl_kernels_batched.hip).
+hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
+                                    int grid, int block, size_t lds, hipStream_t s) {
+    if (precision == KARL_FP32) {
+        if (boris)
+            hipLaunchKernelGGL((transport_kernel<float, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    } else {
+        if (boris)
+            hipLaunchKernelGGL((transport_kernel<double, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t transport_occupancy_batched(int precision, bool boris, int block, size_t lds, int* blocks_per_cu) {
+    if (precision == KARL_FP32)
+        return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true, false, 0, true>, block, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
+    return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true, false, 0, true>, block, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
+}
+#else
 size_t lds_bytes(const DevJob& j, int precision) {
     const size_t rs = precision == KARL_FP32 ? sizeof(float) : sizeof(double);
     size_t b = (size_t)(kNCnt + kNLed) * 8 + (size_t)(kS + 2) * KARL_MAX_PROC * sizeof(int32_t);
@@ -2282,13 +2308,9 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
         }
         return hipGetLastError();
     }
+    if (batched) return launch_transport_batched(jobs_dev, boris, g, precision, grid, block, lds, s);
     if (precision == KARL_FP32) {
-        if (batched) {
-            if (boris)
-                hipLaunchKernelGGL((transport_kernel<float, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-            else
-                hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        } else if (coop) {
+        if (coop) {
             hipLaunchKernelGGL((transport_kernel<float, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         } else if (boris) {
             hipLaunchKernelGGL((transport_kernel<float, false, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
@@ -2296,12 +2318,7 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
             hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         }
     } else {
-        if (batched) {
-            if (boris)
-                hipLaunchKernelGGL((transport_kernel<double, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-            else
-                hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        } else if (coop) {
+        if (coop) {
             hipLaunchKernelGGL((transport_kernel<double, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         } else if (boris) {
             hipLaunchKernelGGL((transport_kernel<double, false, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
@@ -2363,22 +2380,19 @@ hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drai
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 1>, block, lds);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 1>, block, lds);
     }
+    if (batched) return transport_occupancy_batched(precision, boris, block, lds, blocks_per_cu);
     if (precision == KARL_FP32) {
-        if (batched)
-            return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true, false, 0, true>, block, lds)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
         if (coop)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, true>, block, lds);
         return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 0, true>, block, lds)
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false>, block, lds);
     }
-    if (batched)
-        return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true, false, 0, true>, block, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
     if (coop)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, true>, block, lds);
     return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 0, true>, block, lds)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false>, block, lds);
 }
+
+#endif
 
 }  // namespace karl
