@@ -99,9 +99,11 @@ uint64_t ko_mix64(uint64_t z) {
 
 
 /* ------------------------------------------------------------------ */
-/* elementary functions written out with IEEE basic operations only, so */
-/* that an independent implementation of the same steps reproduces them */
-/* bit for bit (the guiding-centre phase amplifies any 1-ulp difference) */
+/* elementary functions written out with IEEE basic operations only     */
+/* (fused multiply-add, rounded once, among them: every series step is   */
+/* one fma), so that an independent implementation of the same steps     */
+/* reproduces them bit for bit (the guiding-centre phase amplifies any   */
+/* 1-ulp difference)                                                     */
 /* ------------------------------------------------------------------ */
 #define SQRT_HALF 0.70710678118654757
 #define LN2_HI 0.6931471805601177        /* ln 2 rounded to 40 bits: e*LN2_HI is exact */
@@ -127,22 +129,22 @@ double ko_log(double x) {
     double f = m - 1.0;
     double s = f / (m + 1.0);
     double z = s * s;
-    double p = 0.04;                      /* 1/25 */
-    p = 0.043478260869565216 + z * p;     /* 1/23 */
-    p = 0.047619047619047616 + z * p;     /* 1/21 */
-    p = 0.05263157894736842 + z * p;      /* 1/19 */
-    p = 0.058823529411764705 + z * p;     /* 1/17 */
-    p = 0.06666666666666667 + z * p;      /* 1/15 */
-    p = 0.07692307692307693 + z * p;      /* 1/13 */
-    p = 0.09090909090909091 + z * p;      /* 1/11 */
-    p = 0.1111111111111111 + z * p;       /* 1/9  */
-    p = 0.14285714285714285 + z * p;      /* 1/7  */
-    p = 0.2 + z * p;                      /* 1/5  */
-    p = 0.3333333333333333 + z * p;       /* 1/3  */
+    double p = 0.04;                             /* 1/25 */
+    p = fma(z, p, 0.043478260869565216);         /* 1/23 */
+    p = fma(z, p, 0.047619047619047616);         /* 1/21 */
+    p = fma(z, p, 0.05263157894736842);          /* 1/19 */
+    p = fma(z, p, 0.058823529411764705);         /* 1/17 */
+    p = fma(z, p, 0.06666666666666667);          /* 1/15 */
+    p = fma(z, p, 0.07692307692307693);          /* 1/13 */
+    p = fma(z, p, 0.09090909090909091);          /* 1/11 */
+    p = fma(z, p, 0.1111111111111111);           /* 1/9  */
+    p = fma(z, p, 0.14285714285714285);          /* 1/7  */
+    p = fma(z, p, 0.2);                          /* 1/5  */
+    p = fma(z, p, 0.3333333333333333);           /* 1/3  */
     double t = 2.0 * s;
-    double lm = t + t * (z * p);
+    double lm = fma(t, z * p, t);
     double de = (double)e;
-    return de * LN2_HI + (de * LN2_LO + lm);
+    return fma(de, LN2_HI, fma(de, LN2_LO, lm));
 }
 
 /* sin and cos: r = x - k pi/2 (Cody-Waite with four 26-bit pieces of pi/2, exact products
@@ -158,34 +160,34 @@ void ko_sincos(double x, double* sn, double* cs) {
     if (fabs(x) > PIO4) {
         double xx = x;
         if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / TWO_PI) * TWO_PI;
-        double k = floor(xx * TWO_OVER_PI + 0.5);
-        r = xx - k * PIO2_1;
-        r = r - k * PIO2_2;
-        r = r - k * PIO2_3;
-        r = r - k * PIO2_4;
+        double k = floor(fma(xx, TWO_OVER_PI, 0.5));
+        r = fma(-k, PIO2_1, xx);
+        r = fma(-k, PIO2_2, r);
+        r = fma(-k, PIO2_3, r);
+        r = fma(-k, PIO2_4, r);
         q = (long long)k;
     }
     double z = r * r;
-    double ps = -8.22063524662433e-18;    /* -1/19! */
-    ps = 2.8114572543455206e-15 + z * ps; /*  1/17! */
-    ps = -7.647163731819816e-13 + z * ps; /* -1/15! */
-    ps = 1.6059043836821613e-10 + z * ps; /*  1/13! */
-    ps = -2.505210838544172e-08 + z * ps; /* -1/11! */
-    ps = 2.7557319223985893e-06 + z * ps; /*  1/9!  */
-    ps = -0.0001984126984126984 + z * ps; /* -1/7!  */
-    ps = 0.008333333333333333 + z * ps;   /*  1/5!  */
-    ps = -0.16666666666666666 + z * ps;   /* -1/3!  */
-    double sv = r + r * (z * ps);
-    double pc = 4.110317623312165e-19;    /*  1/20! */
-    pc = -1.5619206968586225e-16 + z * pc; /* -1/18! */
-    pc = 4.779477332387385e-14 + z * pc;  /*  1/16! */
-    pc = -1.1470745597729725e-11 + z * pc; /* -1/14! */
-    pc = 2.08767569878681e-09 + z * pc;   /*  1/12! */
-    pc = -2.755731922398589e-07 + z * pc; /* -1/10! */
-    pc = 2.48015873015873e-05 + z * pc;   /*  1/8!  */
-    pc = -0.001388888888888889 + z * pc;  /* -1/6!  */
-    pc = 0.041666666666666664 + z * pc;   /*  1/4!  */
-    double cv = (1.0 - 0.5 * z) + (z * z) * pc;
+    double ps = -8.22063524662433e-18;           /* -1/19! */
+    ps = fma(z, ps, 2.8114572543455206e-15);     /*  1/17! */
+    ps = fma(z, ps, -7.647163731819816e-13);     /* -1/15! */
+    ps = fma(z, ps, 1.6059043836821613e-10);     /*  1/13! */
+    ps = fma(z, ps, -2.505210838544172e-08);     /* -1/11! */
+    ps = fma(z, ps, 2.7557319223985893e-06);     /*  1/9!  */
+    ps = fma(z, ps, -0.0001984126984126984);     /* -1/7!  */
+    ps = fma(z, ps, 0.008333333333333333);       /*  1/5!  */
+    ps = fma(z, ps, -0.16666666666666666);       /* -1/3!  */
+    double sv = fma(r, z * ps, r);
+    double pc = 4.110317623312165e-19;           /*  1/20! */
+    pc = fma(z, pc, -1.5619206968586225e-16);    /* -1/18! */
+    pc = fma(z, pc, 4.779477332387385e-14);      /*  1/16! */
+    pc = fma(z, pc, -1.1470745597729725e-11);    /* -1/14! */
+    pc = fma(z, pc, 2.08767569878681e-09);       /*  1/12! */
+    pc = fma(z, pc, -2.755731922398589e-07);     /* -1/10! */
+    pc = fma(z, pc, 2.48015873015873e-05);       /*  1/8!  */
+    pc = fma(z, pc, -0.001388888888888889);      /* -1/6!  */
+    pc = fma(z, pc, 0.041666666666666664);       /*  1/4!  */
+    double cv = fma(z * z, pc, fma(-0.5, z, 1.0));
     switch (q & 3) {
         case 0: *sn = sv; *cs = cv; break;
         case 1: *sn = cv; *cs = -sv; break;

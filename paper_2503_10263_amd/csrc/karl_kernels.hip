@@ -42,11 +42,12 @@ constexpr int kNCnt = KARL_NCOUNTERS;
 constexpr int kNLed = KARL_NLEDGER;
 
 // ---------------------------------------------------------------- elementary functions
-// FP64 logarithm and sine/cosine built from IEEE basic operations only.  The guiding-centre
-// phase (omega t ~ 1e5 rad) amplifies any 1-ulp difference of a transcendental roughly
-// fifty-fold per collision, so these are spelled out step by step -- frexp reduction and
-// atanh series for ln, Cody-Waite reduction by pi/2 in four 26-bit pieces and Taylor
-// series for sin/cos -- which any other evaluation of the same steps reproduces exactly.
+// FP64 logarithm and sine/cosine built from IEEE basic operations only (fused multiply-add,
+// rounded once, among them).  The guiding-centre phase (omega t ~ 1e5 rad) amplifies any
+// 1-ulp difference of a transcendental roughly fifty-fold per collision, so these are spelled
+// out step by step -- frexp reduction and atanh series for ln, Cody-Waite reduction by pi/2
+// in four 26-bit pieces and Taylor series for sin/cos, each series step one fused
+// multiply-add -- which any other evaluation of the same steps reproduces exactly.
 constexpr double kSqrtHalf = 0.70710678118654757;
 constexpr double kLn2Hi = 0.6931471805601177;         // ln 2 to 40 bits (e * hi exact)
 constexpr double kLn2Lo = -1.7239444525614835e-13;    // ln 2 - hi
@@ -70,21 +71,21 @@ __device__ __forceinline__ double klog(double x) {
     const double s = f / (m + 1.0);          // ln m = 2 atanh(s)
     const double z = s * s;
     double p = 0.04;                         // coefficients 1/(2n+1), n = 12 .. 1
-    p = 0.043478260869565216 + z * p;
-    p = 0.047619047619047616 + z * p;
-    p = 0.05263157894736842 + z * p;
-    p = 0.058823529411764705 + z * p;
-    p = 0.06666666666666667 + z * p;
-    p = 0.07692307692307693 + z * p;
-    p = 0.09090909090909091 + z * p;
-    p = 0.1111111111111111 + z * p;
-    p = 0.14285714285714285 + z * p;
-    p = 0.2 + z * p;
-    p = 0.3333333333333333 + z * p;
+    p = fma(z, p, 0.043478260869565216);
+    p = fma(z, p, 0.047619047619047616);
+    p = fma(z, p, 0.05263157894736842);
+    p = fma(z, p, 0.058823529411764705);
+    p = fma(z, p, 0.06666666666666667);
+    p = fma(z, p, 0.07692307692307693);
+    p = fma(z, p, 0.09090909090909091);
+    p = fma(z, p, 0.1111111111111111);
+    p = fma(z, p, 0.14285714285714285);
+    p = fma(z, p, 0.2);
+    p = fma(z, p, 0.3333333333333333);
     const double t = 2.0 * s;
-    const double lm = t + t * (z * p);
+    const double lm = fma(t, z * p, t);
     const double de = (double)e;
-    return de * kLn2Hi + (de * kLn2Lo + lm);
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
 }
 __device__ __forceinline__ float klog(float x) { return logf(x); }
 
@@ -99,34 +100,34 @@ __device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
     if (fabs(x) > kPiO4) {
         double xx = x;
         if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / kTWO_PI_DEF) * kTWO_PI_DEF;
-        const double k = floor(xx * kTwoOverPi + 0.5);
-        r = xx - k * kPiO2_1;
-        r = r - k * kPiO2_2;
-        r = r - k * kPiO2_3;
-        r = r - k * kPiO2_4;
+        const double k = floor(fma(xx, kTwoOverPi, 0.5));
+        r = fma(-k, kPiO2_1, xx);
+        r = fma(-k, kPiO2_2, r);
+        r = fma(-k, kPiO2_3, r);
+        r = fma(-k, kPiO2_4, r);
         q = (long long)k;
     }
     const double z = r * r;
     double ps = -8.22063524662433e-18;       // sine: -1/19! ... -1/3!
-    ps = 2.8114572543455206e-15 + z * ps;
-    ps = -7.647163731819816e-13 + z * ps;
-    ps = 1.6059043836821613e-10 + z * ps;
-    ps = -2.505210838544172e-08 + z * ps;
-    ps = 2.7557319223985893e-06 + z * ps;
-    ps = -0.0001984126984126984 + z * ps;
-    ps = 0.008333333333333333 + z * ps;
-    ps = -0.16666666666666666 + z * ps;
-    const double sv = r + r * (z * ps);
+    ps = fma(z, ps, 2.8114572543455206e-15);
+    ps = fma(z, ps, -7.647163731819816e-13);
+    ps = fma(z, ps, 1.6059043836821613e-10);
+    ps = fma(z, ps, -2.505210838544172e-08);
+    ps = fma(z, ps, 2.7557319223985893e-06);
+    ps = fma(z, ps, -0.0001984126984126984);
+    ps = fma(z, ps, 0.008333333333333333);
+    ps = fma(z, ps, -0.16666666666666666);
+    const double sv = fma(r, z * ps, r);
     double pc = 4.110317623312165e-19;       // cosine: 1/20! ... 1/4!
-    pc = -1.5619206968586225e-16 + z * pc;
-    pc = 4.779477332387385e-14 + z * pc;
-    pc = -1.1470745597729725e-11 + z * pc;
-    pc = 2.08767569878681e-09 + z * pc;
-    pc = -2.755731922398589e-07 + z * pc;
-    pc = 2.48015873015873e-05 + z * pc;
-    pc = -0.001388888888888889 + z * pc;
-    pc = 0.041666666666666664 + z * pc;
-    const double cv = (1.0 - 0.5 * z) + (z * z) * pc;
+    pc = fma(z, pc, -1.5619206968586225e-16);
+    pc = fma(z, pc, 4.779477332387385e-14);
+    pc = fma(z, pc, -1.1470745597729725e-11);
+    pc = fma(z, pc, 2.08767569878681e-09);
+    pc = fma(z, pc, -2.755731922398589e-07);
+    pc = fma(z, pc, 2.48015873015873e-05);
+    pc = fma(z, pc, -0.001388888888888889);
+    pc = fma(z, pc, 0.041666666666666664);
+    const double cv = fma(z * z, pc, fma(-0.5, z, 1.0));
     switch (q & 3) {
         case 0: *sn = sv; *cs = cv; break;
         case 1: *sn = cv; *cs = -sv; break;
