@@ -58,6 +58,19 @@ constexpr double kPiO2_2 = -1.3909067675399456e-08;
 constexpr double kPiO2_3 = 6.123233932053594e-17;
 constexpr double kPiO2_4 = 6.368317178484799e-25;
 
+// A series constant.  The batched unit keeps the compiler's hoisting of loop invariants, which
+// would hold every FP64 coefficient of these series in registers across the transport loop;
+// there each one is pinned to a scalar register pair at its use instead (an empty volatile asm
+// cannot be hoisted), and the fused multiply-add takes it as its one scalar operand.
+#ifdef KARL_BATCHED_UNIT
+__device__ __forceinline__ double KSC(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+#else
+#define KSC(c) (c)
+#endif
+
 __device__ __forceinline__ double klog(double x) {
     if (!(x > 0.0)) return (x == 0.0) ? -INFINITY : NAN;
     if (isinf(x)) return x;
@@ -71,21 +84,21 @@ __device__ __forceinline__ double klog(double x) {
     const double s = f / (m + 1.0);          // ln m = 2 atanh(s)
     const double z = s * s;
     double p = 0.04;                         // coefficients 1/(2n+1), n = 12 .. 1
-    p = fma(z, p, 0.043478260869565216);
-    p = fma(z, p, 0.047619047619047616);
-    p = fma(z, p, 0.05263157894736842);
-    p = fma(z, p, 0.058823529411764705);
-    p = fma(z, p, 0.06666666666666667);
-    p = fma(z, p, 0.07692307692307693);
-    p = fma(z, p, 0.09090909090909091);
-    p = fma(z, p, 0.1111111111111111);
-    p = fma(z, p, 0.14285714285714285);
-    p = fma(z, p, 0.2);
-    p = fma(z, p, 0.3333333333333333);
+    p = fma(z, p, KSC(0.043478260869565216));
+    p = fma(z, p, KSC(0.047619047619047616));
+    p = fma(z, p, KSC(0.05263157894736842));
+    p = fma(z, p, KSC(0.058823529411764705));
+    p = fma(z, p, KSC(0.06666666666666667));
+    p = fma(z, p, KSC(0.07692307692307693));
+    p = fma(z, p, KSC(0.09090909090909091));
+    p = fma(z, p, KSC(0.1111111111111111));
+    p = fma(z, p, KSC(0.14285714285714285));
+    p = fma(z, p, KSC(0.2));
+    p = fma(z, p, KSC(0.3333333333333333));
     const double t = 2.0 * s;
     const double lm = fma(t, z * p, t);
     const double de = (double)e;
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    return fma(de, KSC(kLn2Hi), fma(de, KSC(kLn2Lo), lm));
 }
 __device__ __forceinline__ float klog(float x) { return logf(x); }
 
@@ -100,33 +113,33 @@ __device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
     if (fabs(x) > kPiO4) {
         double xx = x;
         if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / kTWO_PI_DEF) * kTWO_PI_DEF;
-        const double k = floor(fma(xx, kTwoOverPi, 0.5));
-        r = fma(-k, kPiO2_1, xx);
-        r = fma(-k, kPiO2_2, r);
-        r = fma(-k, kPiO2_3, r);
-        r = fma(-k, kPiO2_4, r);
+        const double k = floor(fma(xx, KSC(kTwoOverPi), 0.5));
+        r = fma(-k, KSC(kPiO2_1), xx);
+        r = fma(-k, KSC(kPiO2_2), r);
+        r = fma(-k, KSC(kPiO2_3), r);
+        r = fma(-k, KSC(kPiO2_4), r);
         q = (long long)k;
     }
     const double z = r * r;
     double ps = -8.22063524662433e-18;       // sine: -1/19! ... -1/3!
-    ps = fma(z, ps, 2.8114572543455206e-15);
-    ps = fma(z, ps, -7.647163731819816e-13);
-    ps = fma(z, ps, 1.6059043836821613e-10);
-    ps = fma(z, ps, -2.505210838544172e-08);
-    ps = fma(z, ps, 2.7557319223985893e-06);
-    ps = fma(z, ps, -0.0001984126984126984);
-    ps = fma(z, ps, 0.008333333333333333);
-    ps = fma(z, ps, -0.16666666666666666);
+    ps = fma(z, ps, KSC(2.8114572543455206e-15));
+    ps = fma(z, ps, KSC(-7.647163731819816e-13));
+    ps = fma(z, ps, KSC(1.6059043836821613e-10));
+    ps = fma(z, ps, KSC(-2.505210838544172e-08));
+    ps = fma(z, ps, KSC(2.7557319223985893e-06));
+    ps = fma(z, ps, KSC(-0.0001984126984126984));
+    ps = fma(z, ps, KSC(0.008333333333333333));
+    ps = fma(z, ps, KSC(-0.16666666666666666));
     const double sv = fma(r, z * ps, r);
     double pc = 4.110317623312165e-19;       // cosine: 1/20! ... 1/4!
-    pc = fma(z, pc, -1.5619206968586225e-16);
-    pc = fma(z, pc, 4.779477332387385e-14);
-    pc = fma(z, pc, -1.1470745597729725e-11);
-    pc = fma(z, pc, 2.08767569878681e-09);
-    pc = fma(z, pc, -2.755731922398589e-07);
-    pc = fma(z, pc, 2.48015873015873e-05);
-    pc = fma(z, pc, -0.001388888888888889);
-    pc = fma(z, pc, 0.041666666666666664);
+    pc = fma(z, pc, KSC(-1.5619206968586225e-16));
+    pc = fma(z, pc, KSC(4.779477332387385e-14));
+    pc = fma(z, pc, KSC(-1.1470745597729725e-11));
+    pc = fma(z, pc, KSC(2.08767569878681e-09));
+    pc = fma(z, pc, KSC(-2.755731922398589e-07));
+    pc = fma(z, pc, KSC(2.48015873015873e-05));
+    pc = fma(z, pc, KSC(-0.001388888888888889));
+    pc = fma(z, pc, KSC(0.041666666666666664));
     const double cv = fma(z * z, pc, fma(-0.5, z, 1.0));
     switch (q & 3) {
         case 0: *sn = sv; *cs = cv; break;
