@@ -177,8 +177,13 @@ template <> struct Prec<float> {
 
 // ---------------------------------------------------------------- random numbers
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 products
-// with the Weyl key schedule.
+// with the Weyl key schedule.  Each round's two three-way exclusive ors are one gfx950
+// three-input bit operation each (truth table 0x96 = a ^ b ^ c).
 struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
                                      uint32_t c2, uint32_t c3) {
@@ -186,8 +191,8 @@ __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint
     for (int r = 0; r < 10; ++r) {
         const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
         const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
