@@ -148,7 +148,17 @@ __device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
         default: *sn = -cv; *cs = sv; break;
     }
 }
-__device__ __forceinline__ void ksincos(float x, float* s, float* c) { sincosf(x, s, c); }
+// FP32 transport state: sine and cosine in single precision from the hardware's sine and cosine,
+// which take the angle in revolutions.  The angle is first brought to [-1/2, 1/2] revolution
+// (x/2pi minus its nearest integer): at the guiding-centre phases of up to ~1e5 rad this adds
+// about as much error as the single-precision rounding of x itself (4e-3 rad), and it replaces
+// the library's exact large-argument reduction, which every wave holding one such lane ran.
+__device__ __forceinline__ void ksincos(float x, float* s, float* c) {
+    float r = x * 0.15915494309189535f;
+    r = r - rintf(r);
+    *s = __builtin_amdgcn_sinf(r);
+    *c = __builtin_amdgcn_cosf(r);
+}
 
 __device__ __forceinline__ double ksqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float ksqrt(float x) { return sqrtf(x); }
