@@ -29,6 +29,10 @@ HIPCC_FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 transport state: single-precision division and square root from the hardware's
+    # reciprocal and square root (about 2.5 ulp) instead of the correctly rounded expansions;
+    # FP64 code is unaffected (the FP64 kernels compile to identical instructions)
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
 ]
 
 
