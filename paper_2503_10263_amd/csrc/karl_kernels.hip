@@ -100,7 +100,9 @@ __device__ __forceinline__ double klog(double x) {
     const double de = (double)e;
     return fma(de, KSC(kLn2Hi), fma(de, KSC(kLn2Lo), lm));
 }
-__device__ __forceinline__ float klog(float x) { return logf(x); }
+// FP32 transport state: natural logarithm from the hardware's single-precision base-2 logarithm
+// (its arguments here -- energies, uniforms of at least 2^-24 -- are normal numbers or 0).
+__device__ __forceinline__ float klog(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 
 __device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
     if (!isfinite(x)) {
