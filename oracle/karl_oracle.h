@@ -5,8 +5,9 @@
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or call
  * this code: only the tests, the smoke check and the CPU-baseline leg of the
  * benchmark use it.  It shares no code, header, table or constant with the HIP
- * library; it is written from the paper and from the reading of it listed in the
- * design notes (draw schedule, geometry, kinematics).
+ * library; it is written from the paper, and where the paper leaves a choice open
+ * (the draw schedule of the random numbers, geometry conventions, kinematic details)
+ * each function states the reading it takes.
  *
  * All arrays are host memory owned by the caller.  Functions return 0 on success
  * and a negative value on invalid input; they never abort.
