@@ -16,6 +16,7 @@ LIB = os.path.join(PKG, "libkarl.so")
 # batched kernels, in a unit of their own, keep it (they measured 3 % slower without)
 UNITS = [
     ("karl_kernels.hip", ["-mllvm", "-disable-machine-licm"]),
+    ("karl_kernels_drain.hip", ["-mllvm", "-disable-machine-licm"]),
     ("karl_kernels_batched.hip", []),
     ("karl_api.hip", []),
     ("karl_server.hip", []),

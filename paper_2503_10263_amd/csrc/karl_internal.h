@@ -166,6 +166,10 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
                             bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s);
 hipError_t launch_target_fields(const DevJob& j, double t_sim, hipStream_t s);
+// the deferred-launch kernels (their own compilation unit): launch and blocks per CU
+hipError_t launch_transport_drain(const DevJob* jobs_dev, bool dense, const GenArgs& g, int precision,
+                                  int grid, int block, size_t lds, hipStream_t s);
+hipError_t transport_occupancy_drain(int precision, int block, size_t lds, int* blocks_per_cu);
 // the batched kernels (their own compilation unit): launch and blocks per CU
 hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
                                     int grid, int block, size_t lds, hipStream_t s);

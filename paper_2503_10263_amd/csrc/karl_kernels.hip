@@ -58,17 +58,39 @@ constexpr double kPiO2_2 = -1.3909067675399456e-08;
 constexpr double kPiO2_3 = 6.123233932053594e-17;
 constexpr double kPiO2_4 = 6.368317178484799e-25;
 
-// A series constant.  The batched unit keeps the compiler's hoisting of loop invariants, which
-// would hold every FP64 coefficient of these series in registers across the transport loop;
-// there each one is pinned to a scalar register pair at its use instead (an empty volatile asm
-// cannot be hoisted), and the fused multiply-add takes it as its one scalar operand.
-#ifdef KARL_BATCHED_UNIT
-__device__ __forceinline__ double KSC(double c) {
+// The constants of the FP64 series below, in the order they are used.  The deferred-launch
+// kernels (their own unit) read them from a copy in LDS that the launch stages at its start: a
+// 64-bit LDS read per use, beside the vector pipeline, where a literal costs two vector moves
+// before an accumulating multiply-add (the other single-job kernels keep the literals: there the
+// early LDS reads held too many registers).  The batched unit keeps the compiler's hoisting of
+// loop invariants, which would hold every coefficient in registers across the transport loop;
+// there each one is pinned to a scalar register pair at its use (an empty volatile asm cannot
+// be hoisted), and the fused multiply-add takes it as its one scalar operand.
+constexpr double kSeriesTab[] = {
+    0.04, 0.043478260869565216, 0.047619047619047616, 0.05263157894736842,   // ln: 1/(2n+1),
+    0.058823529411764705, 0.06666666666666667, 0.07692307692307693,           // n = 12 .. 1
+    0.09090909090909091, 0.1111111111111111, 0.14285714285714285, 0.2, 0.3333333333333333,
+    kLn2Hi, kLn2Lo,                                                           // 12, 13
+    kTwoOverPi, kPiO2_1, kPiO2_2, kPiO2_3, kPiO2_4,                           // 14 .. 18
+    -8.22063524662433e-18, 2.8114572543455206e-15, -7.647163731819816e-13,    // sine: -1/19! ..
+    1.6059043836821613e-10, -2.505210838544172e-08, 2.7557319223985893e-06,   // -1/3!, 19 .. 27
+    -0.0001984126984126984, 0.008333333333333333, -0.16666666666666666,
+    4.110317623312165e-19, -1.5619206968586225e-16, 4.779477332387385e-14,    // cosine: 1/20! ..
+    -1.1470745597729725e-11, 2.08767569878681e-09, -2.755731922398589e-07,    // 1/4!, 28 .. 36
+    2.48015873015873e-05, -0.001388888888888889, 0.041666666666666664,
+};
+constexpr int kNSeries = (int)(sizeof(kSeriesTab) / sizeof(double));
+#if defined(KARL_BATCHED_UNIT)
+__device__ __forceinline__ double KC(int i) {
+    double c = kSeriesTab[i];
     asm volatile("" : "+s"(c));
     return c;
 }
+#elif defined(KARL_DRAIN_UNIT)
+__shared__ double s_series[kNSeries];
+#define KC(i) (s_series[(i)])
 #else
-#define KSC(c) (c)
+#define KC(i) (kSeriesTab[(i)])
 #endif
 
 __device__ __forceinline__ double klog(double x) {
@@ -83,22 +105,22 @@ __device__ __forceinline__ double klog(double x) {
     const double f = m - 1.0;
     const double s = f / (m + 1.0);          // ln m = 2 atanh(s)
     const double z = s * s;
-    double p = 0.04;                         // coefficients 1/(2n+1), n = 12 .. 1
-    p = fma(z, p, KSC(0.043478260869565216));
-    p = fma(z, p, KSC(0.047619047619047616));
-    p = fma(z, p, KSC(0.05263157894736842));
-    p = fma(z, p, KSC(0.058823529411764705));
-    p = fma(z, p, KSC(0.06666666666666667));
-    p = fma(z, p, KSC(0.07692307692307693));
-    p = fma(z, p, KSC(0.09090909090909091));
-    p = fma(z, p, KSC(0.1111111111111111));
-    p = fma(z, p, KSC(0.14285714285714285));
-    p = fma(z, p, KSC(0.2));
-    p = fma(z, p, KSC(0.3333333333333333));
+    double p = KC(0);                        // coefficients 1/(2n+1), n = 12 .. 1
+    p = fma(z, p, KC(1));
+    p = fma(z, p, KC(2));
+    p = fma(z, p, KC(3));
+    p = fma(z, p, KC(4));
+    p = fma(z, p, KC(5));
+    p = fma(z, p, KC(6));
+    p = fma(z, p, KC(7));
+    p = fma(z, p, KC(8));
+    p = fma(z, p, KC(9));
+    p = fma(z, p, KC(10));
+    p = fma(z, p, KC(11));
     const double t = 2.0 * s;
     const double lm = fma(t, z * p, t);
     const double de = (double)e;
-    return fma(de, KSC(kLn2Hi), fma(de, KSC(kLn2Lo), lm));
+    return fma(de, KC(12), fma(de, KC(13), lm));
 }
 // FP32 transport state: natural logarithm from the hardware's single-precision base-2 logarithm
 // (its arguments here -- energies, uniforms of at least 2^-24 -- are normal numbers or 0).
@@ -115,33 +137,33 @@ __device__ __forceinline__ void ksincos(double x, double* sn, double* cs) {
     if (fabs(x) > kPiO4) {
         double xx = x;
         if (fabs(xx) >= 2.0e8) xx = xx - trunc(xx / kTWO_PI_DEF) * kTWO_PI_DEF;
-        const double k = floor(fma(xx, KSC(kTwoOverPi), 0.5));
-        r = fma(-k, KSC(kPiO2_1), xx);
-        r = fma(-k, KSC(kPiO2_2), r);
-        r = fma(-k, KSC(kPiO2_3), r);
-        r = fma(-k, KSC(kPiO2_4), r);
+        const double k = floor(fma(xx, KC(14), 0.5));
+        r = fma(-k, KC(15), xx);
+        r = fma(-k, KC(16), r);
+        r = fma(-k, KC(17), r);
+        r = fma(-k, KC(18), r);
         q = (long long)k;
     }
     const double z = r * r;
-    double ps = -8.22063524662433e-18;       // sine: -1/19! ... -1/3!
-    ps = fma(z, ps, KSC(2.8114572543455206e-15));
-    ps = fma(z, ps, KSC(-7.647163731819816e-13));
-    ps = fma(z, ps, KSC(1.6059043836821613e-10));
-    ps = fma(z, ps, KSC(-2.505210838544172e-08));
-    ps = fma(z, ps, KSC(2.7557319223985893e-06));
-    ps = fma(z, ps, KSC(-0.0001984126984126984));
-    ps = fma(z, ps, KSC(0.008333333333333333));
-    ps = fma(z, ps, KSC(-0.16666666666666666));
+    double ps = KC(19);                      // sine: -1/19! ... -1/3!
+    ps = fma(z, ps, KC(20));
+    ps = fma(z, ps, KC(21));
+    ps = fma(z, ps, KC(22));
+    ps = fma(z, ps, KC(23));
+    ps = fma(z, ps, KC(24));
+    ps = fma(z, ps, KC(25));
+    ps = fma(z, ps, KC(26));
+    ps = fma(z, ps, KC(27));
     const double sv = fma(r, z * ps, r);
-    double pc = 4.110317623312165e-19;       // cosine: 1/20! ... 1/4!
-    pc = fma(z, pc, KSC(-1.5619206968586225e-16));
-    pc = fma(z, pc, KSC(4.779477332387385e-14));
-    pc = fma(z, pc, KSC(-1.1470745597729725e-11));
-    pc = fma(z, pc, KSC(2.08767569878681e-09));
-    pc = fma(z, pc, KSC(-2.755731922398589e-07));
-    pc = fma(z, pc, KSC(2.48015873015873e-05));
-    pc = fma(z, pc, KSC(-0.001388888888888889));
-    pc = fma(z, pc, KSC(0.041666666666666664));
+    double pc = KC(28);                      // cosine: 1/20! ... 1/4!
+    pc = fma(z, pc, KC(29));
+    pc = fma(z, pc, KC(30));
+    pc = fma(z, pc, KC(31));
+    pc = fma(z, pc, KC(32));
+    pc = fma(z, pc, KC(33));
+    pc = fma(z, pc, KC(34));
+    pc = fma(z, pc, KC(35));
+    pc = fma(z, pc, KC(36));
     const double cv = fma(z * z, pc, fma(-0.5, z, 1.0));
     switch (q & 3) {
         case 0: *sn = sv; *cs = cv; break;
@@ -2050,6 +2072,9 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         const unsigned long long* g_sc = (const unsigned long long*)&J.sc;
         for (int i = tid; i < (int)(sizeof(SpeciesConst) / 8); i += blockDim.x)
             ((unsigned long long*)s_sc)[i] = g_sc[i];
+#ifdef KARL_DRAIN_UNIT
+        for (int i = tid; i < kNSeries; i += blockDim.x) s_series[i] = kSeriesTab[i];
+#endif
         __syncthreads();
         L0 = Lds<Real>{s_cnt, s_led, s_pidx, s_kind, s_tgt, s_eth, s_xs, s_ngas, s_zf, s_rf, s_sc, false};
     }
@@ -2287,7 +2312,30 @@ __global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long l
 
 }  // namespace
 
-#ifdef KARL_BATCHED_UNIT
+#if defined(KARL_DRAIN_UNIT)
+// The deferred-launch kernels, compiled in a unit of their own (see karl_kernels_drain.hip).
+hipError_t launch_transport_drain(const DevJob* jobs_dev, bool dense, const GenArgs& g, int precision,
+                                  int grid, int block, size_t lds, hipStream_t s) {
+    if (precision == KARL_FP32) {
+        if (dense)
+            hipLaunchKernelGGL((transport_kernel<float, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<float, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    } else {
+        if (dense)
+            hipLaunchKernelGGL((transport_kernel<double, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else
+            hipLaunchKernelGGL((transport_kernel<double, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t transport_occupancy_drain(int precision, int block, size_t lds, int* blocks_per_cu) {
+    if (precision == KARL_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 1>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 1>, block, lds);
+}
+#elif defined(KARL_BATCHED_UNIT)
 // The batched kernels, compiled in a unit of their own (see karl_kernels_batched.hip).
 hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
                                     int grid, int block, size_t lds, hipStream_t s) {
@@ -2325,20 +2373,7 @@ size_t lds_bytes(const DevJob& j, int precision) {
 hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, bool drain, bool dense,
                             bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s) {
-    if (drain && !batched) {
-        if (precision == KARL_FP32) {
-            if (dense)
-                hipLaunchKernelGGL((transport_kernel<float, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-            else
-                hipLaunchKernelGGL((transport_kernel<float, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        } else {
-            if (dense)
-                hipLaunchKernelGGL((transport_kernel<double, false, false, 2>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-            else
-                hipLaunchKernelGGL((transport_kernel<double, false, false, 1>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
-        }
-        return hipGetLastError();
-    }
+    if (drain && !batched) return launch_transport_drain(jobs_dev, dense, g, precision, grid, block, lds, s);
     if (batched) return launch_transport_batched(jobs_dev, boris, g, precision, grid, block, lds, s);
     if (precision == KARL_FP32) {
         if (coop) {
@@ -2406,11 +2441,7 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 
 hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, bool boris, int block,
                                size_t lds, int* blocks_per_cu) {
-    if (drain && !batched) {
-        if (precision == KARL_FP32)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, false, 1>, block, lds);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, false, false, 1>, block, lds);
-    }
+    if (drain && !batched) return transport_occupancy_drain(precision, block, lds, blocks_per_cu);
     if (batched) return transport_occupancy_batched(precision, boris, block, lds, blocks_per_cu);
     if (precision == KARL_FP32) {
         if (coop)
