@@ -291,6 +291,11 @@ karl_status karl_reset_tallies(void* job, void* hip_stream);
 karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches,
                            int64_t* generations, int64_t* max_queue);
 
+/* Of karl_job_stats: the deferred launches alone (the launch over the deferred queue of
+   species that make no secondaries, run after the generations of every chunk), *kernel_ms and
+   *n_launches since creation or the last reset. */
+karl_status karl_job_drain_stats(void* job, double* kernel_ms, int64_t* n_launches);
+
 /* Particles that the job's deferred launches put into the ring at the end of a slice
    (karl_job_desc.slice_steps), since creation or the last karl_reset_tallies; 0 without
    slices.  Both pointers must be valid. */

@@ -86,6 +86,21 @@ class _Tallies(C.Structure):
 
 
 _lib = None
+_lib_fast = None
+
+
+def load_fast() -> C.CDLL:
+    """The same source built for speed (-O3 -march=native, contraction allowed) into a
+    temporary directory for this host: used only to time the oracle as a CPU baseline, never
+    for parity (its results may differ in the last bits)."""
+    global _lib_fast
+    if _lib_fast is None:
+        import tempfile
+        out = os.path.join(tempfile.mkdtemp(prefix="karl_oracle_fast_"), "liboracle_karl_fast.so")
+        cmd = ["gcc", "-O3", "-march=native", "-std=c99", "-shared", "-fPIC", "-o", out, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        _lib_fast = _setup(C.CDLL(out))
+    return _lib_fast
 
 
 def lib():
@@ -93,43 +108,46 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        L.ko_run.argtypes = [C.POINTER(_Desc), C.c_int64, C.c_int64, C.POINTER(_Tallies)]
-        L.ko_run.restype = C.c_int
-        L.ko_fields.argtypes = [C.POINTER(_Desc), C.POINTER(_Tallies), C.c_double, C.c_double,
-                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.ko_fields.restype = C.c_int
-        L.ko_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
-        L.ko_philox.restype = None
-        L.ko_u53.argtypes = [C.c_uint32, C.c_uint32]
-        L.ko_u53.restype = C.c_double
-        L.ko_constants.argtypes = [C.POINTER(C.c_double)]
-        L.ko_constants.restype = None
-        L.ko_log.argtypes = [C.c_double]
-        L.ko_log.restype = C.c_double
-        L.ko_sincos.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.ko_sincos.restype = None
-        L.ko_mix64.argtypes = [C.c_uint64]
-        L.ko_mix64.restype = C.c_uint64
-        L.ko_beta_shape.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.ko_beta_shape.restype = C.c_double
-        L.ko_birth.argtypes = [C.POINTER(_Desc), C.c_int64, C.POINTER(C.c_double)]
-        L.ko_birth.restype = C.c_int
-        L.ko_debug_collide.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int64, C.c_uint64,
-                                       C.c_uint32, C.c_double, C.POINTER(C.c_double),
-                                       C.POINTER(C.c_double)]
-        L.ko_debug_collide.restype = C.c_int
-        L.ko_debug_angle.argtypes = [C.POINTER(_Desc), C.c_int, C.c_double, C.c_double]
-        L.ko_debug_angle.restype = C.c_double
-        L.ko_debug_boris.argtypes = [C.POINTER(_Desc), C.c_int, C.POINTER(C.c_double),
-                                     C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
-        L.ko_debug_boris.restype = C.c_int
-        L.ko_debug_helix.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
-                                     C.POINTER(C.c_double), C.c_double, C.c_double,
-                                     C.POINTER(C.c_double)]
-        L.ko_debug_helix.restype = None
-        _lib = L
+        _lib = _setup(C.CDLL(LIB_PATH))
     return _lib
+
+
+def _setup(L: C.CDLL) -> C.CDLL:
+    L.ko_run.argtypes = [C.POINTER(_Desc), C.c_int64, C.c_int64, C.POINTER(_Tallies)]
+    L.ko_run.restype = C.c_int
+    L.ko_fields.argtypes = [C.POINTER(_Desc), C.POINTER(_Tallies), C.c_double, C.c_double,
+                            C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.ko_fields.restype = C.c_int
+    L.ko_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
+    L.ko_philox.restype = None
+    L.ko_u53.argtypes = [C.c_uint32, C.c_uint32]
+    L.ko_u53.restype = C.c_double
+    L.ko_constants.argtypes = [C.POINTER(C.c_double)]
+    L.ko_constants.restype = None
+    L.ko_log.argtypes = [C.c_double]
+    L.ko_log.restype = C.c_double
+    L.ko_sincos.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.ko_sincos.restype = None
+    L.ko_mix64.argtypes = [C.c_uint64]
+    L.ko_mix64.restype = C.c_uint64
+    L.ko_beta_shape.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.ko_beta_shape.restype = C.c_double
+    L.ko_birth.argtypes = [C.POINTER(_Desc), C.c_int64, C.POINTER(C.c_double)]
+    L.ko_birth.restype = C.c_int
+    L.ko_debug_collide.argtypes = [C.POINTER(_Desc), C.c_int, C.c_int64, C.c_uint64,
+                                   C.c_uint32, C.c_double, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]
+    L.ko_debug_collide.restype = C.c_int
+    L.ko_debug_angle.argtypes = [C.POINTER(_Desc), C.c_int, C.c_double, C.c_double]
+    L.ko_debug_angle.restype = C.c_double
+    L.ko_debug_boris.argtypes = [C.POINTER(_Desc), C.c_int, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
+    L.ko_debug_boris.restype = C.c_int
+    L.ko_debug_helix.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_double, C.c_double,
+                                 C.POINTER(C.c_double)]
+    L.ko_debug_helix.restype = None
+    return L
 
 
 def _dptr(a: np.ndarray):
@@ -274,8 +292,10 @@ def empty_tallies(w, digests: bool = False, hist: bool = False) -> Dict[str, np.
 
 
 def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, digests: bool = False,
-        hist: bool = False, tallies: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
-    """Transport primaries [pid_begin, pid_end) of workload `w`; returns (or adds into) tallies."""
+        hist: bool = False, tallies: Optional[Dict[str, np.ndarray]] = None,
+        library: Optional[C.CDLL] = None) -> Dict[str, np.ndarray]:
+    """Transport primaries [pid_begin, pid_end) of workload `w`; returns (or adds into) tallies.
+    `library` selects another build of the same source (load_fast() for timing)."""
     if pid_end is None:
         pid_end = w.n_primaries
     t = tallies if tallies is not None else empty_tallies(w, digests, hist)
@@ -294,7 +314,7 @@ def run(w, pid_begin: int = 0, pid_end: Optional[int] = None, digests: bool = Fa
         T.hist = _dptr(t["hist"])
     if "density_time_e" in t:
         T.density_time_e = _dptr(t["density_time_e"])
-    rc = lib().ko_run(C.byref(D.d), pid_begin, pid_end, C.byref(T))
+    rc = (library or lib()).ko_run(C.byref(D.d), pid_begin, pid_end, C.byref(T))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (rc={rc})")
     return t

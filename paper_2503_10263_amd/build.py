@@ -68,16 +68,5 @@ def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
     return out
 
 
-def build_calibration() -> str:
-    """Copy kernel of known traffic used to scale the HBM counters (FETCH_SIZE, WRITE_SIZE)."""
-    out = os.path.join(PKG, "copy_calibration")
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-o", out, os.path.join(PKG, "csrc", "copy_calibration.hip")]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    return out
-
-
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -358,9 +358,12 @@ struct Launcher {
     unsigned long long* ring_flag = nullptr;
     int64_t ring_cap = 0;
     unsigned long long* host_ctl = nullptr; // pinned copy of ctl[1..4] and a scratch word
+    bool own_host = false;                  // host_ctl allocated by init (else the caller's)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int64_t launches = 0, generations = 0, max_queue = 0;
+    double drain_ms = 0.0;                  // of kernel_ms: the deferred (drain) launches
+    int64_t drain_launches = 0;
     int64_t slices = 0;                     // ring entries written by deferred launches
     // batched launches: per-job item ranges, fetch counters and the queue sort's scratch
     int32_t n_jobs = 1;
@@ -373,8 +376,10 @@ struct Launcher {
     unsigned long long* sort_cursor = nullptr;
     bool ready = false;
 
+    // host_words: caller-provided host memory for the counters read back after each launch
+    // (then no pinned memory and no timing events are created: nothing is allocated)
     karl_status init(char* queues, size_t entries, unsigned long long* control, int prec,
-                     bool is_batched, size_t lds_bytes) {
+                     bool is_batched, size_t lds_bytes, unsigned long long* host_words = nullptr) {
         precision = prec;
         batched = is_batched;
         capacity = (int64_t)entries;
@@ -404,17 +409,23 @@ struct Launcher {
             if (per_cu < 1) per_cu = 1;
             max_blocks_drain = per_cu * prop.multiProcessorCount;
         }
-        HIP_CHECK(hipHostMalloc((void**)&host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
-        HIP_CHECK(hipEventCreate(&ev0));
-        HIP_CHECK(hipEventCreate(&ev1));
-        HIP_CHECK(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
-        HIP_CHECK(hipStreamSynchronize(nullptr));
+        if (host_words) {
+            host_ctl = host_words;
+            own_host = false;
+        } else {
+            HIP_CHECK(hipHostMalloc((void**)&host_ctl, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+            own_host = true;
+            HIP_CHECK(hipEventCreate(&ev0));
+            HIP_CHECK(hipEventCreate(&ev1));
+            HIP_CHECK(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, nullptr));
+            HIP_CHECK(hipStreamSynchronize(nullptr));
+        }
         ready = true;
         return KARL_OK;
     }
 
     void release() {
-        if (host_ctl) (void)hipHostFree(host_ctl);
+        if (host_ctl && own_host) (void)hipHostFree(host_ctl);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         host_ctl = nullptr;
@@ -423,8 +434,8 @@ struct Launcher {
     }
 
     void reset_stats() {
-        kernel_ms = 0.0;
-        launches = generations = max_queue = slices = 0;
+        kernel_ms = drain_ms = 0.0;
+        launches = generations = max_queue = slices = drain_launches = 0;
     }
 
     // Run every generation of n primary items (chunk of the item space starting at item_base;
@@ -509,10 +520,10 @@ struct Launcher {
                     HIP_CHECK(karl::launch_fill_u64(ctl + 7, 1, 0ull, s));
                 }
             }
-            HIP_CHECK(hipEventRecord(ev0, s));
+            if (ev0) HIP_CHECK(hipEventRecord(ev0, s));
             HIP_CHECK(karl::launch_transport(jobs_dev, batched, use_coop, use_drain, dense, boris, g, precision,
                                              (int)blocks, kBlock, lds, s));
-            HIP_CHECK(hipEventRecord(ev1, s));
+            if (ev1) HIP_CHECK(hipEventRecord(ev1, s));
             HIP_CHECK(hipMemcpyAsync(host_ctl, qcount, 4 * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, s));
             if (use_drain && slice_mask)
@@ -520,9 +531,15 @@ struct Launcher {
                                          hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
             if (use_drain && slice_mask) slices += (int64_t)host_ctl[6];
-            float ms = 0.f;
-            HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-            kernel_ms += ms;
+            if (ev0) {
+                float ms = 0.f;
+                HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+                kernel_ms += ms;
+                if (use_drain) {
+                    drain_ms += ms;
+                    drain_launches += 1;
+                }
+            }
             launches += 1;
             if (mode == 1) generations += 1;
             const unsigned long long produced = host_ctl[0];
@@ -670,24 +687,26 @@ constexpr int64_t kTuneSegments = 100000;   // a tuning chunk must show at least
 
 // Transport primaries [b, e) in chunks.  With KARL_MAP_AUTO the first chunk runs with the lane
 // mapping and its segments per interaction choose the mapping of the following chunks.
-karl_status transport_range(Job* j, int64_t b, int64_t pid_end, hipStream_t s) {
+// The launcher, the tally snapshot and the chunk size are arguments: the job's own (queues in
+// its workspace) or those of the transport without allocation (queues in the library's array).
+karl_status transport_range(Job* j, Launcher& run, char* snap, int64_t& chunk, int64_t b,
+                            int64_t pid_end, hipStream_t s) {
     char* tallies = j->ws + j->lay.tallies;
-    char* snap = j->ws + j->lay.snapshot;
     while (b < pid_end) {
-        const int64_t n = std::min<int64_t>(j->chunk, pid_end - b);
+        const int64_t n = std::min<int64_t>(chunk, pid_end - b);
         const bool wave = j->chosen == KARL_MAP_WAVE;
-        j->run.coop = wave;
+        run.coop = wave;
         int64_t s0 = 0, i0 = 0;
         karl_status st = read_steps(j, s, &s0, &i0);
         if (st != KARL_OK) return st;
-        const double k0 = j->run.kernel_ms;
+        const double k0 = run.kernel_ms;
         HIP_CHECK(hipMemcpyAsync(snap, tallies, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
         karl::GenArgs g{};
         g.n_jobs = 1;
         g.pid_begin0 = b;
         bool overflow = false;
         int64_t max_gen = 0;
-        st = j->run.run(g, n, s, &overflow, &max_gen);
+        st = run.run(g, n, s, &overflow, &max_gen);
         if (st != KARL_OK) {
             j->failed = true;
             return st;
@@ -695,28 +714,28 @@ karl_status transport_range(Job* j, int64_t b, int64_t pid_end, hipStream_t s) {
         if (overflow) {
             // undo the partial chunk and retry with half as many primaries
             HIP_CHECK(hipMemcpyAsync(tallies, snap, j->lay.tally_bytes, hipMemcpyDeviceToDevice, s));
-            if ((st = j->run.clear_overflow(s)) != KARL_OK) {
+            if ((st = run.clear_overflow(s)) != KARL_OK) {
                 j->failed = true;
                 return st;
             }
             if (n == 1) {
                 j->failed = true;
                 return fail(KARL_EOVERFLOW, "primary %lld alone overflows a queue of %lld entries",
-                            (long long)b, (long long)j->run.capacity);
+                            (long long)b, (long long)run.capacity);
             }
-            j->chunk = std::max<int64_t>(1, n / 2);
+            chunk = std::max<int64_t>(1, n / 2);
             continue;
         }
         int64_t s1 = 0, i1 = 0;
         if ((st = read_steps(j, s, &s1, &i1)) != KARL_OK) return st;
-        if (s1 > s0) j->ms_seg[wave ? 1 : 0] = (j->run.kernel_ms - k0) / (double)(s1 - s0);
+        if (s1 > s0 && run.ev0) j->ms_seg[wave ? 1 : 0] = (run.kernel_ms - k0) / (double)(s1 - s0);
         if (j->chosen == KARL_MAP_AUTO && s1 - s0 >= kTuneSegments) {
             j->seg_per_int = (double)(s1 - s0) / (double)std::max<int64_t>(1, i1 - i0);
             j->chosen = j->seg_per_int >= kWaveRatio ? KARL_MAP_WAVE : KARL_MAP_LANE;
         }
         b += n;
         j->n_transported += n;
-        j->chunk = next_chunk(j->chunk, n, max_gen, j->run.capacity);
+        chunk = next_chunk(chunk, n, max_gen, run.capacity);
     }
     return KARL_OK;
 }
@@ -1028,7 +1047,7 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
     HIP_CHECK(hipSetDevice(j->device));
     karl_status st = ensure_launcher(j);
     if (st != KARL_OK) return st;
-    return transport_range(j, pid_begin, pid_end, s);
+    return transport_range(j, j->run, j->ws + j->lay.snapshot, j->chunk, pid_begin, pid_end, s);
 }
 
 karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {
@@ -1129,6 +1148,14 @@ karl_status karl_job_stats(void* job, double* kernel_ms, int64_t* n_launches, in
     if (n_launches) *n_launches = j->run.launches;
     if (generations) *generations = j->run.generations;
     if (max_queue) *max_queue = j->run.max_queue;
+    return KARL_OK;
+}
+
+karl_status karl_job_drain_stats(void* job, double* kernel_ms, int64_t* n_launches) {
+    Job* j = (Job*)job;
+    if (!j || !kernel_ms || !n_launches) return fail(KARL_EINVAL, "job and outputs must not be NULL");
+    *kernel_ms = j->run.drain_ms;
+    *n_launches = j->run.drain_launches;
     return KARL_OK;
 }
 

@@ -39,7 +39,7 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
 # names of the entry points declared in include/karl.h
 ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
                 "karl_read_fields", "karl_update_target_fields", "karl_reset_tallies",
-                "karl_job_stats", "karl_job_slices", "karl_job_mapping",
+                "karl_job_stats", "karl_job_drain_stats", "karl_job_slices", "karl_job_mapping",
                 "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
                 "karl_batch_stats", "karl_destroy_batch",
@@ -140,6 +140,7 @@ def lib():
         L.karl_job_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.karl_job_slices.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.karl_job_drain_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.karl_job_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]
@@ -363,6 +364,12 @@ class Job:
         check(lib().karl_job_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
         return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
                 "max_queue": q.value}
+
+    def drain_stats(self) -> Dict[str, float]:
+        """Kernel time and launches of the deferred (drain) launches alone."""
+        ms, n = C.c_double(), C.c_int64()
+        check(lib().karl_job_drain_stats(self.h, C.byref(ms), C.byref(n)))
+        return {"kernel_ms": ms.value, "launches": n.value}
 
     def slices(self) -> int:
         """Particles put into the ring at the end of a slice by the deferred launches."""

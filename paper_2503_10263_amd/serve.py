@@ -18,7 +18,8 @@ def collisions_of(counters: np.ndarray) -> int:
 
 
 def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], realtime: bool = True,
-           keep_tallies: bool = False, threaded: bool = True, on_complete=None) -> Dict[str, object]:
+           keep_tallies: bool = False, threaded: bool = True, on_complete=None,
+           deadline_s: float = float("inf")) -> Dict[str, object]:
     """Submit request i at its arrival time (seconds after the start; all at once when
     `realtime` is False) until every request has completed; read each job's counters (or all
     its tallies with keep_tallies) and release it.  With `threaded` the server's worker
@@ -27,7 +28,9 @@ def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], real
 
     Latency of a job = completion time - arrival time, where completion is the end of the
     round that transported its last primary (as seen by this loop).  Returns per-job
-    latency/collisions, their p50/p99, the throughput and the server's statistics."""
+    latency/collisions, their p50/p99, the throughput and the server's statistics.  A run
+    still going `deadline_s` seconds after the start is stopped: jobs not completed by then
+    count with their latency so far (a lower bound; "censored" gives their number)."""
     n = len(requests)
     order = sorted(range(n), key=lambda k: requests[k][0])
     arrival: Dict[int, float] = {}
@@ -44,6 +47,8 @@ def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], real
     try:
         while done < n:
             now = time.perf_counter() - t0
+            if now > deadline_s:
+                break
             while nxt < n and (not realtime or requests[order[nxt]][0] <= now):
                 k = order[nxt]
                 t = server.submit(requests[k][1])
@@ -78,6 +83,12 @@ def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], real
         if threaded:
             server.stop()
     wall = time.perf_counter() - t0
+    censored = 0
+    for t, k in index_of.items():
+        if latency[k] == 0.0:
+            latency[k] = wall - arrival[t]
+            censored += 1
+    censored += n - len(index_of)
     first = min(r[0] for r in requests) if realtime else 0.0
     st = server.stats()
     return {
@@ -91,5 +102,51 @@ def replay(server: "karl.Server", requests: Sequence[Tuple[float, object]], real
         "collisions_per_s": float(collisions.sum() / max(wall - first, 1e-9)),
         "busy_fraction": st["busy_ms"] / 1e3 / max(wall, 1e-9),
         "max_backlog": max(b for _, b in backlog) if backlog else 0,
+        "censored": censored,
         "stats": st,
     }
+
+
+def window(server: "karl.Server", requests: Sequence[Tuple[float, object]], window_s: float) -> Dict[str, object]:
+    """Submit the requests arriving within `window_s` seconds at their arrival times while the
+    server's worker threads run, collect what completes, and stop at the end of the window
+    (the workers finish their current rounds; unfinished jobs stay in the server, which the
+    caller destroys).  Returns what arrived and completed, the primaries still to transport,
+    and the collisions per second the device transported over the window (completed and
+    unfinished jobs alike)."""
+    order = sorted(range(len(requests)), key=lambda k: requests[k][0])
+    tickets = {}
+    done = set()
+    nxt = 0
+    server.start()
+    t0 = time.perf_counter()
+    try:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= window_s:
+                break
+            while nxt < len(order) and requests[order[nxt]][0] <= now:
+                k = order[nxt]
+                tickets[server.submit(requests[k][1])] = k
+                nxt += 1
+            until_next = requests[order[nxt]][0] - now if nxt < len(order) else window_s - now
+            server.wait(1e3 * min(max(until_next, 0.0), 0.05))
+            for t in server.poll():
+                done.add(t)
+    finally:
+        server.stop()
+    elapsed = time.perf_counter() - t0
+    for t in server.poll():
+        done.add(t)
+    collisions = 0
+    for t in tickets:
+        try:
+            c = server.read_tallies(t, only=("counters",))["counters"]
+        except karl.KarlError:       # never admitted: nothing transported
+            continue
+        collisions += collisions_of(c)
+    st = server.stats()
+    arrived_prims = sum(requests[k][1].n_primaries for k in tickets.values())
+    return {"arrived": len(tickets), "completed": len(done), "elapsed_s": elapsed,
+            "primaries": int(st["primaries"]), "primaries_backlog": int(arrived_prims - st["primaries"]),
+            "collisions": int(collisions), "collisions_per_s": collisions / elapsed}

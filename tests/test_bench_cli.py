@@ -1,10 +1,14 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a message before any
-device work, and the defaults are the launch configuration of the measured runs."""
+device work; the driver's invocation (--gpus 1 --steps 20 --warmup 5) plans a run that fits the
+full case's 1e6 primaries and the time limit, also checked before any device work."""
 import os
 import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+DRIVER_ARGS = ["--gpus", "1", "--steps", "20", "--warmup", "5"]
 
 
 def test_more_than_one_gpu_is_refused():
@@ -14,11 +18,31 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_defaults_are_the_measured_launch_configuration():
+def test_driver_invocation_fits_the_job_and_the_time_limit():
+    import bench
     from paper_2503_10263_amd import workloads as W
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+    pl = bench.plan(bench.parse(DRIVER_ARGS))
+    assert (5 + 20) * pl["batch"] <= bench.N_FULL
+    assert pl["batch"] == 40000                      # 1e6 // 25
+    assert pl["slice_steps"] == W.FULL_SLICE_STEPS and pl["batched_queue"] == W.BATCHED_QUEUE
+    assert pl["estimated_total_s"] <= bench.TIME_LIMIT_S - bench.MARGIN_S, pl["estimated_s"]
+
+
+def test_driver_invocation_plan_without_device_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *DRIVER_ARGS, "--plan"],
                        capture_output=True, text=True, timeout=120)
-    assert r.returncode == 0
-    assert W.FULL_STEP_PRIMARIES == 131072 and W.FULL_SLICE_STEPS == 1 << 15
-    assert W.BATCHED_QUEUE == 1 << 28
-    assert (W.FULL_SLICE_STEPS & (W.FULL_SLICE_STEPS - 1)) == 0   # slices are a power of two
+    assert r.returncode == 0, r.stderr
+    assert '"batch": 40000' in r.stderr and r.stdout == ""
+
+
+def test_oversized_runs_are_refused_before_device_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "20", "--warmup", "5",
+                        "--batch", "131072", "--plan"], capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "exceed" in r.stderr
+
+
+def test_defaults_are_small_and_within_the_job():
+    import bench
+    pl = bench.plan(bench.parse([]))
+    assert (pl["warmup"] + pl["steps"]) * pl["batch"] <= bench.N_FULL
+    assert (pl["slice_steps"] & (pl["slice_steps"] - 1)) == 0   # slices are a power of two
