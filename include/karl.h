@@ -259,6 +259,24 @@ karl_status karl_create_job(const karl_job_desc* desc, void** out);
    overlapping ranges count twice. */
 karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* hip_stream);
 
+/* Transport without allocation, for callers that cannot allocate memory at transport time:
+   code under stream or graph capture, tight serving loops, harnesses that forbid hipMalloc.
+   Same arguments, results and errors as karl_transport (the same kernels; digests and integer
+   tallies identical, FP64 tallies up to the order of additions), but the call allocates
+   nothing -- no device or pinned memory, no events: the generation and deferred queues, the
+   control words and the tally snapshot used to undo a chunk whose queue overflowed live in a
+   static device array of KARL_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every
+   device it runs on until the process ends.  The job's tallies (its workspace) must leave
+   room in that array for queues of 4096 entries (else KARL_EINVAL); the queue capacity is
+   whatever the array leaves, and chunks halve on overflow as in karl_transport.  The deferred
+   launch runs whole histories (no slices, whatever the job's slice_steps), and the launches
+   are not timed (karl_job_stats does not count them).  Every call on a device shares that
+   device's array and finds the previous call's contents in it (the control words are cleared
+   at each call): calls that overlap on one device would race, so the library serializes them
+   with a lock per device.  Synchronous like karl_transport. */
+#define KARL_NOALLOC_SCRATCH_BYTES ((uint64_t)64 << 20)
+karl_status karl_transport_noalloc(void* job, int64_t pid_begin, int64_t pid_end, void* hip_stream);
+
 /* Copy the tallies into caller-owned host buffers (synchronizes `hip_stream`). Returns the
    job's sticky device status (KARL_EOVERFLOW, KARL_ENUMERIC) if one was raised. */
 karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream);

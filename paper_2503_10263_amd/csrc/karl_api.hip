@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "karl.h"
@@ -740,6 +741,33 @@ karl_status transport_range(Job* j, Launcher& run, char* snap, int64_t& chunk, i
     return KARL_OK;
 }
 
+// ---- transport without allocation (karl_transport_noalloc)
+// Callers that cannot allocate device memory get their queues, control words and tally
+// snapshot from this array, one copy per device, held until the process ends.  In host code
+// its name is only a stand-in: the device address comes from hipGetSymbolAddress, once per
+// device, and only that address is passed to kernels and copies.
+constexpr int kMaxDevices = 64;
+constexpr int64_t kNoallocMinEntries = 4096;
+static __device__ __align__(256) unsigned char scratch[KARL_NOALLOC_SCRATCH_BYTES];
+std::mutex g_noalloc_mu[kMaxDevices];
+char* g_noalloc_ptr[kMaxDevices] = {};
+Launcher g_noalloc_run[kMaxDevices];
+unsigned long long g_noalloc_host[kMaxDevices][8];
+
+// the device address of `scratch` on `dev` (the current device), looked up on first use
+karl_status noalloc_scratch(int dev, char** out) {
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(KARL_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_noalloc_ptr[dev] = (char*)p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return KARL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1048,6 +1076,47 @@ karl_status karl_transport(void* job, int64_t pid_begin, int64_t pid_end, void* 
     karl_status st = ensure_launcher(j);
     if (st != KARL_OK) return st;
     return transport_range(j, j->run, j->ws + j->lay.snapshot, j->chunk, pid_begin, pid_end, s);
+}
+
+karl_status karl_transport_noalloc(void* job, int64_t pid_begin, int64_t pid_end, void* hip_stream) {
+    Job* j = (Job*)job;
+    if (!j) return fail(KARL_ESTATE, "job is NULL");
+    if (j->failed) return fail(KARL_ESTATE, "job failed earlier; destroy and recreate it");
+    if (pid_begin < 0 || pid_end < pid_begin || pid_end > j->n_primaries)
+        return fail(KARL_EINVAL, "pid range [%lld, %lld) outside 0..%lld", (long long)pid_begin,
+                    (long long)pid_end, (long long)j->n_primaries);
+    if (j->device < 0 || j->device >= kMaxDevices)
+        return fail(KARL_EINVAL, "device %d beyond the %d devices of the no-allocation path",
+                    j->device, kMaxDevices);
+    // the array holds the control words, a snapshot of the tallies (undo of a chunk whose queue
+    // overflowed) and four queues of at least kNoallocMinEntries entries
+    const size_t fixed = align_up(kControlBytes) + align_up(j->lay.tally_bytes);
+    if (fixed + 4 * (size_t)kNoallocMinEntries * kQueueEntryBytes > KARL_NOALLOC_SCRATCH_BYTES)
+        return fail(KARL_EINVAL, "the job's tallies (%zu bytes) leave no room for queues of %lld entries "
+                    "in the %zu-byte array of karl_transport_noalloc; use karl_transport",
+                    j->lay.tally_bytes, (long long)kNoallocMinEntries, (size_t)KARL_NOALLOC_SCRATCH_BYTES);
+    if (pid_end == pid_begin) return KARL_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_CHECK(hipSetDevice(j->device));
+    std::lock_guard<std::mutex> lk(g_noalloc_mu[j->device]);
+    char* base = nullptr;
+    karl_status st = noalloc_scratch(j->device, &base);
+    if (st != KARL_OK) return st;
+    unsigned long long* ctl = (unsigned long long*)base;
+    char* snap = base + align_up(kControlBytes);
+    char* queues = snap + align_up(j->lay.tally_bytes);
+    const size_t entries = (KARL_NOALLOC_SCRATCH_BYTES - fixed) / (4 * kQueueEntryBytes);
+    Launcher& run = g_noalloc_run[j->device];
+    run = Launcher{};
+    if ((st = run.init(queues, entries, ctl, j->precision, false, j->lds, g_noalloc_host[j->device])) != KARL_OK)
+        return st;
+    run.jobs_dev = j->run.jobs_dev;
+    run.dense = j->run.dense;
+    run.boris = j->run.boris;
+    // the array keeps the previous call's contents: the control words start at zero
+    HIP_CHECK(karl::launch_fill_u64(ctl, kControlBytes / 8, 0ull, s));
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(j->chunk, (int64_t)entries / 4));
+    return transport_range(j, run, snap, chunk, pid_begin, pid_end, s);
 }
 
 karl_status karl_read_tallies(void* job, karl_tallies* out, void* hip_stream) {

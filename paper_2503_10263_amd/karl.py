@@ -37,7 +37,8 @@ STATUS_NAMES = {EINVAL: "KARL_EINVAL", ENOMEM: "KARL_ENOMEM", EDEVICE: "KARL_EDE
                 EOVERFLOW: "KARL_EOVERFLOW", ESTATE: "KARL_ESTATE", ENUMERIC: "KARL_ENUMERIC"}
 
 # names of the entry points declared in include/karl.h
-ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport", "karl_read_tallies",
+ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport",
+                "karl_transport_noalloc", "karl_read_tallies",
                 "karl_read_fields", "karl_update_target_fields", "karl_reset_tallies",
                 "karl_job_stats", "karl_job_drain_stats", "karl_job_slices", "karl_job_mapping",
                 "karl_destroy_job",
@@ -132,6 +133,7 @@ def lib():
         L.karl_workspace_bytes.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
         L.karl_create_job.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_void_p)]
         L.karl_transport.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+        L.karl_transport_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         L.karl_read_tallies.argtypes = [C.c_void_p, C.POINTER(Tallies), C.c_void_p]
         L.karl_read_fields.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
@@ -344,6 +346,13 @@ class Job:
         if pid_end is None:
             pid_end = self.w.n_primaries
         check(lib().karl_transport(self.h, int(pid_begin), int(pid_end), self._stream(stream)))
+
+    def transport_noalloc(self, pid_begin: int = 0, pid_end: Optional[int] = None, stream=None):
+        """karl_transport_noalloc: the same transport with its queues in the library's static
+        device array (no allocation during the call)."""
+        if pid_end is None:
+            pid_end = self.w.n_primaries
+        check(lib().karl_transport_noalloc(self.h, int(pid_begin), int(pid_end), self._stream(stream)))
 
     def read_tallies(self, stream=None, only=None) -> Dict[str, np.ndarray]:
         return _read_tallies(self.h, self.w, self.digests, self.history, stream, only)

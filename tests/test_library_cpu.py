@@ -117,6 +117,7 @@ def test_bad_plane_and_nonfinite_density(karl):
 def test_null_job_is_an_error_not_a_crash(karl):
     lib = karl.lib()
     assert lib.karl_transport(None, 0, 1, None) == karl.ESTATE
+    assert lib.karl_transport_noalloc(None, 0, 1, None) == karl.ESTATE
     assert lib.karl_destroy_job(None) == karl.EINVAL
     n = C.c_int64(-1)
     assert lib.karl_job_slices(None, C.byref(n)) == karl.EINVAL and n.value == -1
