@@ -355,6 +355,13 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
 karl_status karl_batch_stats(void* batch, double* kernel_ms, int64_t* n_launches,
                              int64_t* generations, int64_t* max_queue);
 
+/* Flight segments advanced by wave-cooperative flights in the batch's launches since its
+   creation: a batched launch gives the flights of jobs whose mapping is (or was tuned to)
+   KARL_MAP_WAVE to the whole wave, the others one lane per particle.  A job on KARL_MAP_AUTO
+   chooses after the chunk in which its flight segments since creation reach 1e5: the wave
+   mapping if it made at least 32 segments per interaction.  Results do not depend on it. */
+karl_status karl_batch_wave_segments(void* batch, int64_t* wave_segments);
+
 /* Release host resources of the batch (the caller still owns its workspace). */
 karl_status karl_destroy_batch(void* batch);
 

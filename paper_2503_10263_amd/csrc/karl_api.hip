@@ -402,10 +402,10 @@ struct Launcher {
         HIP_CHECK(karl::transport_occupancy(prec, is_batched, false, false, true, kBlock, lds, &per_cu));
         if (per_cu < 1) per_cu = 1;
         max_blocks_boris = per_cu * prop.multiProcessorCount;
+        HIP_CHECK(karl::transport_occupancy(prec, is_batched, true, false, false, kBlock, lds, &per_cu));
+        if (per_cu < 1) per_cu = 1;
+        max_blocks_coop = per_cu * prop.multiProcessorCount;
         if (!is_batched) {
-            HIP_CHECK(karl::transport_occupancy(prec, false, true, false, false, kBlock, lds, &per_cu));
-            if (per_cu < 1) per_cu = 1;
-            max_blocks_coop = per_cu * prop.multiProcessorCount;
             HIP_CHECK(karl::transport_occupancy(prec, false, false, true, false, kBlock, lds, &per_cu));
             if (per_cu < 1) per_cu = 1;
             max_blocks_drain = per_cu * prop.multiProcessorCount;
@@ -495,14 +495,14 @@ struct Launcher {
             g.qdef_count = dcount + di;
             g.capacity = capacity;
             g.status = (unsigned int*)(ctl + 2);
-            g.wave_segments = batched ? nullptr : ctl + 6;
+            g.wave_segments = ctl + 6;
             HIP_CHECK(karl::launch_fill_u64(fetch, 2, 0ull, s));
             if (batched) {
                 HIP_CHECK(karl::launch_fill_u64(job_fetch, (size_t)n_jobs, 0ull, s));
                 HIP_CHECK(karl::launch_fill_u64(job_waves, (size_t)n_jobs, 0ull, s));
             }
             const bool use_drain = drain && !batched;
-            const bool use_coop = coop && !batched && !use_drain;
+            const bool use_coop = coop && !use_drain && !boris;
             const int64_t cap_blocks = use_drain ? max_blocks_drain : use_coop ? max_blocks_coop
                                        : boris ? max_blocks_boris : max_blocks;
             int64_t blocks = (items + kBlock - 1) / kBlock;
@@ -1341,6 +1341,7 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
         if (b < 0 || e < b || e > j->n_primaries)
             return fail(KARL_EINVAL, "job %d: pid range [%lld, %lld) invalid", i, (long long)b, (long long)e);
         B->host_jobs[i] = j->dj;
+        B->host_jobs[i].wave = j->chosen == KARL_MAP_WAVE ? 1 : 0;
         offs[i + 1] = offs[i] + (e - b);
     }
     const int64_t total = offs[n_jobs];
@@ -1351,6 +1352,13 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
     // the kernel built with the Boris mover only when a job of the batch needs it
     R.boris = false;
     for (int i = 0; i < n_jobs; ++i) R.boris = R.boris || ((Job*)jobs[i])->dj.boris != 0;
+    // the kernel variant with wave-cooperative flights only while a job of the batch uses them
+    auto any_wave = [&]() {
+        for (int i = 0; i < n_jobs; ++i)
+            if (B->host_jobs[i].wave) return true;
+        return false;
+    };
+    R.coop = any_wave();
     HIP_CHECK(hipMemcpyAsync(R.jobs_dev, B->host_jobs, sizeof(karl::DevJob) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
     int64_t c0 = 0;
     while (c0 < total) {
@@ -1397,6 +1405,26 @@ karl_status karl_transport_batch(void* batch, void* const* jobs, const int64_t* 
             const int64_t lo = std::max(c0, offs[i]), hi = std::min(c0 + n, offs[i + 1]);
             if (hi > lo) ((Job*)jobs[i])->n_transported += hi - lo;
         }
+        // mapping choice of the jobs still on KARL_MAP_AUTO: once a job's flight segments since
+        // creation reach kTuneSegments, its segments per interaction choose the wave mapping for
+        // its particles in the following chunks (the crossover measured for single jobs)
+        bool changed = false;
+        for (int i = j_lo; i < j_hi && i < n_jobs; ++i) {
+            Job* j = (Job*)jobs[i];
+            if (j->chosen != KARL_MAP_AUTO) continue;
+            int64_t segs = 0, ints = 0;
+            if ((st = read_steps(j, s, &segs, &ints)) != KARL_OK) return st;
+            if (segs < kTuneSegments) continue;
+            j->seg_per_int = (double)segs / (double)std::max<int64_t>(1, ints);
+            j->chosen = j->seg_per_int >= kWaveRatio ? KARL_MAP_WAVE : KARL_MAP_LANE;
+            if (j->chosen == KARL_MAP_WAVE) {
+                B->host_jobs[i].wave = 1;
+                HIP_CHECK(hipMemcpyAsync(&R.jobs_dev[i].wave, &B->host_jobs[i].wave, sizeof(int32_t),
+                                         hipMemcpyHostToDevice, s));
+                changed = true;
+            }
+        }
+        if (changed) R.coop = any_wave();
         c0 += n;
         B->chunk = next_chunk(B->chunk, n, max_gen, R.capacity);
     }
@@ -1412,6 +1440,16 @@ karl_status karl_batch_stats(void* batch, double* kernel_ms, int64_t* n_launches
     if (n_launches) *n_launches = R[0]->launches + R[1]->launches;
     if (generations) *generations = R[0]->generations + R[1]->generations;
     if (max_queue) *max_queue = std::max(R[0]->max_queue, R[1]->max_queue);
+    return KARL_OK;
+}
+
+karl_status karl_batch_wave_segments(void* batch, int64_t* wave_segments) {
+    Batch* B = (Batch*)batch;
+    if (!B || !wave_segments) return fail(KARL_EINVAL, "batch and wave_segments must not be NULL");
+    unsigned long long v = 0ull;
+    HIP_CHECK(hipSetDevice(B->device));
+    HIP_CHECK(hipMemcpy(&v, B->run[0].ctl + 6, sizeof(v), hipMemcpyDeviceToHost));
+    *wave_segments = (int64_t)v;
     return KARL_OK;
 }
 

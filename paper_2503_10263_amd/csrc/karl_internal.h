@@ -94,7 +94,8 @@ struct DevJob {
     const double* edges;   // [n_species][n_bins+1]
     const int32_t* plane_of;   // [n_z+1] plane index or -1
     const double* dens_edges;  // [n_species][n_dens_bins+1] or NULL
-    int32_t n_dens_bins, reserved1;
+    int32_t n_dens_bins;
+    int32_t wave;          // batched launches: flights of this job's particles by the whole wave
     // tallies
     unsigned long long* counters;
     double* ledger;
@@ -171,9 +172,9 @@ hipError_t launch_transport_drain(const DevJob* jobs_dev, bool dense, const GenA
                                   int grid, int block, size_t lds, hipStream_t s);
 hipError_t transport_occupancy_drain(int precision, int block, size_t lds, int* blocks_per_cu);
 // the batched kernels (their own compilation unit): launch and blocks per CU
-hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
+hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, bool coop, const GenArgs& g, int precision,
                                     int grid, int block, size_t lds, hipStream_t s);
-hipError_t transport_occupancy_batched(int precision, bool boris, int block, size_t lds, int* blocks_per_cu);
+hipError_t transport_occupancy_batched(int precision, bool boris, bool coop, int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_fields(const DevJob& j, double t_sim, double* density, double* jz, double* jr,
                          hipStream_t s);
 // Regroup n queue entries by job: count per job, exclusive scan into first/count, scatter.

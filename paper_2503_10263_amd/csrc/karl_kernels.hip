@@ -2023,11 +2023,34 @@ __device__ __forceinline__ void ring_put(const GenArgs& G, Part<Real>& p, bool w
 #define KARL_WAVES_PER_SIMD 1
 #endif
 
+// The wave's counter slot of job ju: found among the slot tags, or taken over from the least
+// recent job (whose counts are flushed to its tallies first).  Called by all active lanes of a
+// wave with the same ju.
+__device__ __forceinline__ unsigned long long* job_slot(const DevJob* jobs, unsigned long long* wslots,
+                                                       volatile int32_t* wtags, int ju) {
+    int slot = -1;
+    for (int k = 0; k < kSlots; ++k)
+        if (wtags[k] == ju) slot = k;
+    if (slot < 0) {
+        slot = wtags[kSlots];
+        const int old = wtags[slot];
+        const unsigned long long mine = __ballot(true);
+        if ((int)lane_id() == __ffsll((long long)mine) - 1) {
+            if (old >= 0) slot_flush(jobs, old, wslots + (size_t)slot * kSlotWords);
+            wtags[slot] = ju;
+            wtags[kSlots] = (slot + 1) % kSlots;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    return wslots + (size_t)slot * kSlotWords;
+}
+
 // kBatched = false: one job (jobs[0]); its tables are staged in LDS and its event counters
 // reduced in LDS.  kBatched = true: every lane carries a job index; the lanes of a wave are
 // served job by job (one pass per distinct job, normally one) so that the job's parameters are
-// read with scalar loads.  kCoop (one job, guiding-centre mode): before each step, the flights
-// of particles that just crossed a face are advanced by the whole wave (coop_flight).  kDrain
+// read with scalar loads.  kCoop (guiding-centre mode): before each step, the flights of
+// particles that just crossed a face are advanced by the whole wave (coop_flight) -- in batched
+// launches those of the jobs that chose the wave mapping (DevJob::wave).  kDrain
 // (one job): the deferred-queue launch, without the birth and ionization code, which leaves
 // the kernel half the registers and twice the waves per SIMD (1: without, 2: with the
 // energy-resolved density tally).
@@ -2152,6 +2175,20 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
             }
             if (p.alive || p.start) advance<Real, kDrain, kBoris>(jobs[0], L0, G, p, lc);
         } else {
+            if constexpr (kCoop) {
+                // wave-cooperative flights (coop_flight) of the particles whose job chose the
+                // wave mapping: each flight is one job's, whose tables and counter slot the
+                // whole wave uses for it
+                unsigned long long cm = __ballot(p.alive && !p.start && p.fly && jobs[p.job].wave != 0);
+                while (cm) {
+                    const int j = __ffsll((long long)cm) - 1;
+                    cm &= cm - 1ull;
+                    const int ju = bc_i(p.job, j);
+                    const DevJob& J = jobs[ju];
+                    unsigned long long* sc = job_slot(jobs, wslots, wtags, ju);
+                    coop_flight(J, global_view<Real>(J, sc, (double*)(sc + kNCnt)), G, p, lc, j);
+                }
+            }
             bool todo = p.alive || p.start;
             const int key = kS * p.job + (p.start ? 0 : p.sp);
             for (;;) {
@@ -2162,22 +2199,7 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
                 if (todo && key == k0) {
                     const int ju = __builtin_amdgcn_readfirstlane(p.job);
                     const DevJob& J = jobs[ju];
-                    // find this job's slot, or take one over (flushing the job that held it)
-                    int slot = -1;
-                    for (int k = 0; k < kSlots; ++k)
-                        if (wtags[k] == ju) slot = k;
-                    if (slot < 0) {
-                        slot = wtags[kSlots];
-                        const int old = wtags[slot];
-                        const unsigned long long mine = __ballot(true);
-                        if ((int)lane_id() == __ffsll((long long)mine) - 1) {
-                            if (old >= 0) slot_flush(jobs, old, wslots + (size_t)slot * kSlotWords);
-                            wtags[slot] = ju;
-                            wtags[kSlots] = (slot + 1) % kSlots;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                    unsigned long long* sc = wslots + (size_t)slot * kSlotWords;
+                    unsigned long long* sc = job_slot(jobs, wslots, wtags, ju);
                     advance<Real, 0, kBoris>(J, global_view<Real>(J, sc, (double*)(sc + kNCnt)), G, p, lc);
                     todo = false;
                 }
@@ -2337,28 +2359,36 @@ hipError_t transport_occupancy_drain(int precision, int block, size_t lds, int* 
 }
 #elif defined(KARL_BATCHED_UNIT)
 // The batched kernels, compiled in a unit of their own (see karl_kernels_batched.hip).
-hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, const GenArgs& g, int precision,
+// coop: the variant with wave-cooperative flights for the particles of jobs that chose them
+// (DevJob::wave; guiding-centre jobs without the Boris mover)
+hipError_t launch_transport_batched(const DevJob* jobs_dev, bool boris, bool coop, const GenArgs& g, int precision,
                                     int grid, int block, size_t lds, hipStream_t s) {
     if (precision == KARL_FP32) {
         if (boris)
             hipLaunchKernelGGL((transport_kernel<float, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else if (coop)
+            hipLaunchKernelGGL((transport_kernel<float, true, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         else
             hipLaunchKernelGGL((transport_kernel<float, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
     } else {
         if (boris)
             hipLaunchKernelGGL((transport_kernel<double, true, false, 0, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
+        else if (coop)
+            hipLaunchKernelGGL((transport_kernel<double, true, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
         else
             hipLaunchKernelGGL((transport_kernel<double, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
     }
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy_batched(int precision, bool boris, int block, size_t lds, int* blocks_per_cu) {
+hipError_t transport_occupancy_batched(int precision, bool boris, bool coop, int block, size_t lds, int* blocks_per_cu) {
     if (precision == KARL_FP32)
         return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true, false, 0, true>, block, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
+               : coop ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true, true>, block, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, true>, block, lds);
     return boris ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true, false, 0, true>, block, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
+           : coop ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true, true>, block, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<double, true>, block, lds);
 }
 #else
 size_t lds_bytes(const DevJob& j, int precision) {
@@ -2374,7 +2404,7 @@ hipError_t launch_transport(const DevJob* jobs_dev, bool batched, bool coop, boo
                             bool boris, const GenArgs& g, int precision, int grid, int block, size_t lds,
                             hipStream_t s) {
     if (drain && !batched) return launch_transport_drain(jobs_dev, dense, g, precision, grid, block, lds, s);
-    if (batched) return launch_transport_batched(jobs_dev, boris, g, precision, grid, block, lds, s);
+    if (batched) return launch_transport_batched(jobs_dev, boris, coop, g, precision, grid, block, lds, s);
     if (precision == KARL_FP32) {
         if (coop) {
             hipLaunchKernelGGL((transport_kernel<float, false, true>), dim3(grid), dim3(block), lds, s, jobs_dev, g);
@@ -2442,7 +2472,7 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 hipError_t transport_occupancy(int precision, bool batched, bool coop, bool drain, bool boris, int block,
                                size_t lds, int* blocks_per_cu) {
     if (drain && !batched) return transport_occupancy_drain(precision, block, lds, blocks_per_cu);
-    if (batched) return transport_occupancy_batched(precision, boris, block, lds, blocks_per_cu);
+    if (batched) return transport_occupancy_batched(precision, boris, coop, block, lds, blocks_per_cu);
     if (precision == KARL_FP32) {
         if (coop)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<float, false, true>, block, lds);

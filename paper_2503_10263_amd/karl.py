@@ -43,7 +43,7 @@ ENTRY_POINTS = ["karl_workspace_bytes", "karl_create_job", "karl_transport",
                 "karl_job_stats", "karl_job_drain_stats", "karl_job_slices", "karl_job_mapping",
                 "karl_destroy_job",
                 "karl_batch_workspace_bytes", "karl_create_batch", "karl_transport_batch",
-                "karl_batch_stats", "karl_destroy_batch",
+                "karl_batch_stats", "karl_batch_wave_segments", "karl_destroy_batch",
                 "karl_server_workspace_bytes", "karl_create_server", "karl_server_submit",
                 "karl_server_step", "karl_server_start", "karl_server_wait", "karl_server_stop",
                 "karl_server_poll", "karl_server_job", "karl_server_release",
@@ -154,6 +154,7 @@ def lib():
                                            C.c_int32, C.c_void_p]
         L.karl_batch_stats.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.karl_batch_wave_segments.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.karl_destroy_batch.argtypes = [C.c_void_p]
         L.karl_server_workspace_bytes.argtypes = [C.POINTER(ServerDesc), C.POINTER(C.c_uint64)]
         L.karl_create_server.argtypes = [C.POINTER(ServerDesc), C.POINTER(C.c_void_p)]
@@ -462,6 +463,12 @@ class Batch:
         check(lib().karl_batch_stats(self.h, C.byref(ms), C.byref(n), C.byref(g), C.byref(q)))
         return {"kernel_ms": ms.value, "launches": n.value, "generations": g.value,
                 "max_queue": q.value}
+
+    def wave_segments(self) -> int:
+        """Flight segments advanced by wave-cooperative flights in this batch's launches."""
+        n = C.c_int64()
+        check(lib().karl_batch_wave_segments(self.h, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -88,3 +88,68 @@ def test_straight_line_jobs_use_the_lane_mapping():
         assert job.mapping()["mapping"] == "lane"
     finally:
         job.close()
+
+
+def _mixed_batch(n_long=1200):
+    """Jobs of one batch: long flights (low column on fine grids: the wave mapping), short
+    flights, a job without a field (always lane-mapped)."""
+    ws = [W.cfg_tiny(n_primaries=n_long, column_cm2=1.0e16, bz=2.5, n_r=4, n_z=512, seed=2),
+          W.cfg_tiny(n_primaries=900, column_cm2=1.0e17, bz=2.5, n_r=4, n_z=64, seed=3),
+          W.cfg_tiny(n_primaries=700, column_cm2=1.0e16, bz=1.5, n_r=8, n_z=512, seed=4),
+          W.cfg_tiny(n_primaries=500, seed=5)]
+    ws[0].planes, ws[1].planes, ws[2].planes = [0, 100, 512], [0, 32, 64], [0, 256, 512]
+    return ws
+
+
+@pytest.mark.parametrize("mode", ["forced", "tuned"])
+def test_batched_wave_flights_equal_oracle(mode):
+    """Batched FP64 launches with wave-cooperative flights for the jobs on the wave mapping
+    (forced at creation, or tuned from KARL_MAP_AUTO by the first of two transport calls):
+    every job's digests and tallies equal the oracle's."""
+    from paper_2503_10263_amd import karl
+    ws = _mixed_batch()
+    maps = ["wave", "lane", "wave", "lane"] if mode == "forced" else ["auto"] * 4
+    jobs = [karl.Job(w, digests=True, queue_capacity=1 << 12, mapping=m) for w, m in zip(ws, maps)]
+    batch = karl.Batch(max_jobs=8, queue_capacity=1 << 20)
+    try:
+        if mode == "forced":
+            batch.transport(jobs, [(0, w.n_primaries) for w in ws])
+        else:
+            # the first call tunes each job's mapping, the second uses it
+            batch.transport(jobs, [(0, w.n_primaries // 2) for w in ws])
+            assert batch.wave_segments() == 0
+            batch.transport(jobs, [(w.n_primaries // 2, w.n_primaries) for w in ws])
+        chosen = [j.mapping()["mapping"] for j in jobs]
+        got = [j.read_tallies() for j in jobs]
+        wave_segs = batch.wave_segments()
+    finally:
+        for j in jobs:
+            j.close()
+        batch.close()
+    assert chosen[0] == "wave" and chosen[2] == "wave" and chosen[3] == "lane", chosen
+    assert wave_segs > 0
+    for w, g in zip(ws, got):
+        o = run_oracle(w, [(0, w.n_primaries)], digests=True)
+        np.testing.assert_array_equal(g["digests"], o["digests"])
+        compare_tallies(g, o, max(abs(o["ledger"][0]), 1.0))
+
+
+def test_batched_wave_flights_fp32_equal_lane():
+    from paper_2503_10263_amd import karl
+    ws = _mixed_batch(3000)
+    res = {}
+    for m in ("wave", "lane"):
+        jobs = [karl.Job(w, precision="fp32", digests=True, queue_capacity=1 << 12, mapping=m) for w in ws]
+        batch = karl.Batch(max_jobs=8, queue_capacity=1 << 20)
+        try:
+            batch.transport(jobs, [(0, w.n_primaries) for w in ws])
+            res[m] = ([j.read_tallies() for j in jobs], batch.wave_segments())
+        finally:
+            for j in jobs:
+                j.close()
+            batch.close()
+    assert res["wave"][1] > 0 and res["lane"][1] == 0
+    for gw, gl in zip(res["wave"][0], res["lane"][0]):
+        np.testing.assert_array_equal(gw["digests"], gl["digests"])
+        for k in ["counters", "recomb", "jz", "jr", "spectra"]:
+            np.testing.assert_array_equal(gw[k], gl[k], err_msg=k)

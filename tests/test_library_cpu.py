@@ -39,7 +39,7 @@ def test_workspace_bytes(karl):
     w = W.cfg_full(n_primaries=1000)
     d = karl.Descriptor(w, queue_capacity=1 << 20)
     n = d.workspace_bytes()
-    # four queues of 72-byte entries (two generation buffers, two deferred buffers) dominate
+    # four queues of 76-byte entries (two generation buffers, two deferred buffers) dominate
     assert 4 * (1 << 20) * 72 < n < 4 * (1 << 20) * 72 + 32 * 2**20
     d32 = karl.Descriptor(w, precision=karl.FP32, queue_capacity=1 << 20)
     assert d32.workspace_bytes() < n
@@ -121,6 +121,7 @@ def test_null_job_is_an_error_not_a_crash(karl):
     assert lib.karl_destroy_job(None) == karl.EINVAL
     n = C.c_int64(-1)
     assert lib.karl_job_slices(None, C.byref(n)) == karl.EINVAL and n.value == -1
+    assert lib.karl_batch_wave_segments(None, C.byref(n)) == karl.EINVAL and n.value == -1
 
 
 def test_invalid_angle_tables_are_rejected(karl):
