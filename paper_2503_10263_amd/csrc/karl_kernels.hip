@@ -1865,6 +1865,30 @@ __device__ __forceinline__ void advance(const DevJob& J, const Lds<Real>& L, con
 }
 
 // ---------------------------------------------------------------- deferred launch in slices
+// Issue priority of a wave (0..3; the immediate operand of s_setprio).
+__device__ __forceinline__ void set_wave_prio(uint32_t p) {
+    switch (p) {
+        case 0: __builtin_amdgcn_s_setprio(0); break;
+        case 1: __builtin_amdgcn_s_setprio(1); break;
+        case 2: __builtin_amdgcn_s_setprio(2); break;
+        default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
+
+// Every 64 iterations of a transport loop, the wave takes the issue priority (its slot on the
+// SIMD + the period of 2^18 ticks of the 100 MHz clock) mod 4.  A SIMD issues from its oldest
+// wave first: left alone, the four waves of a SIMD advance at rates of about 1 : 1.5 : 2 : 2.4,
+// so that a particle's progress depends on the waves it happened to run on, and a launch ends
+// with a tail of particles that ran on slow ones.  The waves resident on a SIMD hold distinct
+// slots (HW_ID bits 3:0), so each period gives them distinct priorities, each period another
+// order: over a slice every wave runs at about the mean rate.
+__device__ __forceinline__ void rotate_prio(uint32_t& iter) {
+    if ((++iter & 63u) == 0u) {
+        const uint32_t slot = (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | 4);   // HW_ID[3:0]
+        set_wave_prio(((uint32_t)(__builtin_amdgcn_s_memrealtime() >> 18) + slot) & 3u);
+    }
+}
+
 // The lanes of the deferred launch claim indices of one counter (G.fetch): index u < n_items is
 // item u of the deferred queue, u >= n_items the ring entry u - n_items.  A wave claims only
 // indices below n_items + ring_tail, i.e. items written before the launch or ring entries whose
@@ -2137,7 +2161,9 @@ __global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void tran
         }
         bool wait = false;   // a ring entry is claimed (index in p.lin), not yet readable
         int skip = 0;        // wave-uniform: loop iterations before idle lanes look for work again
+        uint32_t iter = 0;   // loop iterations (issue-priority rotation)
         for (;;) {
+            rotate_prio(iter);
             if (wait) take_ring(G, p, wait);
             const bool need = !p.alive && !p.start && !wait;
             if (__ballot(need)) {
