@@ -352,8 +352,14 @@ struct LaneCnt {
 };
 // The deferred launch's counts: species 0 (which a job defers only when its electrons make no
 // products) with one atomic per event like species 2 and 3, so that the launch keeps registers
-// for species 1 only.
-struct LaneCntLean : LaneCnt {};
+// for species 1 only.  The interactions per process are counted per lane for the lane's last
+// process (flushed when the process changes and at the end of the launch): the deferred species
+// have few processes (the H2+ of the full case one), and a register increment replaces the
+// wave-aggregated LDS atomic of the other kernels.
+struct LaneCntLean : LaneCnt {
+    int32_t proc = -1;
+    uint32_t proc_n = 0;
+};
 template <typename LC>
 constexpr bool kLeanCnt = __is_same(LC, LaneCntLean);
 template <bool kB, typename T, typename F> struct PickT { using type = T; };
@@ -403,6 +409,15 @@ __device__ __forceinline__ void count_n(const Lds<Real>& L, uint32_t& reg, int i
     }
 }
 
+__device__ __forceinline__ void count_proc(unsigned long long* cnt, LaneCntLean& lc, int pi) {
+    if (pi != lc.proc) {
+        if (lc.proc_n) atomicAdd(&cnt[KARL_C_PROC + lc.proc], (unsigned long long)lc.proc_n);
+        lc.proc = pi;
+        lc.proc_n = 0u;
+    }
+    ++lc.proc_n;
+}
+
 __device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt, double* led) {
     const uint32_t v[11] = {lc.step0, lc.step1, lc.coll0, lc.coll1, lc.zc0, lc.zc1, lc.rc0, lc.rc1,
                             lc.redraw, lc.beb, lc.beta};
@@ -414,6 +429,13 @@ __device__ __forceinline__ void flush_lane(LaneCnt& lc, unsigned long long* cnt,
         if (v[k]) atomicAdd(&cnt[idx[k]], (unsigned long long)v[k]);
     if (lc.e_prim != 0.0) atomicAdd(&led[KARL_L_E_PRIMARY], lc.e_prim);
     lc = LaneCnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0.0};
+}
+
+__device__ __forceinline__ void flush_lane(LaneCntLean& lc, unsigned long long* cnt, double* led) {
+    if (lc.proc_n) atomicAdd(&cnt[KARL_C_PROC + lc.proc], (unsigned long long)lc.proc_n);
+    lc.proc = -1;
+    lc.proc_n = 0u;
+    flush_lane(static_cast<LaneCnt&>(lc), cnt, led);
 }
 
 
@@ -1092,7 +1114,8 @@ template <typename Real, typename LC>
 __device__ __forceinline__ void count_interaction(const DevJob& J, const Lds<Real>& L, LC& lc,
                                                   Part<Real>& p, int sp, int pi) {
     count_ev(L, lc, KARL_C_COLL, sp);
-    wave_count(L.cnt, KARL_C_PROC + pi);
+    if constexpr (kLeanCnt<LC>) count_proc(L.cnt, lc, pi);
+    else wave_count(L.cnt, KARL_C_PROC + pi);
     p.n_int += 1;
     ev(p, 2u, (uint32_t)pi, (uint32_t)(p.ir * J.n_z + p.iz), (J.flags & KARL_FLAG_DIGESTS) != 0);
 }
