@@ -2066,9 +2066,13 @@ __device__ __forceinline__ void ring_put(const GenArgs& G, Part<Real>& p, bool w
     }
 }
 
-#ifndef KARL_WAVES_PER_SIMD
-#define KARL_WAVES_PER_SIMD 1
-#endif
+// Waves per SIMD a transport kernel is built for (its register budget is 512 / waves).  The
+// deferred kernels and the FP32 batched kernels are held to four: the FP32 batched kernel then
+// keeps 17 registers' worth (68 bytes) in scratch, and measured 13 % faster than at the three
+// waves its 158 registers allow without.  The others take what their registers give (FP64 plain
+// 3, FP32 plain 4, FP64 batched 2; held to four, the FP64 kernels spill 116-308 bytes).
+template <typename Real, bool kBatched, int kDrain>
+constexpr int kMinWaves = kDrain ? 4 : (kBatched && sizeof(Real) == 4) ? 4 : 1;
 
 // The wave's counter slot of job ju: found among the slot tags, or taken over from the least
 // recent job (whose counts are flushed to its tallies first).  Called by all active lanes of a
@@ -2102,7 +2106,7 @@ __device__ __forceinline__ unsigned long long* job_slot(const DevJob* jobs, unsi
 // the kernel half the registers and twice the waves per SIMD (1: without, 2: with the
 // energy-resolved density tally).
 template <typename Real, bool kBatched, bool kCoop = false, int kDrain = 0, bool kBoris = false>
-__global__ __launch_bounds__(kBlock, kDrain ? 4 : KARL_WAVES_PER_SIMD) void transport_kernel(
+__global__ __launch_bounds__(kBlock, (kMinWaves<Real, kBatched, kDrain>)) void transport_kernel(
     const DevJob* __restrict__ jobs, const GenArgs G) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x;
