@@ -46,3 +46,18 @@ def test_defaults_are_small_and_within_the_job():
     pl = bench.plan(bench.parse([]))
     assert (pl["warmup"] + pl["steps"]) * pl["batch"] <= bench.N_FULL
     assert (pl["slice_steps"] & (pl["slice_steps"] - 1)) == 0   # slices are a power of two
+
+
+def test_profiled_constants_belong_to_these_kernel_sources():
+    """The issue fraction, HBM bytes and batched issue fraction that bench.py reports were
+    measured (rocprofv3, summaries under profiles/) on kernel sources of a stated hash; the bench
+    reports them only while the sources still have that hash, and the committed profiles are
+    those of the committed kernels."""
+    import bench
+    sha = bench.kernels_sha256()
+    for name in ("VALU_ISSUE", "HBM_TRAFFIC", "BATCHED_VALU"):
+        assert getattr(bench, name)["kernels_sha256"] == sha, name
+    for prof in ("transport_kernel_drain_full_case_sq.md", "transport_kernel_full_case_hbm.md",
+                 "transport_kernel_full_case_ktrace.md", "transport_kernel_batched_fp32_batched_case.md"):
+        with open(os.path.join(ROOT, "profiles", prof)) as f:
+            assert sha in f.read(), prof
