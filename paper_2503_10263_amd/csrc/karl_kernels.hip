@@ -93,6 +93,24 @@ __shared__ double s_series[kNSeries];
 #define KC(i) (kSeriesTab[(i)])
 #endif
 
+// a / b, correctly rounded, where both operands are finite, b is nonzero, and the exponents of a
+// (unless it is +0), b, 1/b and a/b all lie well inside the normal range: the compiler's division
+// without its operand scaling and special-case fix-up, which for such operands change nothing --
+// the reciprocal, two Newton steps, the quotient, its residual and the corrected quotient, each
+// one rounding, as in the full sequence.  The callers' operands are bounded by construction.
+__device__ __forceinline__ double kdiv(double a, double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    const double q = a * y;
+    const double r = fma(-b, q, a);
+    return fma(r, y, q);
+}
+// FP32 transport state: the hardware reciprocal (build flag), as any division
+__device__ __forceinline__ float kdiv(float a, float b) { return a / b; }
+
 __device__ __forceinline__ double klog(double x) {
     if (!(x > 0.0)) return (x == 0.0) ? -INFINITY : NAN;
     if (isinf(x)) return x;
@@ -103,7 +121,7 @@ __device__ __forceinline__ double klog(double x) {
         e = e - 1;
     }
     const double f = m - 1.0;
-    const double s = f / (m + 1.0);          // ln m = 2 atanh(s)
+    const double s = kdiv(f, m + 1.0);       // ln m = 2 atanh(s); f in (-0.30, 0.42], m + 1 in [1.7, 2.5)
     const double z = s * s;
     double p = KC(0);                        // coefficients 1/(2n+1), n = 12 .. 1
     p = fma(z, p, KC(1));
@@ -196,9 +214,11 @@ __device__ __forceinline__ float kfmax(float a, float b) { return fmaxf(a, b); }
 template <typename Real> struct Prec;
 template <> struct Prec<double> {
     static constexpr double eps = 1.1102230246251565404e-16;  // 2^-53
-    // 53-bit uniform in [0,1) from two 32-bit words
+    // 53-bit uniform in [0,1) from two 32-bit words: ((a >> 5) 2^26 + (b >> 6)) 2^-53.  Every
+    // step is exact (an integer below 2^53, then a power of two), so the product and sum are
+    // one fused multiply-add with the same result.
     static __device__ __forceinline__ double uni(uint32_t a, uint32_t b, uint32_t) {
-        return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * eps;
+        return fma((double)(a >> 5), 67108864.0, (double)(b >> 6)) * eps;
     }
 };
 template <> struct Prec<float> {
@@ -556,7 +576,7 @@ __device__ __forceinline__ void rotate(Real u, Real v, Real w, Real mu, Real phi
     Real a, b, c;
     if (kfabs(w) < (Real)1 - (Real)1e-10) {
         const Real t = ksqrt((Real)1 - w * w);
-        const Real it = (Real)1 / t;
+        const Real it = kdiv((Real)1, t);   // t >= 1.4e-5
         a = mu * u + s * (u * w * cp - v * sp) * it;
         b = mu * v + s * (v * w * cp + u * sp) * it;
         c = mu * w - s * t * cp;
@@ -565,7 +585,7 @@ __device__ __forceinline__ void rotate(Real u, Real v, Real w, Real mu, Real phi
         b = s * sp;
         c = (w > (Real)0) ? mu : -mu;
     }
-    const Real in = (Real)1 / ksqrt(a * a + b * b + c * c);
+    const Real in = kdiv((Real)1, ksqrt(a * a + b * b + c * c));   // a unit vector's norm
     out[0] = a * in;
     out[1] = b * in;
     out[2] = c * in;
@@ -599,7 +619,7 @@ __device__ __forceinline__ void set_velocity(Part<Real>& p, Real e_from_v2, cons
     p.e = v2 * e_from_v2;
     p.vel = ksqrt(v2);
     if (p.vel > (Real)0) {
-        const Real iv = (Real)1 / p.vel;
+        const Real iv = kdiv((Real)1, p.vel);
         p.u = vv[0] * iv;
         p.v = vv[1] * iv;
         p.w = vv[2] * iv;
@@ -650,7 +670,7 @@ __device__ double k_elastic(const DevJob& J, const Lds<Real>& L, Part<Real>& p, 
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     Real gh[3] = {(Real)0, (Real)0, (Real)1};
     if (gm > (Real)0) {
-        const Real ig = (Real)1 / gm;
+        const Real ig = kdiv((Real)1, gm);
         gh[0] = g[0] * ig;
         gh[1] = g[1] * ig;
         gh[2] = g[2] * ig;
@@ -820,7 +840,7 @@ __device__ void k_ionization(const DevJob& J, const Lds<Real>& L, const GenArgs&
     const Real gm = ksqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     Real gh[3] = {(Real)0, (Real)0, (Real)1};
     if (gm > (Real)0) {
-        const Real ig = (Real)1 / gm;
+        const Real ig = kdiv((Real)1, gm);
         gh[0] = g[0] * ig;
         gh[1] = g[1] * ig;
         gh[2] = g[2] * ig;
@@ -1489,7 +1509,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
     if (dist != dist || sum != sum) atomicOr(J.status, STATUS_NUMERIC);
 
     const Real l = (dist < sg) ? dist : sg;
-    const Real dt = l / p.vel;
+    const Real dt = kdiv(l, p.vel);   // l >= 0 (+0 at most), a speed
     p.t_cell += (double)dt;
     p.t_alive += (double)dt;
     if (kDrain != 1 && J.dense) add_dense(J, sp, p.ir, p.iz, (double)p.e, (double)dt);
@@ -1522,7 +1542,7 @@ __device__ void step(const DevJob& J, const Lds<Real>& L, const GenArgs& G, Part
         if (J.gc) {
             const Real om = (Real)L.sc->omega[sp];
             const Real iom = (Real)L.sc->inv_om[sp];
-            const Real al = -(om * (p.s_path / p.vel));
+            const Real al = -(om * kdiv(p.s_path, p.vel));
             Real sa, ca;
             ksincos(al, &sa, &ca);
             const Real un = ca * p.u - sa * p.v;
