@@ -127,7 +127,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_2503_10263_amd.build "
                                "(hipcc --offload-arch=gfx950); there is no CPU fallback")
         L = C.CDLL(LIB_PATH)
         L.karl_workspace_bytes.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
