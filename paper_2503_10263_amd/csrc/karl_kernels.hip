@@ -2108,12 +2108,14 @@ __device__ __forceinline__ void ring_put(const GenArgs& G, Part<Real>& p, bool w
 }
 
 // Waves per SIMD a transport kernel is built for (its register budget is 512 / waves).  The
-// deferred kernels and the FP32 batched kernels are held to four: the FP32 batched kernel then
-// keeps 17 registers' worth (68 bytes) in scratch, and measured 13 % faster than at the three
-// waves its 158 registers allow without.  The others take what their registers give (FP64 plain
-// 3, FP32 plain 4, FP64 batched 2; held to four, the FP64 kernels spill 116-308 bytes).
+// deferred kernels and the FP32 batched kernels are held to four, the FP64 batched kernels to
+// three: the FP32 batched kernel then keeps 17 registers' worth (68 bytes) in scratch and
+// measured 13 % faster than at the three waves its 158 registers allow without; the FP64
+// batched kernel keeps 148 bytes and measured 17 % faster than at the two waves of its 222
+// registers.  The single-job kernels take what their registers give (FP64 plain 3, FP32 plain
+// 4; held to four, the FP64 plain kernel keeps 132 bytes and measured slower).
 template <typename Real, bool kBatched, int kDrain>
-constexpr int kMinWaves = kDrain ? 4 : (kBatched && sizeof(Real) == 4) ? 4 : 1;
+constexpr int kMinWaves = kDrain ? 4 : kBatched ? (sizeof(Real) == 4 ? 4 : 3) : 1;
 
 // The wave's counter slot of job ju: found among the slot tags, or taken over from the least
 // recent job (whose counts are flushed to its tallies first).  Called by all active lanes of a
