@@ -6,7 +6,6 @@ a temporary directory and runs the program."""
 import os
 import shutil
 import subprocess
-import sys
 import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from paper_2503_10263_amd import workloads as W
-from parity_util import compare_tallies, parity, run_gpu, run_oracle
+from parity_util import compare_tallies, parity, run_oracle
 
 pytestmark = pytest.mark.gpu
 

@@ -6,7 +6,6 @@ Bar for FP32 (the reading of Sec. 2.1's estimator: the same process, rounded mor
 mean energy deposited per primary within 0.1 % of FP64, and the exit spectra equal by a
 two-sample chi-square over bins merged to >= 20 counts at p > 0.01.  The runs share their
 streams, so the batch-paired statistics (the same primaries in each batch) are reported too."""
-import numpy as np
 import pytest
 
 from paper_2503_10263_amd import workloads as W

@@ -16,7 +16,6 @@ import math
 
 import numpy as np
 import pytest
-from scipy import stats
 
 from paper_2503_10263_amd import workloads as W
 
