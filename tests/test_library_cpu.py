@@ -198,3 +198,20 @@ def test_boris_descriptor_rules():
     w = W.boris_column(n_primaries=10)
     w.e_field = np.full_like(w.e_field, np.nan)
     assert rejected(w)
+
+
+def test_device_arith_helper_loads_and_rejects_bad_calls():
+    """The GPU tests' helper of the kernels' elementary arithmetic is built beside the library,
+    exports one entry point per kernel unit, and rejects an unknown operation or a negative
+    count (and does nothing for none) before any device work."""
+    import device_arith as D
+    if not os.path.exists(D.LIB_PATH):
+        D.build()
+    L = D.load()
+    for unit, (name, _) in D.UNITS.items():
+        f = getattr(L, name)
+        assert f(99, 1, None, None, None, None) == -1, unit
+        assert f(D.DIV64, -1, None, None, None, None) == -1, unit
+        assert f(D.DIV64, 0, None, None, None, None) == 0, unit
+    with pytest.raises(AssertionError):
+        D.apply("drain", D.LOG64, np.zeros(4, np.float32))     # FP32 buffer for an FP64 operation
