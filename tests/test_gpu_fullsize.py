@@ -5,7 +5,8 @@ benchmark's step of 131072 primary ids in one karl_transport call, as one chunk,
 launch in slices of 2^15 steps.  The oracle computes
 sampled histories one by one: their event digests and per-history energy ledgers must be
 identical.  Over the whole batch, properties that hold at any size: every particle deleted
-exactly once, one electron and one ion per ionization, the energy budget.
+exactly once, one electron and one ion per ionization, the energy budget.  Again for the
+bench's last timed step at --steps 20 --warmup 5 (primary ids 960000..999999).
 
 Batched case (256 jobs, FP32) at full size in one karl_transport_batch: the same integer
 identities per job, the energy budget per job within the FP32 bound, and sampled jobs equal
@@ -71,6 +72,44 @@ def test_full_case_bench_batch_sampled_histories():
         h_g, h_o = g["hist"][pid], o["hist"][pid]
         np.testing.assert_array_equal(h_g[2:], h_o[2:])               # particles born / deleted
         assert np.all(np.abs(h_g[:2] - h_o[:2]) <= 1e-12 * abs(h_o[0])), f"primary {pid}: ledger"
+
+
+@pytest.mark.timeout(600)
+def test_full_case_last_bench_step_sampled_histories():
+    """The last timed step of bench.py --steps 20 --warmup 5 (primary ids up to 999999, the
+    keys' high bits), one karl_transport call as the bench makes it: sampled histories equal to
+    the oracle's, and the identities over the step."""
+    import bench
+    import oracle
+    from paper_2503_10263_amd import karl
+    pl = bench.plan(bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"]))
+    batch = pl["batch"]
+    lo = (pl["warmup"] + pl["steps"] - 1) * batch
+    hi = lo + batch
+    assert hi <= 1_000_000
+    w = W.cfg_full(n_primaries=1_000_000)
+    print(f"full case: primaries {lo}..{hi - 1} in one call, slices of {pl['slice_steps']} steps", flush=True)
+    job = karl.Job(w, precision="fp64", digests=True, history=True, chunk=batch,
+                   slice_steps=pl["slice_steps"])
+    try:
+        job.transport(lo, hi)
+        g = job.read_tallies()
+    finally:
+        job.close()
+    _identities(g["counters"], g["ledger"], batch, w.processes, 1e-10)
+    assert np.all(g["digests"][:lo] == 0)
+    sampled = [lo, lo + 1, lo + 12345, 999983, hi - 1]
+
+    def one(pid):
+        return oracle.run(w, pid, pid + 1, digests=True, hist=True)
+
+    with ThreadPoolExecutor(max_workers=len(sampled)) as ex:
+        refs = list(ex.map(one, sampled))
+    for pid, o in zip(sampled, refs):
+        assert g["digests"][pid] == o["digests"][pid], f"primary {pid}: event sequence differs"
+        np.testing.assert_array_equal(g["hist"][pid][2:], o["hist"][pid][2:])
+        assert np.all(np.abs(g["hist"][pid][:2] - o["hist"][pid][:2]) <= 1e-12 * abs(o["hist"][pid][0])), \
+            f"primary {pid}: ledger"
 
 
 def test_batched_case_full_size_fp32():
