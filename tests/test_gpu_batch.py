@@ -115,3 +115,32 @@ def test_many_jobs_counters_equal_alone():
             np.testing.assert_array_equal(g[key], alone[key], err_msg=f"job {k}: {key}")
         job.close()
     batch.close()
+
+
+def test_batched_case_last_primaries_of_large_jobs_fp64():
+    """The batched case's own jobs at their own sizes: the last 500 primary ids of its four largest
+    jobs (ids up to 968026) and of its last two jobs (the highest seeds), in one FP64 batched
+    transport, equal to the oracle: every digest, integer tallies exactly, FP64 tallies to 1e-12."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2503_10263_amd import karl
+    ws = W.cfg_batched(n_jobs=256)
+    pick = [int(k) for k in np.argsort([w.n_primaries for w in ws])[::-1][:4]] + [255, 254]
+    sel = [ws[k] for k in pick]
+    ranges = [(w.n_primaries - 500, w.n_primaries) for w in sel]
+    print("batched case: jobs", pick, "ranges", ranges, flush=True)
+    jobs = [karl.Job(w, precision="fp64", digests=True, queue_capacity=1024) for w in sel]
+    batch = karl.Batch(max_jobs=len(sel), queue_capacity=1 << 20)
+    try:
+        batch.transport(jobs, ranges)
+        got = [j.read_tallies() for j in jobs]
+    finally:
+        for j in jobs:
+            j.close()
+        batch.close()
+    with ThreadPoolExecutor(max_workers=len(sel)) as ex:
+        refs = list(ex.map(lambda a: run_oracle(a[0], [a[1]], digests=True), zip(sel, ranges)))
+    for k, (lo, hi), g, o in zip(pick, ranges, got, refs):
+        match = g["digests"][lo:hi] == o["digests"][lo:hi]
+        assert match.all(), f"job {k}: {int((~match).sum())} of {hi - lo} histories differ"
+        assert np.all(g["digests"][:lo] == 0)
+        compare_tallies(g, o, abs(o["ledger"][0]))
