@@ -273,11 +273,11 @@ BATCHED_QUEUE = 1 << 28
 
 
 def cfg_tiny(n_primaries: int = 10_000, seed: int = 1, bz: float = 0.0,
-             column_cm2: float = 1.0e16, n_r: int = 1, n_z: int = 1) -> Workload:
+             column_cm2: float = 1.0e16, n_r: int = 1, n_z: int = 1, n_e: int = 256) -> Workload:
     """Tiny plain FP64 case: 1 m tube of radius 45 mm, uniform H2 with the given column
     density, straight-line transport, elastic + BEB ionization + one 12.6 eV excitation,
-    1 eV exit spectra at both ends; ions counted, not tracked."""
-    n_e = 256
+    1 eV exit spectra at both ends; ions counted, not tracked.  Cross-section tables of n_e
+    log-spaced nodes (256 in the case itself)."""
     length = 1.0
     n = column_cm2 * 1.0e4 / length
     return Workload(
@@ -287,13 +287,13 @@ def cfg_tiny(n_primaries: int = 10_000, seed: int = 1, bz: float = 0.0,
         n_e=n_e, source=SOURCE_BETA, seed=seed, planes=[0, n_z], n_primaries=n_primaries)
 
 
-def cfg_full(n_primaries: int = 1_000_000, seed: int = 1) -> Workload:
+def cfg_full(n_primaries: int = 1_000_000, seed: int = 1, n_e: int = 256) -> Workload:
     """Full plain FP64 case: 10 m cylinder of radius 45 mm, axial profile flat over the
     central 8 m with linear falloff to 5 % at the ends (column 5e17 cm^-2), uniform 2.5 T
     axial field (guiding-centre transport), 8 electron processes including recombination on
     a frozen ion-density field, tracked H2+ with Langevin elastic scattering, 64x512 (r,z)
-    grids and 2048-bin spectra per species at z = 0, 5, 10 m."""
-    n_e = 256
+    grids and 2048-bin spectra per species at z = 0, 5, 10 m.  Cross-section tables of n_e
+    log-spaced nodes (256 in the case itself)."""
     length, n_z, n_r = 10.0, 512, 64
     column = 5.0e17 * 1.0e4
     shape = cell_average([0.0, 1.0, 9.0, 10.0], [0.05, 1.0, 1.0, 0.05], length, n_z)

@@ -83,3 +83,20 @@ def parity(w, lo=0, hi=None, min_match=0.999, **gpu_kw):
         np.testing.assert_array_equal(hg[:, 2:], ho[:, 2:])
         assert_float_close("hist", hg[:, :2], ho[:, :2], scale=1e-3)
     return g, o, frac
+
+
+def assert_identities(c, L, n_primaries, processes, energy_rtol):
+    """Identities of a transport that hold at any size: one electron per primary and per
+    ionization, one ion per ionization, every particle deleted exactly once, and the energy
+    budget (primary energy = energy leaving + excitation + binding + given to the gas) within
+    energy_rtol."""
+    from paper_2503_10263_amd import karl as K
+    from paper_2503_10263_amd import workloads as W
+    nr = K.NREASON
+    n_ion = sum(int(c[K.C_PROC + i]) for i, p in enumerate(processes) if p.kind == W.IONIZATION)
+    assert c[K.C_BIRTH] == n_primaries + n_ion    # electrons: primaries + one per ionization
+    assert c[K.C_BIRTH + 1] == n_ion              # ions: one per ionization
+    deaths = c[K.C_DEATH:K.C_DEATH + 2 * nr].reshape(2, nr)
+    assert deaths[0].sum() == c[K.C_BIRTH] and deaths[1].sum() == c[K.C_BIRTH + 1]   # each deleted once
+    out = L[K.L_E_DEATH:K.L_E_DEATH + 2 * nr].sum() + L[K.L_E_EXC] + L[K.L_E_BIND] + L[K.L_E_GAS]
+    assert abs(out / L[K.L_E_PRIMARY] - 1.0) < energy_rtol

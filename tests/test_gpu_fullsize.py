@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from paper_2503_10263_amd import workloads as W
+from parity_util import assert_identities as _identities
 
 pytestmark = pytest.mark.gpu
 
@@ -31,18 +32,6 @@ def _gpu():
         pytest.skip("no HIP device")
     import oracle
     oracle.build(force=False)
-
-
-def _identities(c, L, n_primaries, processes, energy_rtol):
-    from paper_2503_10263_amd import karl as K
-    nr = K.NREASON
-    n_ion = sum(int(c[K.C_PROC + i]) for i, p in enumerate(processes) if p.kind == W.IONIZATION)
-    assert c[K.C_BIRTH] == n_primaries + n_ion    # electrons: primaries + one per ionization
-    assert c[K.C_BIRTH + 1] == n_ion              # ions: one per ionization
-    deaths = c[K.C_DEATH:K.C_DEATH + 2 * nr].reshape(2, nr)
-    assert deaths[0].sum() == c[K.C_BIRTH] and deaths[1].sum() == c[K.C_BIRTH + 1]   # each deleted once
-    out = L[K.L_E_DEATH:K.L_E_DEATH + 2 * nr].sum() + L[K.L_E_EXC] + L[K.L_E_BIND] + L[K.L_E_GAS]
-    assert abs(out / L[K.L_E_PRIMARY] - 1.0) < energy_rtol
 
 
 @pytest.mark.timeout(600)

@@ -79,6 +79,7 @@ def _create(karl, desc):
     (lambda d: setattr(d.d, "n_r", 0), -1),
     (lambda d: setattr(d.d, "radius", -1.0), -1),
     (lambda d: setattr(d.d, "n_e", 1), -1),
+    (lambda d: setattr(d.d, "n_e", 1025), -1),
     (lambda d: setattr(d.d.proc[0], "kind", 9), -1),
     (lambda d: setattr(d.d, "precision", 7), -1),
     (lambda d: setattr(d.d, "n_primaries", -5), -1),
