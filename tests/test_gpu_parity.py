@@ -88,6 +88,48 @@ def test_empty_range_leaves_tallies_zero():
         assert not np.any(v), k
 
 
+def _vacuum_straight():
+    return W.cfg_tiny(n_primaries=3000, column_cm2=0.0)
+
+
+def _vacuum_guiding_centre():
+    w = W.cfg_tiny(n_primaries=3000, column_cm2=0.0, bz=2.5, n_r=4, n_z=16)
+    w.planes = [0, 8, 16]
+    return w
+
+
+def _cap_one():
+    w = W.cfg_tiny(n_primaries=3000, column_cm2=1e18)
+    w.species[W.ELECTRON].cap = 1
+    return w
+
+
+def _cut_above_endpoint():
+    w = W.cfg_tiny(n_primaries=3000, column_cm2=1e17)
+    w.species[W.ELECTRON].e_cut = 2.0e4
+    return w
+
+
+@pytest.mark.parametrize("make", [_vacuum_straight, _vacuum_guiding_centre, _cap_one, _cut_above_endpoint],
+                         ids=["vacuum-straight", "vacuum-guiding-centre", "cap-one", "cut-above-endpoint"])
+def test_degenerate_cases(make):
+    """Degenerate cases of the method: no gas (every flight ends at a face, no interaction), an
+    interaction cap of one (each electron deleted at its first interaction, after its products
+    are made), a cutoff above the beta endpoint (every primary deleted at birth)."""
+    w = make()
+    g, o, frac = parity(w)
+    assert frac == 1.0
+    c = o["counters"]
+    deaths = c[oracle.C_DEATH:oracle.C_DEATH + oracle.NREASON]
+    if make in (_vacuum_straight, _vacuum_guiding_centre):
+        assert c[oracle.C_COLL:oracle.C_COLL + 4].sum() == 0
+        assert deaths[W.REASONS.index("exit_low")] + deaths[W.REASONS.index("exit_high")] > 0
+    elif make is _cap_one:
+        assert deaths[W.REASONS.index("cap")] == c[oracle.C_COLL] > 0
+    else:
+        assert deaths[W.REASONS.index("cutoff")] == w.n_primaries == c[oracle.C_BIRTH]
+
+
 def test_chunking_and_queue_overflow_do_not_change_results():
     """A queue of 64 entries forces overflow retries and small chunks; results must equal
     the default launch and the oracle exactly (identity-keyed random numbers)."""
