@@ -59,6 +59,6 @@ def test_profiled_constants_belong_to_these_kernel_sources():
         assert getattr(bench, name)["kernels_sha256"] == sha, name
     for prof in ("transport_kernel_drain_full_case_sq.md", "transport_kernel_full_case_hbm.md",
                  "transport_kernel_full_case_ktrace.md", "transport_kernel_batched_fp32_batched_case.md",
-                 "transport_kernel_l2_full_and_batched_case.md"):
+                 "transport_kernel_l2_full_and_batched_case.md", "transport_kernel_driver_bench_ktrace.md"):
         with open(os.path.join(ROOT, "profiles", prof)) as f:
             assert sha in f.read(), prof
