@@ -301,6 +301,36 @@ karl_status validate(const karl_job_desc* d, bool need_workspace) {
         return fail(KARL_EINVAL, "slice_ring must be in 0..2^40");
     if (d->mapping != KARL_MAP_AUTO && d->mapping != KARL_MAP_LANE && d->mapping != KARL_MAP_WAVE)
         return fail(KARL_EINVAL, "mapping must be KARL_MAP_AUTO, KARL_MAP_LANE or KARL_MAP_WAVE");
+    if (d->precision == KARL_FP32) {
+        // FP32 state: the tables and the geometry that the kernels read in single precision must
+        // stay finite there (gas densities also summed over the cells, for the birth CDF)
+        const double fmax = 3.4028234663852886e38;
+        if (d->radius > fmax || d->length > fmax)
+            return fail(KARL_EINVAL, "radius and length must be below the FP32 range limit");
+        double cum = 0.0;
+        for (int k = 0; k < d->n_z; ++k) {
+            cum += d->n_gas[k];
+            if (!(cum <= fmax))
+                return fail(KARL_EINVAL, "n_gas (summed over the cells) must stay below the FP32 range limit");
+        }
+        for (int i = 0; i < d->n_proc; ++i) {
+            const double sc = d->proc[i].density_power == 2 ? std::ldexp(1.0, 100) : 1.0;
+            for (int k = 0; k < d->n_e; ++k)
+                if (!(d->proc[i].xs[k] * sc <= fmax))
+                    return fail(KARL_EINVAL, "process %d: cross section %d beyond the FP32 range limit", i, k);
+        }
+    }
+    {
+        // the tables and grid faces are staged in LDS: only their sizes matter here
+        karl::DevJob sizes{};
+        sizes.n_proc = d->n_proc;
+        sizes.n_e = d->n_e;
+        sizes.n_z = d->n_z;
+        sizes.n_r = d->n_r;
+        const size_t lds = karl::lds_bytes(sizes, d->precision);
+        if (lds > kMaxLds)
+            return fail(KARL_EINVAL, "tables need %zu bytes of LDS per workgroup (max %zu)", lds, kMaxLds);
+    }
     if (need_workspace) {
         const Layout L = make_layout(d);
         if (!d->workspace) return fail(KARL_EINVAL, "workspace is NULL");
@@ -1045,10 +1075,7 @@ karl_status karl_create_job(const karl_job_desc* d, void** out) {
     j->status = (unsigned int*)(ctl + 5);     // the job's own sticky status (NaN met)
     J.status = j->status;
 
-    const size_t lds = karl::lds_bytes(J, d->precision);
-    if (lds > kMaxLds)
-        return cleanup(fail(KARL_EINVAL, "tables need %zu bytes of LDS per workgroup (max %zu)",
-                            lds, kMaxLds));
+    const size_t lds = karl::lds_bytes(J, d->precision);   // at most kMaxLds (validated)
     TRY_HIP(hipMemcpy(w + L.devjob, &J, sizeof(J), hipMemcpyHostToDevice));
     j->lds = lds;
     j->run.ctl = ctl;

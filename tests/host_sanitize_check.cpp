@@ -137,6 +137,15 @@ int main() {
         d.proc[0].ang_pdf = pdf;
     });
     rejected("Boris mover without time steps", [](karl_job_desc& d) { d.mover = KARL_MOVER_BORIS; });
+    rejected("grid faces beyond the LDS of a workgroup", [](karl_job_desc& d) {
+        static std::vector<double> n(8192, 1e20);
+        d.n_z = 8192;
+        d.n_gas = n.data();
+    });
+    rejected("FP32 cross section beyond the FP32 range", [](karl_job_desc& d) {
+        d.precision = KARL_FP32;
+        const_cast<double*>(d.proc[0].xs)[3] = 1e39;
+    });
     {
         uint64_t bytes = 0;
         expect(karl_workspace_bytes(nullptr, &bytes) == KARL_EINVAL && has_message(), "null descriptor");

@@ -5,7 +5,7 @@ device allows more), and a table has at most 1024 nodes.
 * FP64 full case (nine processes, 64x512 grid, tracked H2+ in the deferred launch, whose kernel
   adds its own LDS copy of the series constants) with tables at the largest node count that
   fits the LDS limit: parity with the oracle.  One node more is rejected with KARL_EINVAL, the
-  message naming the bytes it needs, before the job is usable; the jobs made after it run.
+  message naming the bytes it needs, before any device work; the jobs made after it run.
 * FP32 full case at the node limit of 1024 (its tables take half the bytes): the identities of
   a transport."""
 import re

@@ -216,3 +216,31 @@ def test_device_arith_helper_loads_and_rejects_bad_calls():
         assert f(D.DIV64, 0, None, None, None, None) == 0, unit
     with pytest.raises(AssertionError):
         D.apply("drain", D.LOG64, np.zeros(4, np.float32))     # FP32 buffer for an FP64 operation
+
+
+def test_tables_beyond_lds_and_fp32_range_are_rejected_before_device_work(karl):
+    """Sizing already rejects a job whose tables and grid faces overflow the 64 KiB of LDS a
+    workgroup stages them in, and an FP32 job whose tables or geometry leave the FP32 range (its
+    kernels would read infinities); the same values in FP64 are accepted."""
+    import re as _re
+
+    def code_and_message(w, precision):
+        try:
+            prec = {"fp64": karl.FP64, "fp32": karl.FP32}[precision]
+            karl.Descriptor(w, precision=prec, queue_capacity=1024).workspace_bytes()
+        except karl.KarlError as e:
+            return e.code, str(e)
+        return karl.OK, ""
+
+    code, msg = code_and_message(W.cfg_full(n_primaries=10, n_e=1024), "fp64")
+    assert code == karl.EINVAL and _re.search(r"tables need \d+ bytes of LDS", msg), msg
+    assert code_and_message(W.cfg_full(n_primaries=10, n_e=1024), "fp32")[0] == karl.OK   # half the bytes
+    assert code_and_message(W.cfg_full(n_primaries=10, n_e=512), "fp64")[0] == karl.OK
+    dense = W.cfg_tiny(n_primaries=10, n_z=4)
+    dense.n_gas = np.full(4, 1e38)                   # the birth CDF sums to 4e38
+    assert code_and_message(dense, "fp32")[0] == karl.EINVAL
+    assert code_and_message(dense, "fp64")[0] == karl.OK
+    big = W.cfg_tiny(n_primaries=10)
+    big.processes[0].xs = big.processes[0].xs * 1e60
+    assert code_and_message(big, "fp32")[0] == karl.EINVAL
+    assert code_and_message(big, "fp64")[0] == karl.OK
