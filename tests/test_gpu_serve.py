@@ -157,3 +157,40 @@ def test_realtime_replay_reports_latency():
     assert res["collisions"].sum() > 0
     assert srv.stats()["completed"] == 16
     srv.close()
+
+
+@pytest.mark.timeout(400)
+def test_served_fp64_requests_at_their_drawn_sizes():
+    """Five requests of the serving case at the sizes it draws (1.2e4-6.9e4 primaries, grids
+    32x256-64x512, columns 1e16-4e17 cm^-2, B 1.1-2.9 T) through an FP64 server with the
+    bench's round length: every history's event digest equal to the oracle's on sampled primary
+    ids, and each job's identities (one electron per primary and per ionization, one ion per
+    ionization, each particle deleted once, the energy budget)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from paper_2503_10263_amd import karl
+    from parity_util import assert_identities
+    reqs = W.serving_requests(n=13)
+    pick = [1, 2, 6, 9, 12]
+    ws = [reqs[k][1] for k in pick]
+    print("serving requests", pick, [w.n_primaries for w in ws], flush=True)
+    srv = karl.Server(max_jobs=8, arena_bytes=4 << 30, precision="fp64", queue_capacity=1 << 22,
+                      round_ms=200.0)
+    tickets = [srv.submit(w, digests=True) for w in ws]
+    got = {}
+    while len(got) < len(tickets):
+        srv.step()
+        for t in srv.poll():
+            got[t] = srv.read_tallies(t, digests=True)
+            srv.release(t)
+    srv.close()
+    rng = np.random.default_rng(5)
+    tasks = []
+    for t, w in zip(tickets, ws):
+        assert_identities(got[t]["counters"], got[t]["ledger"], w.n_primaries, w.processes, 1e-10)
+        for pid in [0, w.n_primaries - 1] + [int(p) for p in rng.integers(1, w.n_primaries - 1, 4)]:
+            tasks.append((t, w, pid))
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(lambda a: oracle.run(a[1], a[2], a[2] + 1, digests=True)["digests"][a[2]], tasks))
+    for (t, w, pid), d in zip(tasks, refs):
+        assert got[t]["digests"][pid] == d, f"{w.name} primary {pid}: event sequence differs"
