@@ -194,3 +194,20 @@ def test_served_fp64_requests_at_their_drawn_sizes():
         refs = list(ex.map(lambda a: oracle.run(a[1], a[2], a[2] + 1, digests=True)["digests"][a[2]], tasks))
     for (t, w, pid), d in zip(tasks, refs):
         assert got[t]["digests"][pid] == d, f"{w.name} primary {pid}: event sequence differs"
+
+
+@pytest.mark.timeout(400)
+def test_served_fp32_requests_at_their_drawn_sizes_equal_alone():
+    """The same five serving-case requests at their drawn sizes in FP32 through the server
+    configured as the bench runs it (four worker threads, 200 ms rounds): each job's integer
+    tallies equal to its tallies transported alone, its FP64 sums up to their order."""
+    from paper_2503_10263_amd import karl, serve
+    reqs = W.serving_requests(n=13)
+    sel = [reqs[k] for k in [1, 2, 6, 9, 12]]
+    srv = karl.Server(max_jobs=8, arena_bytes=4 << 30, precision="fp32", queue_capacity=1 << 22,
+                      round_ms=200.0, n_workers=4)
+    res = serve.replay(srv, sel, realtime=False, keep_tallies=True, threaded=True)
+    assert srv.stats()["completed"] == len(sel)
+    srv.close()
+    for (_, w), got in zip(sel, res["tallies"]):
+        _same_up_to_order(got, _alone(w, "fp32"))
