@@ -3,7 +3,7 @@
  * AddressSanitizer and UndefinedBehaviorSanitizer as a program of its own (a sanitized shared
  * library loaded into Python would need its runtime preloaded).
  *
- *   oracle_sanitize_driver <descriptor file> <result file>
+ *   oracle_sanitize_runner <descriptor file> <result file>
  *
  * Descriptor file (written by tests/test_oracle_sanitizers.py, host byte order):
  *   int64 sizeof(ko_desc); the bytes of a ko_desc whose pointers are rewritten here; then one

@@ -1,5 +1,5 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a message before any
-device work; the driver's invocation (--gpus 1 --steps 20 --warmup 5) plans a run that fits the
+device work; the standard invocation (--gpus 1 --steps 20 --warmup 5) plans a run that fits the
 full case's 1e6 primaries and the time limit, also checked before any device work."""
 import os
 import subprocess
@@ -8,7 +8,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-DRIVER_ARGS = ["--gpus", "1", "--steps", "20", "--warmup", "5"]
+STANDARD_ARGS = ["--gpus", "1", "--steps", "20", "--warmup", "5"]
 
 
 def test_more_than_one_gpu_is_refused():
@@ -18,18 +18,18 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_driver_invocation_fits_the_job_and_the_time_limit():
+def test_standard_invocation_fits_the_job_and_the_time_limit():
     import bench
     from paper_2503_10263_amd import workloads as W
-    pl = bench.plan(bench.parse(DRIVER_ARGS))
+    pl = bench.plan(bench.parse(STANDARD_ARGS))
     assert (5 + 20) * pl["batch"] <= bench.N_FULL
     assert pl["batch"] == 40000                      # 1e6 // 25
     assert pl["slice_steps"] == W.FULL_SLICE_STEPS and pl["batched_queue"] == W.BATCHED_QUEUE
     assert pl["estimated_total_s"] <= bench.TIME_LIMIT_S - bench.MARGIN_S, pl["estimated_s"]
 
 
-def test_driver_invocation_plan_without_device_work():
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *DRIVER_ARGS, "--plan"],
+def test_standard_invocation_plan_without_device_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *STANDARD_ARGS, "--plan"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert '"batch": 40000' in r.stderr and r.stdout == ""
@@ -59,6 +59,6 @@ def test_profiled_constants_belong_to_these_kernel_sources():
         assert getattr(bench, name)["kernels_sha256"] == sha, name
     for prof in ("transport_kernel_drain_full_case_sq.md", "transport_kernel_full_case_hbm.md",
                  "transport_kernel_full_case_ktrace.md", "transport_kernel_batched_fp32_batched_case.md",
-                 "transport_kernel_l2_full_and_batched_case.md", "transport_kernel_driver_bench_ktrace.md"):
+                 "transport_kernel_l2_full_and_batched_case.md", "all_kernels_bench_steps20_warmup5_ktrace.md"):
         with open(os.path.join(ROOT, "profiles", prof)) as f:
             assert sha in f.read(), prof

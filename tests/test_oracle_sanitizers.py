@@ -1,5 +1,5 @@
 """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (with leak checking): its C
-source and a small driver (oracle_sanitize_driver.c) built as one sanitized program, run on the
+source and a small runner (oracle_sanitize_runner.c) built as one sanitized program, run on the
 workloads of every feature -- straight lines and guiding centres, the full case with tracked
 ions and energy-resolved densities, angle tables, density fields, ion chemistry, the Boris
 mover -- with any report failing the run; and its tallies equal to the parity build's, bit for
@@ -17,17 +17,17 @@ from paper_2503_10263_amd import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-DRIVER_SRC = os.path.join(HERE, "oracle_sanitize_driver.c")
+RUNNER_SRC = os.path.join(HERE, "oracle_sanitize_runner.c")
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def runner(tmp_path_factory):
     if shutil.which("gcc") is None:
         pytest.skip("no gcc")
     out = str(tmp_path_factory.mktemp("oracle_san") / "oracle_san")
     cmd = ["gcc", "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-           "-I", os.path.join(ROOT, "oracle"), "-o", out, DRIVER_SRC,
+           "-I", os.path.join(ROOT, "oracle"), "-o", out, RUNNER_SRC,
            os.path.join(ROOT, "oracle", "karl_oracle.c"), "-lm"]
     subprocess.run(cmd, check=True)
     return out
@@ -40,7 +40,7 @@ def _arr(ptr, n, dtype=np.float64):
 
 
 def write_descriptor(path, w, lo, hi, digests=True, hist=True):
-    """The descriptor file that oracle_sanitize_driver.c reads (see its header)."""
+    """The descriptor file that oracle_sanitize_runner.c reads (see its header)."""
     D = oracle.Desc(w)
     d = D.d
     ns = d.n_species or 2
@@ -72,7 +72,7 @@ def write_descriptor(path, w, lo, hi, digests=True, hist=True):
 
 
 def read_result(path, ref):
-    """The driver's tallies, in the layout of the parity build's (ref)."""
+    """The runner's tallies, in the layout of the parity build's (ref)."""
     raw = open(path, "rb").read()
     out, off = {}, 0
     for k in ("counters", "ledger", "density_time", "recomb", "jz", "jr", "spectra", "digests",
@@ -112,14 +112,14 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_oracle_clean_under_sanitizers(driver, tmp_path, name):
+def test_oracle_clean_under_sanitizers(runner, tmp_path, name):
     w = CASES[name]()
     lo, hi = 0, w.n_primaries
     desc, res = str(tmp_path / "desc.bin"), str(tmp_path / "res.bin")
     write_descriptor(desc, w, lo, hi)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    p = subprocess.run([driver, desc, res], env=env, capture_output=True, text=True, timeout=600)
+    p = subprocess.run([runner, desc, res], env=env, capture_output=True, text=True, timeout=600)
     assert p.returncode == 0, f"{name}: exit {p.returncode}\n{p.stderr[-4000:]}"
     assert "runtime error" not in p.stderr and "Sanitizer" not in p.stderr, p.stderr[-4000:]
     ref = oracle.run(w, lo, hi, digests=True, hist=True)
